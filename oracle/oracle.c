@@ -1,0 +1,487 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the batched partitioned
+ * tridiagonal solves (PDD and PPT) of Ha, Park & You, "A scalable multi-GPU
+ * method for semi-implicit fractional-step integration of incompressible
+ * Navier-Stokes equations" (arXiv:1812.01178).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the tests, the smoke check and the benchmark's CPU
+ * baseline load it.  It shares no code, header or table with the HIP path.
+ *
+ * Written for readability, not speed: every partition block is copied out,
+ * every spike is a separate Thomas solve, the reduced system is assembled as
+ * a dense matrix and solved by dense Gaussian elimination with partial
+ * pivoting.  Built with -O2 -ffp-contract=off (no fused multiply-add).
+ *
+ * Notation (0-based in code): a line has n rows
+ *     a[j] x[j-1] + b[j] x[j] + c[j] x[j+1] = d[j],   j = 0..n-1,
+ * split into P partitions of m = n/P rows; partition r owns rows
+ * r*m .. r*m+m-1.  For a non-periodic line a[0] and c[n-1] are not part of
+ * the matrix and are never read.  For a periodic line a[0] couples row 0 to
+ * row n-1 and c[n-1] couples row n-1 to row 0.
+ *
+ * Interfaces i = 1..P-1 (and i = P, joining partition P-1 to partition 0,
+ * when periodic) sit between partition L(i) = i-1 and R(i) = i mod P.  The
+ * paper's reduced unknowns y_{2i-1}, y_{2i} (1-based) are stored at 0-based
+ * positions 2i-2 and 2i-1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum {
+    ORC_OK = 0,
+    ORC_E_ARG = 1,
+    ORC_E_SHAPE = 2,
+    ORC_E_ZERO_PIVOT = 3,
+    ORC_E_NOMEM = 7
+};
+
+enum { ORC_EXACT = 0, ORC_PDD = 1, ORC_PPT = 2 };
+
+/* ------------------------------------------------------------------------ */
+/* Thomas algorithm (textbook, no pivoting).                                 */
+/*   c'_0 = c_0/b_0,  d'_0 = d_0/b_0                                         */
+/*   c'_j = c_j/(b_j - a_j c'_{j-1}),  d'_j = (d_j - a_j d'_{j-1})/(same)    */
+/*   x_{n-1} = d'_{n-1},  x_j = d'_j - c'_j x_{j+1}                          */
+/* a[0] and c[n-1] are not read.  cp is caller scratch of length n.          */
+/* ------------------------------------------------------------------------ */
+int orc_thomas(int64_t n, const double *a, const double *b, const double *c,
+               const double *d, double *x, double *cp)
+{
+    if (n < 1) return ORC_E_SHAPE;
+    double den = b[0];
+    if (den == 0.0) return ORC_E_ZERO_PIVOT;
+    cp[0] = (n > 1 ? c[0] : 0.0) / den;
+    x[0] = d[0] / den;
+    for (int64_t j = 1; j < n; ++j) {
+        den = b[j] - a[j] * cp[j - 1];
+        if (den == 0.0) return ORC_E_ZERO_PIVOT;
+        cp[j] = (j < n - 1 ? c[j] : 0.0) / den;
+        x[j] = (d[j] - a[j] * x[j - 1]) / den;
+    }
+    for (int64_t j = n - 2; j >= 0; --j)
+        x[j] = x[j] - cp[j] * x[j + 1];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Periodic (cyclic) tridiagonal system, textbook Sherman-Morrison rank-one  */
+/* correction of the Thomas algorithm.  This is the plain exact solution of  */
+/* a periodic line and is deliberately a different route from the paper's   */
+/* partitioned algebra, so it can pin the periodic PDD/PPT code.             */
+/*   A = B + u v^T,  u = (g, 0..0, c_{n-1}),  v = (1, 0..0, a_0/g),         */
+/*   B = A with b_0 -= g, b_{n-1} -= a_0 c_{n-1}/g and corners removed,     */
+/*   x = p - (v.p)/(1 + v.q) q  with  B p = d, B q = u.                     */
+/* work: 5n doubles.                                                         */
+/* ------------------------------------------------------------------------ */
+int orc_cyclic(int64_t n, const double *a, const double *b, const double *c,
+               const double *d, double *x, double *work)
+{
+    if (n < 3) return ORC_E_SHAPE;
+    double *bb = work, *u = work + n, *q = work + 2 * n, *cp = work + 3 * n;
+    const double alpha = c[n - 1];   /* couples row n-1 to x_0 */
+    const double beta = a[0];        /* couples row 0 to x_{n-1} */
+    const double g = -b[0];
+    for (int64_t j = 0; j < n; ++j) { bb[j] = b[j]; u[j] = 0.0; }
+    bb[0] = b[0] - g;
+    bb[n - 1] = b[n - 1] - alpha * beta / g;
+    u[0] = g;
+    u[n - 1] = alpha;
+    int st = orc_thomas(n, a, bb, c, d, x, cp);
+    if (st) return st;
+    st = orc_thomas(n, a, bb, c, u, q, cp);
+    if (st) return st;
+    const double vx = x[0] + beta / g * x[n - 1];
+    const double vq = q[0] + beta / g * q[n - 1];
+    const double den = 1.0 + vq;
+    if (den == 0.0) return ORC_E_ZERO_PIVOT;
+    const double f = vx / den;
+    for (int64_t j = 0; j < n; ++j) x[j] = x[j] - f * q[j];
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense Gaussian elimination with partial pivoting, K x K row-major M       */
+/* (destroyed), rhs overwritten by the solution.                             */
+/* ------------------------------------------------------------------------ */
+static int gepp_solve(int K, double *M, double *rhs)
+{
+    for (int k = 0; k < K; ++k) {
+        int p = k;
+        double best = fabs(M[k * K + k]);
+        for (int i = k + 1; i < K; ++i)
+            if (fabs(M[i * K + k]) > best) { best = fabs(M[i * K + k]); p = i; }
+        if (best == 0.0) return ORC_E_ZERO_PIVOT;
+        if (p != k) {
+            for (int t = 0; t < K; ++t) {
+                double s = M[k * K + t]; M[k * K + t] = M[p * K + t]; M[p * K + t] = s;
+            }
+            double s = rhs[k]; rhs[k] = rhs[p]; rhs[p] = s;
+        }
+        for (int i = k + 1; i < K; ++i) {
+            double l = M[i * K + k] / M[k * K + k];
+            if (l == 0.0) continue;
+            for (int t = k; t < K; ++t) M[i * K + t] -= l * M[k * K + t];
+            rhs[i] -= l * rhs[k];
+        }
+    }
+    for (int k = K - 1; k >= 0; --k) {
+        double s = rhs[k];
+        for (int t = k + 1; t < K; ++t) s -= M[k * K + t] * rhs[t];
+        rhs[k] = s / M[k * K + k];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Local quantities of one line (Sec. 3.2, Eqs. (5) and (6)).                */
+/*   xt[r*m + t]  = x~ : the block solve  A~ x~ = d                          */
+/*   v [r*m + t]  = A~_r^{-1} (a_{rm} e_0)        (a-corner spike)           */
+/*   w [r*m + t]  = A~_r^{-1} (c_{rm+m-1} e_{m-1})  (c-corner spike)         */
+/* A~ = A - Delta A: each partition block with the coupling to its           */
+/* neighbours removed (its first a and last c set to zero).  A spike that    */
+/* has no corner (v of partition 0, w of partition P-1, non-periodic) is 0.  */
+/* scratch: 6m doubles.                                                      */
+/* ------------------------------------------------------------------------ */
+static int local_solves(int64_t n, int P, int periodic, const double *a,
+                        const double *b, const double *c, const double *d,
+                        double *xt, double *v, double *w, double *scratch)
+{
+    const int64_t m = n / P;
+    double *at = scratch, *bt = scratch + m, *ct = scratch + 2 * m;
+    double *e = scratch + 3 * m, *cp = scratch + 4 * m;
+    for (int r = 0; r < P; ++r) {
+        const int64_t o = (int64_t)r * m;
+        for (int64_t t = 0; t < m; ++t) { at[t] = a[o + t]; bt[t] = b[o + t]; ct[t] = c[o + t]; }
+        at[0] = 0.0;          /* Delta A: remove the a-corner of the block */
+        ct[m - 1] = 0.0;      /* Delta A: remove the c-corner of the block */
+        int st = orc_thomas(m, at, bt, ct, d + o, xt + o, cp);            /* Eq. (5) */
+        if (st) return st;
+        for (int64_t t = 0; t < m; ++t) e[t] = 0.0;
+        if (r >= 1 || periodic) e[0] = a[o];                              /* column of V */
+        st = orc_thomas(m, at, bt, ct, e, v + o, cp);                     /* Eq. (6) */
+        if (st) return st;
+        for (int64_t t = 0; t < m; ++t) e[t] = 0.0;
+        if (r <= P - 2 || periodic) e[m - 1] = c[o + m - 1];              /* column of V */
+        st = orc_thomas(m, at, bt, ct, e, w + o, cp);                     /* Eq. (6) */
+        if (st) return st;
+    }
+    return ORC_OK;
+}
+
+/* Number of interfaces and reduced-system size. */
+static int n_interfaces(int P, int periodic) { return periodic ? P : P - 1; }
+
+/* ------------------------------------------------------------------------ */
+/* Assemble Z = I + E^T A~^{-1} V (Eq. (7)) and E^T x~ for one line.         */
+/* Row 2i-1 (1-based) selects x at the last row of L(i); row 2i the first    */
+/* row of R(i).  The Y = A~^{-1} V column of unknown 2i-1 is the v spike of  */
+/* R(i); the column of unknown 2i is the w spike of L(i).                    */
+/* Z is K x K row-major, K = 2 * n_interfaces.                               */
+/* ------------------------------------------------------------------------ */
+static void assemble_Z(int64_t m, int P, int periodic, const double *xt,
+                       const double *v, const double *w, double *Z, double *rhs)
+{
+    const int NI = n_interfaces(P, periodic), K = 2 * NI;
+    for (int t = 0; t < K * K; ++t) Z[t] = 0.0;
+    for (int i = 1; i <= NI; ++i) {
+        const int L = i - 1, R = i % P;
+        const int u1 = 2 * i - 2, u2 = 2 * i - 1;      /* y_{2i-1}, y_{2i} */
+        const int64_t lastL = (int64_t)L * m + m - 1, firstR = (int64_t)R * m;
+        /* row 2i-1: x at the last row of L */
+        Z[u1 * K + u1] += 1.0;
+        Z[u1 * K + u2] += w[lastL];                    /* w^(L)_m  */
+        if (L >= 1 || periodic) {                      /* v^(L)_m, column of L's left interface */
+            const int il = (L >= 1) ? L : P;
+            Z[u1 * K + (2 * il - 2)] += v[lastL];
+        }
+        /* row 2i: x at the first row of R */
+        Z[u2 * K + u2] += 1.0;
+        Z[u2 * K + u1] += v[firstR];                   /* v^(R)_1  */
+        if (R <= P - 2 || periodic) {                  /* w^(R)_1, column of R's right interface */
+            const int ir = R + 1;
+            Z[u2 * K + (2 * ir - 1)] += w[firstR];
+        }
+        rhs[u1] = xt[lastL];                           /* E^T x~ */
+        rhs[u2] = xt[firstR];
+    }
+}
+
+/* x = x~ - Y y  (Eq. (8)); partition r uses y_{2r-1} with v^(r) and
+ * y_{2r+2} with w^(r) (y_{-1} = y_{2P} = 0 when non-periodic; when periodic
+ * partition 0's left interface is the wrap interface P). */
+static void correct(int64_t m, int P, int periodic, const double *xt,
+                    const double *v, const double *w, const double *y, double *x)
+{
+    for (int r = 0; r < P; ++r) {
+        double yl = 0.0, yr = 0.0;
+        if (r >= 1 || periodic) {
+            const int il = (r >= 1) ? r : P;
+            yl = y[2 * il - 2];
+        }
+        if (r <= P - 2 || periodic) {
+            const int ir = r + 1;
+            yr = y[2 * ir - 1];
+        }
+        const int64_t o = (int64_t)r * m;
+        for (int64_t t = 0; t < m; ++t)
+            x[o + t] = xt[o + t] - v[o + t] * yl - w[o + t] * yr;
+    }
+}
+
+static int check_shape(int64_t n, int P, int periodic)
+{
+    if (n < 1 || P < 1) return ORC_E_SHAPE;
+    if (n % P != 0) return ORC_E_SHAPE;
+    if (n / P < 2 && !(P == 1 && !periodic)) return ORC_E_SHAPE;
+    if (periodic && n < 3) return ORC_E_SHAPE;
+    return ORC_OK;
+}
+
+/* Work array sizes (doubles) for one line. */
+int64_t orc_line_work(int64_t n, int P)
+{
+    const int K = 2 * P;
+    return 6 * n + 6 * (n / (P > 0 ? P : 1)) + 3 * (int64_t)K * K + 4 * K + 16;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PDD (Sec. 3.2, PDD paragraph; Algorithm 1 steps 3-7): Z keeps only its    */
+/* 2x2 diagonal blocks [[1, w^(L)_m], [v^(R)_1, 1]] per interface (the       */
+/* entries v^(L)_m and w^(R)_1 are dropped), each solved with the inverse of */
+/* a 2x2 matrix; then x = x~ - Y y.                                          */
+/* ------------------------------------------------------------------------ */
+int orc_pdd(int64_t n, int P, int periodic, const double *a, const double *b,
+            const double *c, const double *d, double *x, double *work)
+{
+    int st = check_shape(n, P, periodic);
+    if (st) return st;
+    const int64_t m = n / P;
+    if (P == 1 && !periodic) return orc_thomas(n, a, b, c, d, x, work);
+    double *xt = work, *v = work + n, *w = work + 2 * n, *scratch = work + 3 * n;
+    double *y = scratch + 6 * m;
+    st = local_solves(n, P, periodic, a, b, c, d, xt, v, w, scratch);
+    if (st) return st;
+    const int NI = n_interfaces(P, periodic);
+    for (int i = 1; i <= NI; ++i) {
+        const int L = i - 1, R = i % P;
+        const int64_t lastL = (int64_t)L * m + m - 1, firstR = (int64_t)R * m;
+        const double z12 = w[lastL], z21 = v[firstR];
+        const double r1 = xt[lastL], r2 = xt[firstR];
+        const double det = 1.0 - z12 * z21;
+        if (det == 0.0) return ORC_E_ZERO_PIVOT;
+        y[2 * i - 2] = (r1 - z12 * r2) / det;
+        y[2 * i - 1] = (r2 - z21 * r1) / det;
+    }
+    correct(m, P, periodic, xt, v, w, y, x);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PPT (Sec. 3.2, Eqs. (9)-(11)): with the pair-swapping permutation P,      */
+/* Zbar = P + E^T A~^{-1} V P = Z P is tridiagonal (cyclic when periodic);   */
+/* solve Zbar ybar = E^T x~ by Gaussian elimination with partial pivoting,   */
+/* then x = x~ - Ybar ybar with Ybar = Y P, i.e. y = P ybar.                 */
+/* ------------------------------------------------------------------------ */
+static void permute_pairs(int K, const double *in, double *out)
+{
+    for (int k = 0; k < K; k += 2) { out[k] = in[k + 1]; out[k + 1] = in[k]; }
+}
+
+int orc_ppt(int64_t n, int P, int periodic, const double *a, const double *b,
+            const double *c, const double *d, double *x, double *work)
+{
+    int st = check_shape(n, P, periodic);
+    if (st) return st;
+    const int64_t m = n / P;
+    if (P == 1 && !periodic) return orc_thomas(n, a, b, c, d, x, work);
+    const int NI = n_interfaces(P, periodic), K = 2 * NI;
+    double *xt = work, *v = work + n, *w = work + 2 * n, *scratch = work + 3 * n;
+    double *Z = scratch + 6 * m, *Zbar = Z + K * K, *rhs = Zbar + K * K, *ybar = rhs + K;
+    double *y = ybar + K;
+    st = local_solves(n, P, periodic, a, b, c, d, xt, v, w, scratch);
+    if (st) return st;
+    assemble_Z(m, P, periodic, xt, v, w, Z, rhs);
+    /* Zbar = Z P : swap columns 2i-1 <-> 2i of Z */
+    for (int row = 0; row < K; ++row)
+        for (int col = 0; col < K; col += 2) {
+            Zbar[row * K + col] = Z[row * K + col + 1];
+            Zbar[row * K + col + 1] = Z[row * K + col];
+        }
+    for (int k = 0; k < K; ++k) ybar[k] = rhs[k];
+    st = gepp_solve(K, Zbar, ybar);                                    /* Eq. (10) */
+    if (st) return st;
+    permute_pairs(K, ybar, y);                                         /* Ybar ybar = Y (P ybar) */
+    correct(m, P, periodic, xt, v, w, y, x);                           /* Eq. (11) */
+    return ORC_OK;
+}
+
+/* Exact solution: Thomas (non-periodic) or the Sherman-Morrison cyclic solve. */
+int orc_exact(int64_t n, int periodic, const double *a, const double *b,
+              const double *c, const double *d, double *x, double *work)
+{
+    return periodic ? orc_cyclic(n, a, b, c, d, x, work) : orc_thomas(n, a, b, c, d, x, work);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics for the pattern pins: Z, Zbar (K x K each), E^T x~ and the    */
+/* spikes of one line.  out_Z, out_Zbar: K*K; out_rhs: K; v_out, w_out: n.   */
+/* ------------------------------------------------------------------------ */
+int orc_reduced_system(int64_t n, int P, int periodic, const double *a,
+                       const double *b, const double *c, const double *d,
+                       double *out_Z, double *out_Zbar, double *out_rhs,
+                       double *xt_out, double *v_out, double *w_out)
+{
+    int st = check_shape(n, P, periodic);
+    if (st) return st;
+    if (P == 1 && !periodic) return ORC_E_SHAPE;
+    const int64_t m = n / P;
+    const int K = 2 * n_interfaces(P, periodic);
+    double *scratch = (double *)malloc(sizeof(double) * (size_t)(6 * m + 8));
+    if (!scratch) return ORC_E_NOMEM;
+    st = local_solves(n, P, periodic, a, b, c, d, xt_out, v_out, w_out, scratch);
+    free(scratch);
+    if (st) return st;
+    assemble_Z(m, P, periodic, xt_out, v_out, w_out, out_Z, out_rhs);
+    for (int row = 0; row < K; ++row)
+        for (int col = 0; col < K; col += 2) {
+            out_Zbar[row * K + col] = out_Z[row * K + col + 1];
+            out_Zbar[row * K + col + 1] = out_Z[row * K + col];
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Batched driver.  Line (b0, b1), b0 < nb0, b1 < nb1, has its row j at      */
+/*   d[j*s_j + b0*s_b0 + b1*s_b1]                                            */
+/* and coefficients at a[j*cs_j + b0*cs_b0 + b1*cs_b1] (stride 0 = shared).  */
+/* method: ORC_EXACT, ORC_PDD or ORC_PPT.  d is overwritten by x.            */
+/* Returns the first error met (lines after it may be left unsolved).        */
+/* ------------------------------------------------------------------------ */
+int orc_solve_batch(int method, int64_t n, int P, int periodic,
+                    const double *a, const double *b, const double *c,
+                    int64_t cs_j, int64_t cs_b0, int64_t cs_b1,
+                    double *d, int64_t nb0, int64_t nb1,
+                    int64_t s_j, int64_t s_b0, int64_t s_b1, int nthreads)
+{
+    if (!a || !b || !c || !d) return ORC_E_ARG;
+    if (method != ORC_EXACT) {
+        int st = check_shape(n, P, periodic);
+        if (st) return st;
+    } else if (n < 1 || (periodic && n < 3)) {
+        return ORC_E_SHAPE;
+    }
+    const int64_t nlines = nb0 * nb1;
+    const int64_t lw = orc_line_work(n, P);
+    int status = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(5 * n + lw));
+        if (!buf) {
+#pragma omp critical
+            status = ORC_E_NOMEM;
+        } else {
+            double *la = buf, *lb = buf + n, *lc = buf + 2 * n, *ld = buf + 3 * n;
+            double *lx = buf + 4 * n, *work = buf + 5 * n;
+#pragma omp for schedule(static)
+            for (int64_t L = 0; L < nlines; ++L) {
+                const int64_t b0 = L % nb0, b1 = L / nb0;
+                const int64_t o = b0 * s_b0 + b1 * s_b1, co = b0 * cs_b0 + b1 * cs_b1;
+                for (int64_t j = 0; j < n; ++j) {
+                    la[j] = a[co + j * cs_j];
+                    lb[j] = b[co + j * cs_j];
+                    lc[j] = c[co + j * cs_j];
+                    ld[j] = d[o + j * s_j];
+                }
+                int st;
+                if (method == ORC_PDD) st = orc_pdd(n, P, periodic, la, lb, lc, ld, lx, work);
+                else if (method == ORC_PPT) st = orc_ppt(n, P, periodic, la, lb, lc, ld, lx, work);
+                else st = orc_exact(n, periodic, la, lb, lc, ld, lx, work);
+                if (st) {
+#pragma omp critical
+                    if (status == ORC_OK) status = st;
+                    continue;
+                }
+                for (int64_t j = 0; j < n; ++j) d[o + j * s_j] = lx[j];
+            }
+            free(buf);
+        }
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One ADI sweep over u[Nz][Ny][Nx] (x fastest) along direction dir          */
+/* (0 = x, 1 = y, 2 = z); a, b, c have the length of that direction and are  */
+/* shared by every line (Sec. 2.2: one tridiagonal system per direction).    */
+/* ------------------------------------------------------------------------ */
+int orc_adi_sweep(int method, int dir, double *u, int64_t Nx, int64_t Ny, int64_t Nz,
+                  const double *a, const double *b, const double *c,
+                  int P, int periodic, int nthreads)
+{
+    if (dir == 0)
+        return orc_solve_batch(method, Nx, P, periodic, a, b, c, 1, 0, 0,
+                               u, Ny, Nz, 1, Nx, Nx * Ny, nthreads);
+    if (dir == 1)
+        return orc_solve_batch(method, Ny, P, periodic, a, b, c, 1, 0, 0,
+                               u, Nx, Nz, Nx, 1, Nx * Ny, nthreads);
+    if (dir == 2)
+        return orc_solve_batch(method, Nz, P, periodic, a, b, c, 1, 0, 0,
+                               u, Nx, Ny, Nx * Ny, 1, Nx, nthreads);
+    return ORC_E_ARG;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Wall-normal Poisson solves per spanwise wavenumber (Sec. 2.2; PPT        */
+/* paragraph of Sec. 3.2).  phihat[Nk][Ny][Nx] complex128 interleaved (re,  */
+/* im); for wavenumber k the real matrix is a_j = ay_j, c_j = cy_j,          */
+/* b_j = -(ay_j + cy_j) - lam_k; real and imaginary parts are independent    */
+/* real right-hand sides of the same real matrix.  A mode with lam_k == 0 is */
+/* the singular Neumann operator: row 0 is replaced by x_0 = 0.              */
+/* ------------------------------------------------------------------------ */
+int orc_poisson(int method, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
+                const double *ay, const double *cy, const double *lam, int P, int nthreads)
+{
+    if (!phihat || !ay || !cy || !lam) return ORC_E_ARG;
+    double *bk = (double *)malloc(sizeof(double) * (size_t)(3 * Ny));
+    if (!bk) return ORC_E_NOMEM;
+    double *ak = bk + Ny, *ck = bk + 2 * Ny;
+    int status = ORC_OK;
+    for (int64_t k = 0; k < Nk && status == ORC_OK; ++k) {
+        for (int64_t j = 0; j < Ny; ++j) {
+            ak[j] = ay[j];
+            ck[j] = cy[j];
+            bk[j] = -(ay[j] + cy[j]) - lam[k];
+        }
+        double *plane = phihat + 2 * k * Ny * Nx;
+        if (lam[k] == 0.0) {          /* gauge: x_0 = 0 */
+            bk[0] = 1.0;
+            ck[0] = 0.0;
+            for (int64_t i = 0; i < 2 * Nx; ++i) plane[i] = 0.0;
+        }
+        /* real view: 2*Nx independent real lines, row stride 2*Nx */
+        status = orc_solve_batch(method, Ny, P, 0, ak, bk, ck, 1, 0, 0,
+                                 plane, 2 * Nx, 1, 2 * Nx, 1, 0, nthreads);
+    }
+    free(bk);
+    return status;
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,54 @@
+"""Projection step on a staggered (y, z) grid, FP64, numpy + the oracle's solves.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+The fractional-step method of Sec. 2.2 ends each sub-step by projecting the
+intermediate velocity onto a divergence-free field with the pseudo-pressure
+phi: the Poisson equation for phi is solved with a Fourier transform in the
+periodic spanwise direction and complex tridiagonal solves in y, then the
+velocity is corrected by the gradient of phi.  Here every x-station is an
+independent (y, z) plane, with
+
+* cells j = 0..Ny-1 (wall-clustered widths dy_j), k = 0..Nz-1 (periodic, dz);
+* v on y-faces j = 0..Ny (v = 0 on the wall y = 0 and on the top y = 1);
+* w on z-faces k = 0..Nz-1 (face k between cells k-1 and k).
+
+Discrete divergence D = (v_{j+1}-v_j)/dy_j + (w_{k+1}-w_k)/dz; the matching
+Laplacian div(grad phi) has off-diagonals ay_j = 1/(dy_j h_{j-1/2}),
+cy_j = 1/(dy_j h_{j+1/2}) in y and, after the real FFT in z, the shift
+-lam_k = -(4/dz^2) sin^2(pi k/Nz); the k = 0 mode is gauge pinned.  Because
+the operators are built to match, the corrected velocity is divergence free
+to round-off, which pins the Poisson solve end to end.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import PPT, poisson
+
+
+def divergence(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float) -> np.ndarray:
+    """v[Nz][Ny+1][Nx], w[Nz][Ny][Nx] -> D[Nz][Ny][Nx] at cell centres."""
+    dv = (v[:, 1:, :] - v[:, :-1, :]) / dy[None, :, None]
+    dw = (np.roll(w, -1, axis=0) - w) / dz
+    return dv + dw
+
+
+def project(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float, P: int = 4,
+            method: int = PPT, nthreads: int = 0):
+    """Return (v_new, w_new, phi) with div(v_new, w_new) = 0 to round-off."""
+    Nz, Ny, Nx = w.shape
+    yc_gap = 0.5 * (dy[:-1] + dy[1:])            # h_{j+1/2}, j = 0..Ny-2
+    ay = np.zeros(Ny)
+    cy = np.zeros(Ny)
+    ay[1:] = 1.0 / (dy[1:] * yc_gap)
+    cy[:-1] = 1.0 / (dy[:-1] * yc_gap)
+    lam = (4.0 / dz ** 2) * np.sin(np.pi * np.arange(Nz // 2 + 1) / Nz) ** 2
+    D = divergence(v, w, dy, dz)
+    Dhat = np.ascontiguousarray(np.fft.rfft(D, axis=0))
+    poisson(Dhat, ay, cy, lam, P=P, method=method, nthreads=nthreads)
+    phi = np.fft.irfft(Dhat, n=Nz, axis=0)
+    v_new = v.copy()
+    v_new[:, 1:Ny, :] -= (phi[:, 1:, :] - phi[:, :-1, :]) / yc_gap[None, :, None]
+    w_new = w - (phi - np.roll(phi, 1, axis=0)) / dz
+    return v_new, w_new, phi
