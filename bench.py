@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark: one time step's tridiagonal work on one MI355X.
+
+Workload (synthetic, seeded, boundary-layer shaped; 2048 x 256 x 288 cells):
+  * ADI momentum sweeps over u[Nz][Ny][Nx] (x fastest), FP64, PDD:
+      x: lines of 2048, contiguous, P = 8, uniform mesh, r = dt*nu/dx^2
+      y: lines of 256, stride Nx, P = 4, tanh-stretched wall-normal mesh
+      z: lines of 288, stride Nx*Ny, periodic, P = 4
+  * Poisson wavenumber solves, FP64, PPT, P = 4: spanwise rFFT of an N(0,1)
+    field (input preparation, host, untimed) -> 145 x 256 x 2048 complex;
+    k = 0 gauge pinned.
+A step is the four solves in sequence, each one kernel launch (partition
+factors, spikes and reduced-system rows are computed once, when the plans
+are created).  Inputs are resident in HBM before timing; the solves run in
+place, so each timed step solves the previous step's output (the work does
+not depend on the values).
+
+Prints one JSON line (metric, value = solved unknowns/s for the whole step,
+roofline of the dominant kernel from HIP events, CPU-oracle baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+NX, NY, NZ = 2048, 256, 288
+HBM_PEAK_GBS = 8000.0
+METRIC = "solved unknowns/s + % HBM peak; FP32+refine vs FP64 at 1e-12 rel err"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--nx", type=int, default=NX)
+    ap.add_argument("--ny", type=int, default=NY)
+    ap.add_argument("--nz", type=int, default=NZ)
+    return ap.parse_args()
+
+
+def build_inputs(nx, ny, nz):
+    import workloads as W
+    t0 = time.perf_counter()
+    u0 = W.cfg_field(nx, ny, nz, seed=0)
+    phi0 = W.cfg_poisson_rhs(nx, ny, nz, seed=1)
+    coef = {"x": W.momentum_uniform(nx), "y": W.momentum_stretched(ny), "z": W.momentum_periodic(nz)}
+    ay, cy = W.poisson_metric(ny)
+    lam = W.modified_wavenumbers(nz)
+    log(f"inputs generated in {time.perf_counter() - t0:.1f}s")
+    return u0, phi0, coef, ay, cy, lam
+
+
+ITEMS = [  # name, direction, P, periodic, method
+    ("adi_x", 0, 8, False, "PDD"),
+    ("adi_y", 1, 4, False, "PDD"),
+    ("adi_z", 2, 4, True, "PDD"),
+    ("poisson", None, 4, False, "PPT"),
+]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU y-slab design is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1812_01178_amd as T
+    import oracle
+
+    nx, ny, nz = args.nx, args.ny, args.nz
+    nk = nz // 2 + 1
+    u0, phi0, coef, ay, cy, lam = build_inputs(nx, ny, nz)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = T.tri_create(0, stream.cuda_stream)
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x)).cuda()
+    du0, dphi0 = dev(u0), torch.as_tensor(phi0).cuda()
+    u, phi = du0.clone(), dphi0.clone()
+    dcoef = {k: tuple(dev(v) for v in abc) for k, abc in coef.items()}
+    day, dcy, dlam = dev(ay), dev(cy), dev(lam)
+
+    plans = {}
+    for name, direction, P, per, meth in ITEMS:
+        if name == "poisson":
+            it = dict(kind=T.TRI_ITEM_POISSON, field=phi, Nx=nx, Ny=ny, Nz=nk, a=day, c=dcy, lam=dlam,
+                      P=P, method=T.TRI_PPT)
+        else:
+            a, b, c = dcoef["xyz"[direction]]
+            it = dict(kind=direction, field=u, Nx=nx, Ny=ny, Nz=nz, a=a, b=b, c=c, P=P,
+                      periodic=int(per), method=T.TRI_PDD if meth == "PDD" else T.TRI_PPT)
+        plans[name] = T.tri_plan_create(ctx, [it])
+    T.tri_sync_status(ctx)
+
+    unknowns = {"adi_x": nx * ny * nz, "adi_y": nx * ny * nz, "adi_z": nx * ny * nz,
+                "poisson": nk * ny * nx}
+    bytes_per = {"adi_x": 16, "adi_y": 16, "adi_z": 16, "poisson": 32}   # read d + write x, FP64
+
+    # ---------------- parity on sampled lines, pristine inputs -------------
+    parity = {}
+    if not args.no_parity:
+        rng = np.random.default_rng(123)
+        for name, direction, P, per, meth in ITEMS:
+            om = oracle.PDD if meth == "PDD" else oracle.PPT
+            if name == "poisson":
+                phi.copy_(dphi0)
+                T.tri_plan_execute(plans[name])
+                ks = rng.integers(0, nk, 24)
+                ks[:4] = [0, 1, 2, nk - 1]
+                iis = rng.integers(0, nx, 24)
+                got = phi[torch.as_tensor(ks), :, torch.as_tensor(iis)].cpu().numpy()                    # (24, ny)
+                errs = []
+                b_all = -(ay + cy)
+                for s, (k, i) in enumerate(zip(ks, iis)):
+                    b = b_all - lam[k]
+                    a_, c_ = ay.copy(), cy.copy()
+                    rhs = phi0[k, :, i].copy()
+                    if lam[k] == 0.0:
+                        b = b.copy(); b[0] = 1.0; c_[0] = 0.0; rhs[0] = 0.0
+                    ref = oracle.ppt(a_, b, c_, rhs.real, P) + 1j * oracle.ppt(a_, b, c_, rhs.imag, P)
+                    errs.append(np.max(np.abs(got[s] - ref)) / np.max(np.abs(ref)))
+                parity[name] = float(max(errs))
+            else:
+                u.copy_(du0)
+                T.tri_plan_execute(plans[name])
+                a, b, c = coef["xyz"[direction]]
+                nsamp = 48
+                if direction == 0:
+                    j, k = rng.integers(0, ny, nsamp), rng.integers(0, nz, nsamp)
+                    got = u[torch.as_tensor(k), torch.as_tensor(j), :].cpu().numpy(); lines = u0[k, j, :]
+                elif direction == 1:
+                    i, k = rng.integers(0, nx, nsamp), rng.integers(0, nz, nsamp)
+                    got = u[torch.as_tensor(k), :, torch.as_tensor(i)].cpu().numpy(); lines = u0[k, :, i]
+                else:
+                    i, j = rng.integers(0, nx, nsamp), rng.integers(0, ny, nsamp)
+                    got = u[:, torch.as_tensor(j), torch.as_tensor(i)].T.cpu().numpy(); lines = u0[:, j, i].T
+                fn = oracle.pdd if om == oracle.PDD else oracle.ppt
+                errs = [np.max(np.abs(got[s] - fn(a, b, c, lines[s], P, per))) /
+                        np.max(np.abs(fn(a, b, c, lines[s], P, per))) for s in range(nsamp)]
+                parity[name] = float(max(errs))
+            log(f"parity {name}: max line rel err {parity[name]:.2e}")
+        u.copy_(du0)
+        phi.copy_(dphi0)
+        torch.cuda.synchronize()
+
+    # ---------------- timed steps -----------------------------------------
+    names = [it[0] for it in ITEMS]
+
+    def step(events=None):
+        for idx, name in enumerate(names):
+            if events is not None:
+                events[idx].record(stream)
+            T.tri_plan_execute(plans[name])
+        if events is not None:
+            events[len(names)].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T.tri_sync_status(ctx)
+    per_item_ms = {n: float(np.mean([ev[s][i].elapsed_time(ev[s][i + 1]) for s in range(args.steps)]))
+                   for i, n in enumerate(names)}
+    step_ms_events = float(np.mean([ev[s][0].elapsed_time(ev[s][-1]) for s in range(args.steps)]))
+    ms_per_step = wall * 1e3 / args.steps
+    total_unknowns = sum(unknowns.values())
+    value = total_unknowns / (ms_per_step * 1e-3)
+    kernels = {}
+    for n in names:
+        gbs = unknowns[n] * bytes_per[n] / (per_item_ms[n] * 1e-3) / 1e9
+        kernels[n] = {"ms": round(per_item_ms[n], 4), "unknowns": unknowns[n],
+                      "alg_bytes": unknowns[n] * bytes_per[n], "GB_s": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                      "unknowns_per_s": unknowns[n] / (per_item_ms[n] * 1e-3)}
+        log(f"{n}: {per_item_ms[n]:.4f} ms  {gbs:.0f} GB/s  ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    dom = max(names, key=lambda n: per_item_ms[n])
+    step_bytes = sum(unknowns[n] * bytes_per[n] for n in names)
+
+    # ---------------- CPU oracle baseline (bounded sample) ----------------
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"ADI x/y/z (PDD) + Poisson wavenumber (PPT) solves on {nx}x{ny}x{nz}",
+                   "Nx": nx, "Ny": ny, "Nz": nz, "Nk": nk,
+                   "P": {n: it[2] for n, it in zip(names, ITEMS)},
+                   "method": {n: it[4] for n, it in zip(names, ITEMS)},
+                   "unknowns_per_step": total_unknowns},
+        "hbm_frac_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_ms_events": step_ms_events,
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4), "traffic": None},
+        "parity_max_line_rel_err": parity,
+        "cpu_baseline": cpu,
+    }
+    for p in plans.values():
+        T.tri_plan_destroy(p)
+    T.tri_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, target_s):
+    """The oracle as it stands, all host cores, on a sample of each solve's
+    lines (every q-th outer index), scaled to unknowns/s of the whole step."""
+    cores = len(os.sched_getaffinity(0))
+    Nz, Ny, Nx = u0.shape
+    Nk = phi0.shape[0]
+
+    def run(frac_outer):
+        t_item, n_item = {}, {}
+        # x lines: sample z-planes
+        qz = max(1, int(round(1 / frac_outer)))
+        sub = np.ascontiguousarray(u0[::qz])
+        t0 = time.perf_counter()
+        oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], 8, False, nthreads=cores)
+        t_item["adi_x"], n_item["adi_x"] = time.perf_counter() - t0, sub.size
+        sub = np.ascontiguousarray(u0[::qz])
+        t0 = time.perf_counter()
+        oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], 4, False, nthreads=cores)
+        t_item["adi_y"], n_item["adi_y"] = time.perf_counter() - t0, sub.size
+        qy = max(1, int(round(1 / frac_outer)))
+        sub = np.ascontiguousarray(u0[:, ::qy])
+        t0 = time.perf_counter()
+        oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], 4, True, nthreads=cores)
+        t_item["adi_z"], n_item["adi_z"] = time.perf_counter() - t0, sub.size
+        qk = max(1, int(round(1 / frac_outer)))
+        sub = np.ascontiguousarray(phi0[::qk])
+        t0 = time.perf_counter()
+        oracle.poisson(sub, ay, cy, lam[::qk], P=4, nthreads=cores)
+        t_item["poisson"], n_item["poisson"] = time.perf_counter() - t0, sub.size
+        return t_item, n_item
+
+    frac = 1 / 64
+    t_item, n_item = run(frac)
+    spent = sum(t_item.values())
+    if spent < target_s / 4:
+        frac = min(1.0, frac * target_s / max(spent, 1e-3))
+        t_item, n_item = run(frac)
+    full = {"adi_x": Nx * Ny * Nz, "adi_y": Nx * Ny * Nz, "adi_z": Nx * Ny * Nz, "poisson": Nk * Ny * Nx}
+    step_s = sum(t_item[k] / n_item[k] * full[k] for k in full)
+    total = sum(full.values())
+    log(f"cpu oracle: {sum(t_item.values()):.1f}s on {sum(n_item.values())} unknowns, "
+        f"{cores} threads -> full step {step_s:.2f}s")
+    return {"value": total / step_s, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle PDD/PPT (FP64, C, OpenMP {cores} threads) on every "
+                      f"{int(round(1 / frac))}-th outer plane of each of the 4 solves "
+                      f"({sum(n_item.values())} unknowns, {sum(t_item.values()):.1f}s), scaled to the step",
+            "step_seconds_est": step_s}
+
+
+if __name__ == "__main__":
+    main()

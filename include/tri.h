@@ -1,0 +1,209 @@
+/*
+ * tri.h -- C ABI of libtri: batched partitioned tridiagonal solves with the
+ * Parallel Diagonal Dominant (PDD) and Parallel Partition (PPT) methods on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Ha, Park & You, "A scalable multi-GPU method for semi-implicit
+ * fractional-step integration of incompressible Navier-Stokes equations",
+ * arXiv:1812.01178, Sec. 3.2 (Eqs. (3)-(11), Algorithm 1).  The paper's
+ * domain decomposition of each line over p GPUs becomes P partitions of the
+ * line inside one GPU; the paper's neighbour exchange (PDD) and all-gather
+ * (PPT) become on-chip exchanges.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * A line is the tridiagonal system
+ *     a_j x_{j-1} + b_j x_j + c_j x_{j+1} = d_j,      j = 0 .. n-1
+ * (the paper's A = [a_j, b_j, c_j], Sec. 3.2).  For a non-periodic line a_0
+ * and c_{n-1} are not part of the matrix and are never read.  For a periodic
+ * line (periodic = 1) a_0 couples row 0 to x_{n-1} and c_{n-1} couples row
+ * n-1 to x_0.
+ *
+ * The line is split into P partitions of m = n/P consecutive rows; n must be
+ * divisible by P, and m >= 2 unless P = 1 on a non-periodic line.
+ * 1 <= P <= TRI_MAX_PARTITIONS.  PDD's result depends on P (it drops the
+ * Z entries v_m and w_1, Sec. 3.2); PPT's does not (Eqs. (9)-(11) are exact).
+ *
+ * Memory: every array pointer passed to a solve is a DEVICE pointer on the
+ * context's device, owned by the caller; the library never frees or keeps it
+ * past the call (plans keep the pointers given at creation, see below).
+ * Right-hand sides are overwritten in place by the solution (Algorithm 1
+ * returns its outputs in d1, d2, d3).  Work is queued on the context's
+ * stream and the call returns without waiting, unless a tri_info is passed
+ * (then the call waits for the stream to fill it in).
+ *
+ * Errors: argument and shape errors are returned before anything is launched
+ * and leave the data untouched.  Conditions found on the device (a zero pivot
+ * in a partition block, refinement that did not converge) are recorded in a
+ * sticky status word of the context and returned by tri_sync_status().
+ * All FP64 arithmetic is IEEE double; FP32 arithmetic is used only where a
+ * call's tri_prec asks for it.
+ */
+#ifndef TRI_H
+#define TRI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRI_MAX_PARTITIONS 16
+
+typedef struct tri_ctx_s *tri_ctx;
+typedef struct tri_plan_s *tri_plan;
+
+typedef enum {
+    TRI_OK = 0,
+    TRI_E_ARG = 1,           /* null pointer, bad enum, negative size            */
+    TRI_E_SHAPE = 2,         /* n % P != 0, m < 2, P out of range, n < 3 periodic */
+    TRI_E_ZERO_PIVOT = 3,    /* a partition block hit a zero pivot (device)      */
+    TRI_E_PDD_UNSAFE = 4,    /* reserved: strict PDD truncation check            */
+    TRI_E_NOT_CONVERGED = 5, /* FP32 + FP64 refinement did not converge (device) */
+    TRI_E_HIP = 6,           /* a HIP runtime call failed                        */
+    TRI_E_NOMEM = 7,         /* device or host allocation failed                 */
+    TRI_E_UNSUPPORTED = 8    /* valid request outside what this build handles    */
+} tri_status;
+
+typedef enum { TRI_F64 = 0, TRI_F32_REFINE = 1 } tri_prec;
+typedef enum { TRI_REAL = 0, TRI_COMPLEX = 1 } tri_field;
+typedef enum { TRI_PDD = 0, TRI_PPT = 1 } tri_method;
+typedef enum { TRI_DIR_X = 0, TRI_DIR_Y = 1, TRI_DIR_Z = 2 } tri_dir;
+
+/* Batch of lines.  Line (b0, b1), 0 <= b0 < nb0, 0 <= b1 < nb1, has row j at
+ * element  j*s_j + b0*s_b0 + b1*s_b1  of the field (strides in field
+ * elements; a complex element is one interleaved (re, im) pair of doubles).
+ * nb0 = 0 or nb1 = 0 is an empty batch (returns TRI_OK, launches nothing).
+ * Throughput is best with s_b0 = 1 (lines side by side, rows strided) or
+ * s_j = 1 (rows contiguous). */
+typedef struct {
+    int64_t n, nb0, nb1;
+    int64_t s_j, s_b0, s_b1;
+} tri_lines;
+
+/* Coefficients: row j of line (b0, b1) reads a/b/c at
+ * j*cs_j + b0*cs_b0 + b1*cs_b1.  A zero stride broadcasts: cs_b0 = cs_b1 = 0
+ * is one matrix shared by all lines (factored once per call); cs_b0 = 0 with
+ * cs_b1 != 0 is one matrix per b1 index.  Coefficients are real FP64 even for
+ * complex fields (Sec. 2.2: real matrix, complex right-hand side). */
+typedef struct {
+    const double *a, *b, *c;
+    int64_t cs_j, cs_b0, cs_b1;
+} tri_coef;
+
+/* Optional host-side report (pass NULL to keep the call asynchronous). */
+typedef struct {
+    int sweeps;           /* refinement sweeps done (0 for plain FP64)          */
+    double pdd_drop_max;  /* largest |dropped Z entry| (v_m, w_1) over the call; */
+                          /* PDD's error is bounded by about 4x this times |x|  */
+    double resid_max;     /* FP32+refine: largest final correction / |x|        */
+} tri_info;
+
+/* ---- context ------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, queueing work on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  Allocates the status
+ * word.  *out receives the handle. */
+tri_status tri_create(tri_ctx *out, int device, void *hip_stream);
+/* Release the context and its workspace (waits for its stream). */
+tri_status tri_destroy(tri_ctx ctx);
+/* Change the stream later calls queue on. */
+tri_status tri_set_stream(tri_ctx ctx, void *hip_stream);
+/* Wait for the stream, read and clear the sticky device status word:
+ * TRI_OK, TRI_E_ZERO_PIVOT or TRI_E_NOT_CONVERGED. */
+tri_status tri_sync_status(tri_ctx ctx);
+/* Static English text for a status code. */
+const char *tri_status_string(int status);
+/* Text of the last error that this context returned (validation detail). */
+const char *tri_last_error(tri_ctx ctx);
+
+/* ---- the four solves ------------------------------------------------------ */
+
+/* PDD over a batch of lines (Sec. 3.2, PDD paragraph; Algorithm 1 steps 1-7):
+ * per partition the local solves A~ x~ = d and A~ Y = V (Eqs. (5), (6)), the
+ * 2x2 interface systems of the block-diagonal part of Z (Eq. (7) with v_m and
+ * w_1 dropped), and x = x~ - Y y (Eq. (8)).  field: TRI_REAL (d_inout is
+ * double*) or TRI_COMPLEX (d_inout is interleaved complex128, s_b0 must be 1).
+ * prec: TRI_F64, or TRI_F32_REFINE (FP32 elimination + FP64 residual
+ * refinement towards the exact A^{-1} d, at most 3 sweeps). */
+tri_status tri_pdd_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines,
+                         tri_field field, void *d_inout, int P, int periodic,
+                         tri_prec prec, tri_info *info);
+
+/* PPT over a batch of lines (Sec. 3.2, Eqs. (9)-(11)): the same local
+ * solves, the tridiagonal (cyclic when periodic) system Zbar y = E^T x~ solved
+ * with partial pivoting in FP64, and x = x~ - Ybar y.  Exact for any P.
+ * Arguments as tri_pdd_solve. */
+tri_status tri_ppt_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines,
+                         tri_field field, void *d_inout, int P, int periodic,
+                         tri_prec prec, tri_info *info);
+
+/* One ADI sweep (Sec. 2.2, Sec. 3: one tridiagonal system per direction) over
+ * the field u[Nz][Ny][Nx] (x fastest), in place.  dir: TRI_DIR_X (lines of
+ * length Nx, rows contiguous), TRI_DIR_Y (length Ny, row stride Nx) or
+ * TRI_DIR_Z (length Nz, row stride Nx*Ny).  a, b, c: device arrays of the
+ * length of that direction, shared by every line.  method: TRI_PDD or
+ * TRI_PPT.  periodic: 1 for the spanwise (z) direction of the paper. */
+tri_status adi_sweep(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t Ny,
+                     int64_t Nz, const double *a, const double *b, const double *c,
+                     int P, int periodic, int method, tri_prec prec, tri_info *info);
+
+/* Wall-normal Poisson solves per spanwise wavenumber (Sec. 2.2; PPT
+ * paragraph of Sec. 3.2), in place on phihat[Nk][Ny][Nx] complex128
+ * (interleaved re, im).  For mode k and every x-station the real matrix is
+ *     a_j = ay_j,  c_j = cy_j,  b_j = -(ay_j + cy_j) - lam_k,
+ * with ay_0 = cy_{Ny-1} = 0 for the Neumann ends (device arrays of length
+ * Ny; lam: device array of Nk modified wavenumbers >= 0).  A mode with
+ * lam_k == 0 is singular; it is gauge pinned by replacing row 0 with
+ * x_0 = 0.  Solved by PPT with P partitions.  With prec = TRI_F32_REFINE,
+ * modes k <= fp64_kmax stay in plain FP64. */
+tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t Nx,
+                                    int64_t Ny, int64_t Nk, const double *ay,
+                                    const double *cy, const double *lam, int P,
+                                    tri_prec prec, int fp64_kmax, tri_info *info);
+
+/* ---- plans: factor once, execute many times, capture as a HIP graph ------ */
+
+typedef enum { TRI_ITEM_ADI_X = 0, TRI_ITEM_ADI_Y = 1, TRI_ITEM_ADI_Z = 2,
+               TRI_ITEM_POISSON = 3 } tri_item_kind;
+
+/* One piece of a time step's tridiagonal work.  field: u (ADI, double
+ * [Nz][Ny][Nx]) or phihat (POISSON, complex128 [Nz][Ny][Nx] with Nz = Nk
+ * modes).  ADI: a, b, c of the sweep direction; POISSON: a = ay, c = cy,
+ * lam = modified wavenumbers, b unused.  P = 0 lets the plan's tuner choose
+ * (PPT, or PDD only where the dropped entries are below 1e-15); method is
+ * TRI_PDD or TRI_PPT (POISSON always uses PPT).  The coefficient arrays are
+ * read once, at creation; the field pointer is kept and solved in place at
+ * every execution. */
+typedef struct {
+    int kind;
+    void *field;
+    int64_t Nx, Ny, Nz;
+    const double *a, *b, *c, *lam;
+    int P;
+    int periodic;
+    int method;
+} tri_item;
+
+/* Validate the items, allocate the plan's device tables, factor every
+ * matrix (partition factors, spikes, reduced-system inverses) and choose
+ * the launch shapes.  All allocation happens here. */
+tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
+                           tri_plan *out);
+/* Queue every item's solve on the context stream (no allocation, no host
+ * synchronisation). */
+tri_status tri_plan_execute(tri_plan plan);
+/* Record tri_plan_execute into a HIP graph and instantiate it; *graph_exec_out
+ * receives the hipGraphExec_t, owned by the plan. */
+tri_status tri_plan_capture(tri_plan plan, void **graph_exec_out);
+/* Launch the captured graph on the context stream. */
+tri_status tri_plan_graph_launch(tri_plan plan);
+/* Partition count the plan uses for item i (after tuning), or -1. */
+int tri_plan_item_partitions(tri_plan plan, int i);
+tri_status tri_plan_destroy(tri_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRI_H */

@@ -1,0 +1,607 @@
+// tri_api.hip -- host side of the libtri C ABI (include/tri.h): argument
+// validation, contexts, workspace, kernel selection, plans and HIP graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "tri_internal.h"
+
+using namespace tri;
+
+struct tri_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int *status_dev = nullptr;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::string last_error;
+};
+
+namespace {
+
+tri_status fail(tri_ctx ctx, tri_status st, const char *fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), TRI_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// One solve request after validation, in the real view of the field.
+struct Problem {
+    int method = TRI_PDD;
+    int P = 1, periodic = 0, cplx = 0;
+    LineSet L{};
+    bool general = false;
+    // shared / per-b1 matrices
+    MatSrc src{};
+    int64_t G = 1, g_b1 = 0;
+    // per-line coefficients
+    const double *ga = nullptr, *gb = nullptr, *gc = nullptr;
+    int64_t cs_j = 0, cs_b0 = 0, cs_b1 = 0;
+};
+
+// Kernel choice for a shared-matrix problem.
+struct Launch {
+    int kind = 0;          // 0 strided, 1 contiguous
+    int chunk_max = 0;     // strided: CMAX instance
+    SolveArgs args{};
+};
+
+tri_status check_partition(tri_ctx ctx, int64_t n, int P, int periodic)
+{
+    if (P < 1 || P > TRI_MAX_PARTITIONS)
+        return fail(ctx, TRI_E_SHAPE, "P = %d outside 1..%d", P, TRI_MAX_PARTITIONS);
+    if (n < 1) return fail(ctx, TRI_E_SHAPE, "n = %lld < 1", (long long)n);
+    if (n % P != 0)
+        return fail(ctx, TRI_E_SHAPE, "n = %lld not divisible by P = %d", (long long)n, P);
+    const int64_t m = n / P;
+    if (m < 2 && !(P == 1 && !periodic))
+        return fail(ctx, TRI_E_SHAPE, "partition size m = n/P = %lld < 2", (long long)m);
+    if (periodic && n < 3) return fail(ctx, TRI_E_SHAPE, "periodic line needs n >= 3");
+    return TRI_OK;
+}
+
+int pick_chunk(int m)
+{
+    static const int inst[] = {8, 16, 24, 32, 48, 64, 80};
+    for (int c : inst)
+        if (m <= c) return c;
+    return 0;
+}
+
+tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out)
+{
+    const int64_t n = pb.L.n;
+    const int P = pb.P;
+    const int m = (int)(n / P);
+    SolveArgs a{};
+    a.d = pb.L.d;
+    a.n = n;
+    a.m = m;
+    a.P = P;
+    a.periodic = pb.periodic;
+    a.s_j = pb.L.s_j;
+    a.nb0 = pb.L.nb0;
+    a.nb1 = pb.L.nb1;
+    a.s_b0 = pb.L.s_b0;
+    a.s_b1 = pb.L.s_b1;
+    a.g_b1 = pb.g_b1;
+    a.F = T.F;
+    a.IT = T.IT;
+    a.flags = T.flags;
+    a.nlines = pb.L.nb0 * pb.L.nb1;
+    if (pb.L.s_j == 1 && n > 1) {
+        // contiguous rows: lanes own C consecutive rows, Lp lanes per partition
+        int Lp = 1;
+        while (Lp < 64 && (m + Lp - 1) / Lp > 8) Lp <<= 1;
+        const int C = (m + Lp - 1) / Lp;
+        if (C > kContigMaxC)
+            return fail(ctx, TRI_E_UNSUPPORTED, "contiguous lines with m = %d > %d", m, 64 * kContigMaxC);
+        const int LL = P * Lp;
+        if (LL > 1024) return fail(ctx, TRI_E_UNSUPPORTED, "contiguous line needs %d lanes", LL);
+        if (C > 8 && LL > 256)
+            return fail(ctx, TRI_E_UNSUPPORTED, "contiguous line with m = %d needs P <= 4", m);
+        a.C = C;
+        a.Lp = Lp;
+        a.LL = LL;
+        a.LPB = std::max(1, 256 / LL);
+        out.kind = 1;
+    } else {
+        const int cmax = pick_chunk(m);
+        if (cmax == 0)
+            return fail(ctx, TRI_E_UNSUPPORTED, "strided lines with m = n/P = %d > %d", m, kStridedMaxM);
+        if (cmax > 32 && P > 8)
+            return fail(ctx, TRI_E_UNSUPPORTED, "strided lines with m = %d > 32 need P <= 8", m);
+        a.ngroups0 = (pb.L.nb0 + 63) / 64;
+        out.kind = 0;
+        out.chunk_max = cmax;
+    }
+    out.args = a;
+    return TRI_OK;
+}
+
+hipError_t run_launch(const Launch &l, int method, hipStream_t s)
+{
+    if (l.args.nlines == 0) return hipSuccess;
+    return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
+}
+
+size_t tables_bytes(int64_t G, int64_t n, int P)
+{
+    return tables_bytes_F(G, n) + tables_bytes_IT(G, P) + sizeof(double) * (size_t)G +
+           sizeof(int) * (size_t)G + 256;
+}
+
+Tables carve_tables(void *base, int64_t G, int64_t n, int P, int periodic, int method)
+{
+    Tables T;
+    char *p = (char *)base;
+    T.F = (double *)p;
+    p += tables_bytes_F(G, n);
+    T.IT = (double *)p;
+    p += tables_bytes_IT(G, P);
+    T.drop = (double *)p;
+    p += sizeof(double) * (size_t)G;
+    T.flags = (int *)p;
+    T.G = G;
+    T.n = n;
+    T.P = P;
+    T.periodic = periodic;
+    T.method = method;
+    return T;
+}
+
+tri_status ensure_ws(tri_ctx ctx, size_t bytes)
+{
+    if (bytes <= ctx->ws_bytes) return TRI_OK;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->ws) HIP_TRY(ctx, hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return fail(ctx, TRI_E_NOMEM, "workspace of %zu bytes", bytes);
+    ctx->ws = p;
+    ctx->ws_bytes = bytes;
+    return TRI_OK;
+}
+
+tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info)
+{
+    if (!info) return TRI_OK;
+    info->sweeps = 0;
+    info->resid_max = 0.0;
+    info->pdd_drop_max = 0.0;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (T && T->G > 0) {
+        std::vector<double> h((size_t)T->G);
+        HIP_TRY(ctx, hipMemcpy(h.data(), T->drop, sizeof(double) * (size_t)T->G, hipMemcpyDeviceToHost));
+        for (double v : h) info->pdd_drop_max = std::max(info->pdd_drop_max, v);
+    }
+    return TRI_OK;
+}
+
+// Run one validated problem through the context workspace.
+tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *info)
+{
+    if (prec != TRI_F64)
+        return fail(ctx, TRI_E_UNSUPPORTED, "precision %d not available in this path", (int)prec);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int64_t nlines = pb.L.nb0 * pb.L.nb1;
+    if (nlines == 0) {
+        if (info) *info = tri_info{0, 0.0, 0.0};
+        return TRI_OK;
+    }
+    const int m = (int)(pb.L.n / pb.P);
+    if (pb.general) {
+        if (m > kGeneralMaxM)
+            return fail(ctx, TRI_E_UNSUPPORTED, "per-line coefficients with m = %d > %d", m, kGeneralMaxM);
+        if (m > 16 && pb.P > 8)
+            return fail(ctx, TRI_E_UNSUPPORTED, "per-line coefficients with m = %d > 16 need P <= 8", m);
+        if (pb.method == TRI_PPT && pb.periodic && pb.P > 4)
+            return fail(ctx, TRI_E_UNSUPPORTED, "per-line periodic PPT needs P <= 4");
+        GeneralArgs g{};
+        g.d = pb.L.d;
+        g.n = pb.L.n;
+        g.m = m;
+        g.P = pb.P;
+        g.periodic = pb.periodic;
+        g.cplx = pb.cplx;
+        g.s_j = pb.L.s_j;
+        g.nb0 = pb.L.nb0;
+        g.nb1 = pb.L.nb1;
+        g.s_b0 = pb.L.s_b0;
+        g.s_b1 = pb.L.s_b1;
+        g.ngroups0 = (pb.L.nb0 + 63) / 64;
+        g.a = pb.ga;
+        g.b = pb.gb;
+        g.c = pb.gc;
+        g.cs_j = pb.cs_j;
+        g.cs_b0 = pb.cs_b0;
+        g.cs_b1 = pb.cs_b1;
+        g.status = ctx->status_dev;
+        HIP_TRY(ctx, launch_general(g, pb.method, ctx->stream));
+        return fill_info(ctx, nullptr, info);
+    }
+    tri_status st = ensure_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
+    if (st) return st;
+    Tables T = carve_tables(ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+    Launch l;
+    st = plan_launch(ctx, pb, T, l);
+    if (st) return st;
+    HIP_TRY(ctx, launch_factor(pb.src, T, ctx->status_dev, ctx->stream));
+    HIP_TRY(ctx, run_launch(l, pb.method, ctx->stream));
+    return fill_info(ctx, &T, info);
+}
+
+// Validate a tri_coef/tri_lines request and build its Problem.
+tri_status make_problem(tri_ctx ctx, int method, const tri_coef *coef, const tri_lines *lines,
+                        tri_field field, void *d, int P, int periodic, Problem &pb)
+{
+    if (!coef || !lines) return fail(ctx, TRI_E_ARG, "null coef or lines");
+    if (field != TRI_REAL && field != TRI_COMPLEX) return fail(ctx, TRI_E_ARG, "bad field %d", (int)field);
+    if (periodic != 0 && periodic != 1) return fail(ctx, TRI_E_ARG, "periodic must be 0 or 1");
+    if (lines->nb0 < 0 || lines->nb1 < 0) return fail(ctx, TRI_E_ARG, "negative batch extent");
+    tri_status st = check_partition(ctx, lines->n, P, periodic);
+    if (st) return st;
+    const bool empty = lines->nb0 == 0 || lines->nb1 == 0;
+    if (!empty && (!d || !coef->a || !coef->b || !coef->c))
+        return fail(ctx, TRI_E_ARG, "null data or coefficient pointer");
+    pb.method = method;
+    pb.P = P;
+    pb.periodic = periodic;
+    pb.cplx = field == TRI_COMPLEX;
+    LineSet L{(double *)d, lines->n, lines->nb0, lines->nb1, lines->s_j, lines->s_b0, lines->s_b1};
+    if (pb.cplx) {
+        if (lines->s_b0 != 1 && lines->nb0 > 1)
+            return fail(ctx, TRI_E_UNSUPPORTED, "complex fields need s_b0 = 1");
+        L.nb0 = 2 * lines->nb0;
+        L.s_b0 = 1;
+        L.s_j = 2 * lines->s_j;
+        L.s_b1 = 2 * lines->s_b1;
+    }
+    pb.L = L;
+    if (coef->cs_b0 == 0) {
+        pb.general = false;
+        pb.src = MatSrc{coef->a, coef->b, coef->c, coef->cs_j, coef->cs_b1, nullptr};
+        pb.G = (coef->cs_b1 == 0) ? 1 : lines->nb1;
+        pb.g_b1 = (coef->cs_b1 == 0) ? 0 : 1;
+    } else {
+        pb.general = true;
+        pb.ga = coef->a;
+        pb.gb = coef->b;
+        pb.gc = coef->c;
+        pb.cs_j = coef->cs_j;
+        pb.cs_b0 = coef->cs_b0;
+        pb.cs_b1 = coef->cs_b1;
+    }
+    return TRI_OK;
+}
+
+tri_status adi_problem(tri_ctx ctx, int dir, double *u, int64_t Nx, int64_t Ny, int64_t Nz,
+                       const double *a, const double *b, const double *c, int P, int periodic,
+                       int method, Problem &pb)
+{
+    if (Nx < 0 || Ny < 0 || Nz < 0) return fail(ctx, TRI_E_ARG, "negative grid extent");
+    if (method != TRI_PDD && method != TRI_PPT) return fail(ctx, TRI_E_ARG, "bad method %d", method);
+    tri_lines L{};
+    if (dir == TRI_DIR_X) L = tri_lines{Nx, Ny, Nz, 1, Nx, Nx * Ny};
+    else if (dir == TRI_DIR_Y) L = tri_lines{Ny, Nx, Nz, Nx, 1, Nx * Ny};
+    else if (dir == TRI_DIR_Z) L = tri_lines{Nz, Nx, Ny, Nx * Ny, 1, Nx};
+    else return fail(ctx, TRI_E_ARG, "bad direction %d", dir);
+    if (L.n == 0) return fail(ctx, TRI_E_SHAPE, "empty sweep direction");
+    tri_coef C{a, b, c, 1, 0, 0};
+    return make_problem(ctx, method, &C, &L, TRI_REAL, u, P, periodic, pb);
+}
+
+tri_status poisson_problem(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
+                           const double *ay, const double *cy, const double *lam, int P, Problem &pb)
+{
+    if (Nx < 0 || Ny < 1 || Nk < 0) return fail(ctx, TRI_E_ARG, "bad Poisson extents");
+    tri_status st = check_partition(ctx, Ny, P, 0);
+    if (st) return st;
+    const bool empty = Nx == 0 || Nk == 0;
+    if (!empty && (!phihat || !ay || !cy || !lam)) return fail(ctx, TRI_E_ARG, "null Poisson pointer");
+    pb.method = TRI_PPT;
+    pb.P = P;
+    pb.periodic = 0;
+    pb.cplx = 1;
+    pb.L = LineSet{phihat, Ny, 2 * Nx, Nk, 2 * Nx, 1, 2 * Nx * Ny};
+    pb.general = false;
+    pb.src = MatSrc{ay, nullptr, cy, 1, 0, lam};
+    pb.G = Nk;
+    pb.g_b1 = 1;
+    return TRI_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char *tri_status_string(int status)
+{
+    switch (status) {
+    case TRI_OK: return "success";
+    case TRI_E_ARG: return "invalid argument";
+    case TRI_E_SHAPE: return "invalid shape (n, P or partition size)";
+    case TRI_E_ZERO_PIVOT: return "zero pivot in a partition block";
+    case TRI_E_PDD_UNSAFE: return "PDD truncation above tolerance";
+    case TRI_E_NOT_CONVERGED: return "iterative refinement did not converge";
+    case TRI_E_HIP: return "HIP runtime error";
+    case TRI_E_NOMEM: return "out of memory";
+    case TRI_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+const char *tri_last_error(tri_ctx ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+tri_status tri_create(tri_ctx *out, int device, void *hip_stream)
+{
+    if (!out) return TRI_E_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return TRI_E_HIP;
+    if (device < 0 || device >= count) return TRI_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return TRI_E_HIP;
+    tri_ctx ctx = new (std::nothrow) tri_ctx_s;
+    if (!ctx) return TRI_E_NOMEM;
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipMalloc(&ctx->status_dev, sizeof(int)) != hipSuccess) {
+        delete ctx;
+        return TRI_E_NOMEM;
+    }
+    if (hipMemsetAsync(ctx->status_dev, 0, sizeof(int), ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        (void)hipFree(ctx->status_dev);
+        delete ctx;
+        return TRI_E_HIP;
+    }
+    *out = ctx;
+    return TRI_OK;
+}
+
+tri_status tri_destroy(tri_ctx ctx)
+{
+    if (!ctx) return TRI_E_ARG;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->status_dev) (void)hipFree(ctx->status_dev);
+    delete ctx;
+    return TRI_OK;
+}
+
+tri_status tri_set_stream(tri_ctx ctx, void *hip_stream)
+{
+    if (!ctx) return TRI_E_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return TRI_OK;
+}
+
+tri_status tri_sync_status(tri_ctx ctx)
+{
+    if (!ctx) return TRI_E_ARG;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    int h = 0;
+    HIP_TRY(ctx, hipMemcpy(&h, ctx->status_dev, sizeof(int), hipMemcpyDeviceToHost));
+    HIP_TRY(ctx, hipMemset(ctx->status_dev, 0, sizeof(int)));
+    if (h & kStatusZeroPivot) return fail(ctx, TRI_E_ZERO_PIVOT, "zero pivot reported by a kernel");
+    if (h & kStatusNotConverged) return fail(ctx, TRI_E_NOT_CONVERGED, "refinement did not converge");
+    return TRI_OK;
+}
+
+tri_status tri_pdd_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines, tri_field field,
+                         void *d_inout, int P, int periodic, tri_prec prec, tri_info *info)
+{
+    if (!ctx) return TRI_E_ARG;
+    Problem pb;
+    tri_status st = make_problem(ctx, TRI_PDD, coef, lines, field, d_inout, P, periodic, pb);
+    if (st) return st;
+    return run_problem(ctx, pb, prec, info);
+}
+
+tri_status tri_ppt_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines, tri_field field,
+                         void *d_inout, int P, int periodic, tri_prec prec, tri_info *info)
+{
+    if (!ctx) return TRI_E_ARG;
+    Problem pb;
+    tri_status st = make_problem(ctx, TRI_PPT, coef, lines, field, d_inout, P, periodic, pb);
+    if (st) return st;
+    return run_problem(ctx, pb, prec, info);
+}
+
+tri_status adi_sweep(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t Ny, int64_t Nz,
+                     const double *a, const double *b, const double *c, int P, int periodic,
+                     int method, tri_prec prec, tri_info *info)
+{
+    if (!ctx) return TRI_E_ARG;
+    Problem pb;
+    tri_status st = adi_problem(ctx, dir, u_inout, Nx, Ny, Nz, a, b, c, P, periodic, method, pb);
+    if (st) return st;
+    return run_problem(ctx, pb, prec, info);
+}
+
+tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t Nx, int64_t Ny,
+                                    int64_t Nk, const double *ay, const double *cy,
+                                    const double *lam, int P, tri_prec prec, int fp64_kmax,
+                                    tri_info *info)
+{
+    if (!ctx) return TRI_E_ARG;
+    (void)fp64_kmax;
+    Problem pb;
+    tri_status st = poisson_problem(ctx, phihat_inout, Nx, Ny, Nk, ay, cy, lam, P, pb);
+    if (st) return st;
+    return run_problem(ctx, pb, prec, info);
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Plans
+// ============================================================================
+struct tri_plan_s {
+    tri_ctx ctx = nullptr;
+    tri_prec prec = TRI_F64;
+    struct Item {
+        Problem pb;
+        Tables T;
+        Launch launch;
+        void *mem = nullptr;
+    };
+    std::vector<Item> items;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+tri_status tri_plan_destroy(tri_plan plan)
+{
+    if (!plan) return TRI_E_ARG;
+    (void)hipSetDevice(plan->ctx->device);
+    (void)hipStreamSynchronize(plan->ctx->stream);
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
+    for (auto &it : plan->items)
+        if (it.mem) (void)hipFree(it.mem);
+    delete plan;
+    return TRI_OK;
+}
+
+tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
+                           tri_plan *out)
+{
+    if (!ctx || !out || (n_items > 0 && !items) || n_items < 0) return TRI_E_ARG;
+    *out = nullptr;
+    if (prec != TRI_F64) return fail(ctx, TRI_E_UNSUPPORTED, "precision %d not available in plans", (int)prec);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    tri_plan plan = new (std::nothrow) tri_plan_s;
+    if (!plan) return TRI_E_NOMEM;
+    plan->ctx = ctx;
+    plan->prec = prec;
+    plan->items.resize((size_t)n_items);
+    for (int i = 0; i < n_items; ++i) {
+        const tri_item &it = items[i];
+        tri_plan_s::Item &pi = plan->items[(size_t)i];
+        tri_status st;
+        int P = it.P;
+        if (it.kind == TRI_ITEM_POISSON) {
+            if (P == 0) P = (it.Ny % 4 == 0) ? 4 : ((it.Ny % 2 == 0) ? 2 : 1);
+            st = poisson_problem(ctx, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.c, it.lam, P, pi.pb);
+        } else if (it.kind >= TRI_ITEM_ADI_X && it.kind <= TRI_ITEM_ADI_Z) {
+            const int64_t n = it.kind == TRI_ITEM_ADI_X ? it.Nx : (it.kind == TRI_ITEM_ADI_Y ? it.Ny : it.Nz);
+            if (P == 0) P = (n % 4 == 0 && n / 4 >= 2) ? 4 : ((n % 2 == 0) ? 2 : 1);
+            st = adi_problem(ctx, it.kind - TRI_ITEM_ADI_X, (double *)it.field, it.Nx, it.Ny, it.Nz,
+                             it.a, it.b, it.c, P, it.periodic, it.method, pi.pb);
+        } else {
+            st = fail(ctx, TRI_E_ARG, "item %d: bad kind %d", i, it.kind);
+        }
+        if (st) {
+            tri_plan_destroy(plan);
+            return st;
+        }
+        const Problem &pb = pi.pb;
+        const size_t bytes = tables_bytes(pb.G, pb.L.n, pb.P);
+        if (hipMalloc(&pi.mem, bytes) != hipSuccess) {
+            tri_plan_destroy(plan);
+            return fail(ctx, TRI_E_NOMEM, "plan tables of %zu bytes", bytes);
+        }
+        pi.T = carve_tables(pi.mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+        st = plan_launch(ctx, pb, pi.T, pi.launch);
+        if (st) {
+            tri_plan_destroy(plan);
+            return st;
+        }
+        hipError_t e = launch_factor(pb.src, pi.T, ctx->status_dev, ctx->stream);
+        if (e != hipSuccess) {
+            tri_plan_destroy(plan);
+            return fail(ctx, TRI_E_HIP, "factor launch: %s", hipGetErrorString(e));
+        }
+    }
+    *out = plan;
+    return TRI_OK;
+}
+
+tri_status tri_plan_execute(tri_plan plan)
+{
+    if (!plan) return TRI_E_ARG;
+    tri_ctx ctx = plan->ctx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    for (auto &it : plan->items) HIP_TRY(ctx, run_launch(it.launch, it.pb.method, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status tri_plan_capture(tri_plan plan, void **graph_exec_out)
+{
+    if (!plan) return TRI_E_ARG;
+    tri_ctx ctx = plan->ctx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (!plan->cap_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    if (plan->exec) {
+        (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = nullptr;
+    }
+    if (plan->graph) {
+        (void)hipGraphDestroy(plan->graph);
+        plan->graph = nullptr;
+    }
+    HIP_TRY(ctx, hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (auto &it : plan->items) {
+        e = run_launch(it.launch, it.pb.method, plan->cap_stream);
+        if (e != hipSuccess) break;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(plan->cap_stream, &g);
+    if (e != hipSuccess) return fail(ctx, TRI_E_HIP, "capture launch: %s", hipGetErrorString(e));
+    if (e2 != hipSuccess) return fail(ctx, TRI_E_HIP, "end capture: %s", hipGetErrorString(e2));
+    plan->graph = g;
+    HIP_TRY(ctx, hipGraphInstantiate(&plan->exec, g, nullptr, nullptr, 0));
+    if (graph_exec_out) *graph_exec_out = (void *)plan->exec;
+    return TRI_OK;
+}
+
+tri_status tri_plan_graph_launch(tri_plan plan)
+{
+    if (!plan) return TRI_E_ARG;
+    if (!plan->exec) return fail(plan->ctx, TRI_E_ARG, "plan has no captured graph");
+    HIP_TRY(plan->ctx, hipSetDevice(plan->ctx->device));
+    HIP_TRY(plan->ctx, hipGraphLaunch(plan->exec, plan->ctx->stream));
+    return TRI_OK;
+}
+
+int tri_plan_item_partitions(tri_plan plan, int i)
+{
+    if (!plan || i < 0 || i >= (int)plan->items.size()) return -1;
+    return plan->items[(size_t)i].pb.P;
+}
+
+}  // extern "C"

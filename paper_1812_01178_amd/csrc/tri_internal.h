@@ -1,0 +1,113 @@
+// tri_internal.h -- internal layouts shared by the host API and the HIP
+// kernels of libtri (not installed, not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tri.h"
+
+namespace tri {
+
+constexpr int kPMax = TRI_MAX_PARTITIONS;
+constexpr int kNumFactors = 5;   // beta, alpha, cp, v, w
+
+// ---------------------------------------------------------------------------
+// Factor tables of G shared matrices with n rows split into P partitions.
+//
+// F  [(g*5 + f)*n + J]   row J = r*m + t of matrix g:
+//    f = 0: beta_J  = 1/den_J,  den_J = b_J - a~_J cp_{J-1}   (Thomas pivot)
+//    f = 1: alpha_J = a~_J beta_J                              (forward mult.)
+//    f = 2: cp_J    = c~_J beta_J                              (backward mult.)
+//    f = 3: v_J     spike A~_r^{-1}(a_{rm} e_0)      (Eq. (6), a-corner)
+//    f = 4: w_J     spike A~_r^{-1}(c_{rm+m-1} e_{m-1})  (Eq. (6), c-corner)
+//    where a~, c~ are a, c with each partition's corner couplings removed.
+//    Forward:  g_t = beta_t d_t - alpha_t g_{t-1};  back: x_t = g_t - cp_t x_{t+1}.
+//
+// IT [((g*P + r)*2 + side)*(2P) + q]   reduced-system rows of partition r:
+//    side 0 gives y_left  (the paper's y_{2r-1}, multiplies v^(r)),
+//    side 1 gives y_right (the paper's y_{2r+2}, multiplies w^(r)),
+//    as linear combinations of the tip vector T of the line:
+//    T[2q] = x~ at the first row of partition q, T[2q+1] = x~ at its last row.
+//    PDD: the two nonzeros per side come from one 2x2 interface block.
+//    PPT: a dense row of (pair-swap) * Zbar^{-1}, Zbar^{-1} from GEPP.
+//
+// flags[g]: bit 0 = mode pinned (Poisson lam == 0: row 0 replaced by x_0 = 0,
+//           the right-hand side of row 0 is read as 0).
+// drop[g]:  largest |v_m^(L)|, |w_1^(R)| over the interfaces (entries PDD drops).
+// ---------------------------------------------------------------------------
+struct Tables {
+    double *F = nullptr;
+    double *IT = nullptr;
+    int *flags = nullptr;
+    double *drop = nullptr;
+    int64_t G = 0, n = 0;
+    int P = 0;
+    int periodic = 0;
+    int method = 0;
+};
+
+inline size_t tables_bytes_F(int64_t G, int64_t n) { return sizeof(double) * (size_t)(G * kNumFactors * n); }
+inline size_t tables_bytes_IT(int64_t G, int P) { return sizeof(double) * (size_t)(G * P * 2 * 2 * P); }
+
+// Source of the G matrices for the factor kernel.
+struct MatSrc {
+    const double *a, *b, *c;   // row J of matrix g at J*cs_j + g*cs_g
+    int64_t cs_j, cs_g;
+    const double *lam;         // Poisson mode when non-null: b_J = -(a_J + c_J) - lam[g]
+};
+
+// Lines of a solve, after complex fields are unfolded into real lines
+// (b0' = 2*b0 + component, all strides doubled).
+struct LineSet {
+    double *d;
+    int64_t n, nb0, nb1, s_j, s_b0, s_b1;
+};
+
+struct SolveArgs {
+    double *d;
+    int64_t n;
+    int m, P, periodic;
+    int64_t s_j, nb0, nb1, s_b0, s_b1;
+    int64_t ngroups0;      // strided kernel: ceil(nb0 / 64)
+    int64_t g_b1;          // matrix index = b1 * g_b1 (0: one shared matrix)
+    const double *F;
+    const double *IT;
+    const int *flags;
+    // contiguous kernel
+    int C;                 // rows per lane
+    int Lp;                // lanes per partition (power of two <= 64)
+    int LL;                // lanes per line = P * Lp
+    int LPB;               // lines per block
+    int64_t nlines;        // nb0 * nb1
+};
+
+// Per-line (general) coefficients.
+struct GeneralArgs {
+    double *d;
+    int64_t n;
+    int m, P, periodic, cplx;
+    int64_t s_j, nb0, nb1, s_b0, s_b1;
+    int64_t ngroups0;
+    const double *a, *b, *c;
+    int64_t cs_j, cs_b0, cs_b1;
+    int *status;
+};
+
+// Host launchers (tri_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s);
+hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
+hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s);
+hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
+
+// Largest m the register-resident kernels accept.
+constexpr int kStridedMaxM = 80;
+constexpr int kContigMaxC = 16;
+constexpr int kGeneralMaxM = 32;
+constexpr int kGeneralPPTMaxP = 8;
+
+// Status word bits (device).
+constexpr int kStatusZeroPivot = 1;
+constexpr int kStatusNotConverged = 2;
+
+}  // namespace tri

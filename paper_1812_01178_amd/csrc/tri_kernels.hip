@@ -1,0 +1,763 @@
+// tri_kernels.hip -- gfx950 kernels of libtri (FP64 path).
+//
+// Partitioned tridiagonal solves of Ha, Park & You (arXiv:1812.01178),
+// Sec. 3.2: every line of n rows is split into P partitions; each partition
+// solves its block A~_r (Eqs. (5), (6)); the partitions exchange the first
+// and last entries of x~ ("tips"); the reduced system (PDD: 2x2 blocks of
+// Eq. (7); PPT: Zbar of Eq. (10)) gives the interface unknowns; the
+// correction x = x~ - Y y (Eqs. (8), (11)) is fused into the store.
+//
+// The paper runs one partition per GPU and exchanges tips with MPI; here the
+// partitions of a line live in one workgroup and exchange tips through LDS.
+// The path is HBM-bound (about 1 flop per byte), so the kernels are built
+// around coalesced loads and stores and on-chip residency of each partition
+// between its elimination and its correction; no matrix-core work.
+#include <hip/hip_runtime.h>
+
+#include "tri_internal.h"
+
+namespace tri {
+
+// ===========================================================================
+// Factor kernel: one workgroup per shared matrix g, one thread per partition.
+// Writes the Thomas factors and spikes of every partition block (Eqs. (5),
+// (6) are linear in the right-hand side, so everything except d is done
+// once per matrix) and the reduced-system rows of every partition.
+// ===========================================================================
+struct MatView {
+    MatSrc S;
+    int64_t g;
+    bool pin;
+    __device__ double A(int64_t J) const { return S.a[J * S.cs_j + g * S.cs_g]; }
+    __device__ double Cc(int64_t J) const {
+        if (pin && J == 0) return 0.0;
+        return S.c[J * S.cs_j + g * S.cs_g];
+    }
+    __device__ double B(int64_t J) const {
+        if (S.lam) {
+            if (pin && J == 0) return 1.0;
+            return -(S.a[J * S.cs_j + g * S.cs_g] + S.c[J * S.cs_j + g * S.cs_g]) - S.lam[g];
+        }
+        return S.b[J * S.cs_j + g * S.cs_g];
+    }
+};
+
+// Small dense LU with partial pivoting, K <= 2*kPMax, row-major in LDS.
+constexpr int kKMax = 2 * kPMax;
+
+__global__ __launch_bounds__(64) void k_factor(MatSrc S, Tables T, int *status)
+{
+    __shared__ double Z[kKMax * kKMax];
+    __shared__ double Zi[kKMax * kKMax];
+    __shared__ int piv[kKMax];
+    __shared__ int bad_lu;
+
+    const int64_t g = blockIdx.x;
+    const int P = T.P;
+    const int64_t n = T.n;
+    const int m = (int)(n / P);
+    const int periodic = T.periodic;
+    MatView M{S, g, S.lam != nullptr && S.lam[g] == 0.0};
+    double *F = T.F + g * kNumFactors * n;
+    double *Fb = F, *Fa = F + n, *Fc = F + 2 * n, *Fv = F + 3 * n, *Fw = F + 4 * n;
+    const int tid = threadIdx.x;
+
+    if (tid == 0) {
+        T.flags[g] = M.pin ? 1 : 0;
+        bad_lu = 0;
+    }
+    if (tid < P) {
+        const int r = tid;
+        const int64_t o = (int64_t)r * m;
+        bool bad = false;
+        double cpp = 0.0;
+        for (int t = 0; t < m; ++t) {
+            const int64_t J = o + t;
+            const double aa = (t == 0) ? 0.0 : M.A(J);        // corner removed
+            const double cc = (t == m - 1) ? 0.0 : M.Cc(J);    // corner removed
+            const double den = M.B(J) - aa * cpp;
+            if (!(den != 0.0) || !isfinite(den)) bad = true;
+            const double beta = 1.0 / den;
+            Fb[J] = beta;
+            Fa[J] = aa * beta;
+            cpp = cc * beta;
+            Fc[J] = cpp;
+        }
+        // spike v^(r) = A~_r^{-1} (a_{rm} e_0): only partitions with a left coupling
+        const double a_first = (r >= 1 || periodic) ? M.A(o) : 0.0;
+        double gv = 0.0;
+        for (int t = 0; t < m; ++t) {
+            const int64_t J = o + t;
+            gv = (t == 0) ? Fb[J] * a_first : -Fa[J] * gv;
+            Fv[J] = gv;
+        }
+        double vn = 0.0;
+        for (int t = m - 1; t >= 0; --t) {
+            const int64_t J = o + t;
+            vn = Fv[J] - Fc[J] * vn;
+            Fv[J] = vn;
+        }
+        // spike w^(r) = A~_r^{-1} (c_{rm+m-1} e_{m-1}): only with a right coupling
+        const double c_last = (r <= P - 2 || periodic) ? M.Cc(o + m - 1) : 0.0;
+        double wn = Fb[o + m - 1] * c_last;
+        Fw[o + m - 1] = wn;
+        for (int t = m - 2; t >= 0; --t) {
+            const int64_t J = o + t;
+            wn = -Fc[J] * wn;
+            Fw[J] = wn;
+        }
+        if (bad) atomicOr(status, kStatusZeroPivot);
+    }
+    // zero this matrix's reduced-system rows
+    const int rowlen = 2 * P;
+    double *IT = T.IT + g * (int64_t)P * 2 * rowlen;
+    for (int i = tid; i < P * 2 * rowlen; i += blockDim.x) IT[i] = 0.0;
+    __syncthreads();
+
+    const int NI = periodic ? P : P - 1;
+    const int K = 2 * NI;
+    auto vfirst = [&](int q) { return Fv[(int64_t)q * m]; };
+    auto vlast = [&](int q) { return Fv[(int64_t)q * m + m - 1]; };
+    auto wfirst = [&](int q) { return Fw[(int64_t)q * m]; };
+    auto wlast = [&](int q) { return Fw[(int64_t)q * m + m - 1]; };
+
+    if (tid == 0) {
+        // entries PDD drops from Z: v_m^(L) and w_1^(R) of every interface
+        double dmax = 0.0;
+        for (int i = 1; i <= NI; ++i) {
+            const int L = i - 1, R = i % P;
+            if (L >= 1 || periodic) dmax = fmax(dmax, fabs(vlast(L)));
+            if (R <= P - 2 || periodic) dmax = fmax(dmax, fabs(wfirst(R)));
+        }
+        T.drop[g] = dmax;
+    }
+
+    if (T.method == TRI_PDD) {
+        // 2x2 block of interface i: [[1, w_m^(L)], [v_1^(R), 1]] (y_{2i-1}, y_{2i})
+        //   = (x~_m^(L), x~_1^(R)); inverse of a 2x2 matrix (Algorithm 1, step 5).
+        if (tid < NI) {
+            const int i = tid + 1, L = i - 1, R = i % P;
+            const double w = wlast(L), v = vfirst(R);
+            const double det = 1.0 - w * v;
+            if (!(det != 0.0)) atomicOr(status, kStatusZeroPivot);
+            const double inv = 1.0 / det;
+            // y_{2i-1}: left unknown of partition R
+            double *rowR = IT + ((int64_t)R * 2 + 0) * rowlen;
+            rowR[2 * L + 1] += inv;
+            rowR[2 * R] += -w * inv;
+            // y_{2i}: right unknown of partition L
+            double *rowL = IT + ((int64_t)L * 2 + 1) * rowlen;
+            rowL[2 * R] += inv;
+            rowL[2 * L + 1] += -v * inv;
+        }
+        return;
+    }
+
+    // PPT: Zbar = Z P (Eq. (10)), factor with partial pivoting, invert.
+    if (K == 0) return;
+    if (tid == 0) {
+        for (int t = 0; t < K * K; ++t) Z[t] = 0.0;
+        for (int i = 1; i <= NI; ++i) {
+            const int L = i - 1, R = i % P;
+            const int u1 = 2 * i - 2, u2 = 2 * i - 1;
+            // row of y_{2i-1}; columns already swapped in pairs (Zbar = Z P)
+            Z[u1 * K + (u1 ^ 1)] += 1.0;
+            Z[u1 * K + (u2 ^ 1)] += wlast(L);
+            if (L >= 1 || periodic) {
+                const int il = (L >= 1) ? L : P;
+                Z[u1 * K + ((2 * il - 2) ^ 1)] += vlast(L);
+            }
+            Z[u2 * K + (u2 ^ 1)] += 1.0;
+            Z[u2 * K + (u1 ^ 1)] += vfirst(R);
+            if (R <= P - 2 || periodic) {
+                const int ir = R + 1;
+                Z[u2 * K + ((2 * ir - 1) ^ 1)] += wfirst(R);
+            }
+        }
+        for (int k = 0; k < K; ++k) {
+            int p = k;
+            double best = fabs(Z[k * K + k]);
+            for (int i = k + 1; i < K; ++i)
+                if (fabs(Z[i * K + k]) > best) { best = fabs(Z[i * K + k]); p = i; }
+            piv[k] = p;
+            if (best == 0.0) { bad_lu = 1; break; }
+            if (p != k)
+                for (int t = 0; t < K; ++t) { double s = Z[k * K + t]; Z[k * K + t] = Z[p * K + t]; Z[p * K + t] = s; }
+            for (int i = k + 1; i < K; ++i) {
+                const double l = Z[i * K + k] / Z[k * K + k];
+                Z[i * K + k] = l;
+                for (int t = k + 1; t < K; ++t) Z[i * K + t] -= l * Z[k * K + t];
+            }
+        }
+        if (bad_lu) atomicOr(status, kStatusZeroPivot);
+    }
+    __syncthreads();
+    if (bad_lu) return;
+    if (tid < K) {
+        // column tid of Zbar^{-1}
+        double col[kKMax];
+        for (int i = 0; i < K; ++i) col[i] = (i == tid) ? 1.0 : 0.0;
+        // rows were interchanged whole (multipliers included), so the stored L
+        // belongs to the fully permuted matrix: permute first, then substitute
+        for (int k = 0; k < K; ++k) {
+            const int p = piv[k];
+            if (p != k) { double s = col[k]; col[k] = col[p]; col[p] = s; }
+        }
+        for (int k = 0; k < K; ++k)
+            for (int i = k + 1; i < K; ++i) col[i] -= Z[i * K + k] * col[k];
+        for (int k = K - 1; k >= 0; --k) {
+            double s = col[k];
+            for (int t = k + 1; t < K; ++t) s -= Z[k * K + t] * col[t];
+            col[k] = s / Z[k * K + k];
+        }
+        for (int i = 0; i < K; ++i) Zi[i * K + tid] = col[i];
+    }
+    __syncthreads();
+    if (tid < P) {
+        const int r = tid;
+        // E^T x~ entry u in terms of the tip vector T: u = 2i-2 -> last of L(i),
+        // u = 2i-1 -> first of R(i).
+        auto tipidx = [&](int u) {
+            const int i = u / 2 + 1;
+            return (u & 1) ? 2 * (i % P) : 2 * (i - 1) + 1;
+        };
+        if (r >= 1 || periodic) {
+            const int il = (r >= 1) ? r : P;
+            const int row = 2 * il - 1;              // y_{2il-1} = ybar_{2il}
+            double *dst = IT + ((int64_t)r * 2 + 0) * rowlen;
+            for (int u = 0; u < K; ++u) dst[tipidx(u)] += Zi[row * K + u];
+        }
+        if (r <= P - 2 || periodic) {
+            const int row = 2 * r;                   // y_{2r+2} = ybar_{2r+1}
+            double *dst = IT + ((int64_t)r * 2 + 1) * rowlen;
+            for (int u = 0; u < K; ++u) dst[tipidx(u)] += Zi[row * K + u];
+        }
+    }
+}
+
+hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s)
+{
+    if (T.G <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_factor, dim3((unsigned)T.G), dim3(64), 0, s, src, T, status);
+    return hipGetLastError();
+}
+
+// ===========================================================================
+// Reduced-system evaluation shared by the solve kernels: the left and right
+// interface unknowns of partition r from the tips of its line.
+// tip(q): q = 2*partition (first row) or 2*partition + 1 (last row).
+// ===========================================================================
+template <int METHOD, typename TipFn>
+__device__ __forceinline__ void interface_unknowns(const double *__restrict__ it, int r, int P,
+                                                   int periodic, TipFn tip, double &yl, double &yr)
+{
+    yl = 0.0;
+    yr = 0.0;
+    const bool has_l = (r > 0) || periodic;
+    const bool has_r = (r < P - 1) || periodic;
+    const int rowlen = 2 * P;
+    if (METHOD == TRI_PDD) {
+        if (has_l) {
+            const int L = (r > 0) ? r - 1 : P - 1;
+            yl = it[2 * L + 1] * tip(2 * L + 1) + it[2 * r] * tip(2 * r);
+        }
+        if (has_r) {
+            const int R = (r < P - 1) ? r + 1 : 0;
+            yr = it[rowlen + 2 * R] * tip(2 * R) + it[rowlen + 2 * r + 1] * tip(2 * r + 1);
+        }
+    } else {
+        const int q0 = periodic ? 0 : 1;
+        const int q1 = periodic ? rowlen : rowlen - 1;
+        if (has_l)
+            for (int q = q0; q < q1; ++q) yl += it[q] * tip(q);
+        if (has_r)
+            for (int q = q0; q < q1; ++q) yr += it[rowlen + q] * tip(q);
+    }
+}
+
+// ===========================================================================
+// Strided-direction solve (rows j at stride s_j, lines side by side).
+// Workgroup = P wavefronts; wavefront r holds partition r of 64 neighbouring
+// lines (lane = line), so every row access of a wavefront is one coalesced
+// 512-byte segment and every factor is wavefront-uniform (scalar loads).
+// The m values of each partition stay in VGPRs from load to store.
+// ===========================================================================
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 32 ? 512 : 1024) k_strided(const SolveArgs A)
+{
+    extern __shared__ double tips[];            // [2P][64]
+    const int lane = threadIdx.x & 63;
+    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t blk = blockIdx.x;
+    const int64_t grp = blk % A.ngroups0;
+    const int64_t b1 = blk / A.ngroups0;
+    const int64_t b0 = grp * 64 + lane;
+    const bool active = b0 < A.nb0;
+    const int m = A.m, P = A.P;
+    const int64_t n = A.n;
+    const int64_t g = b1 * A.g_b1;
+    const double *__restrict__ F = A.F + g * (kNumFactors * n) + (int64_t)r * m;
+    const double *__restrict__ Fb = F;
+    const double *__restrict__ Fa = F + n;
+    const double *__restrict__ Fc = F + 2 * n;
+    const double *__restrict__ Fv = F + 3 * n;
+    const double *__restrict__ Fw = F + 4 * n;
+    const int64_t sj = A.s_j;
+    double *__restrict__ p = A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + (int64_t)r * m * sj;
+
+    double x[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) x[t] = 0.0;
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < m) x[t] = p[t * sj];
+    }
+    if (r == 0 && (A.flags[g] & 1)) x[0] = 0.0;   // gauge-pinned row
+
+    // Eq. (5): A~_r x~ = d with the precomputed pivots
+    double gp = 0.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < m) {
+            gp = Fb[t] * x[t] - Fa[t] * gp;
+            x[t] = gp;
+        }
+    const double tip_last = gp;
+    double xn = 0.0;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+        if (t < m) {
+            xn = x[t] - Fc[t] * xn;
+            x[t] = xn;
+        }
+    const double tip_first = x[0];
+
+    // exchange the tips of the P partitions (the paper's SENDRECV / ALLGATHER)
+    tips[(2 * r) * 64 + lane] = tip_first;
+    tips[(2 * r + 1) * 64 + lane] = tip_last;
+    __syncthreads();
+
+    const double *__restrict__ it = A.IT + ((g * P + r) * 2) * (2 * P);
+    double yl, yr;
+    interface_unknowns<METHOD>(it, r, P, A.periodic,
+                               [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
+
+    // Eq. (8) / (11): x = x~ - y_left v^(r) - y_right w^(r), fused with the store
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < m) p[t * sj] = x[t] - yl * Fv[t] - yr * Fw[t];
+    }
+}
+
+template <int CMAX, int METHOD>
+static hipError_t launch_strided_t(const SolveArgs &a, hipStream_t s)
+{
+    const int64_t blocks = a.ngroups0 * a.nb1;
+    const size_t lds = sizeof(double) * 2 * a.P * 64;
+    hipLaunchKernelGGL((k_strided<CMAX, METHOD>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int METHOD>
+static hipError_t launch_strided_m(const SolveArgs &a, int cmax, hipStream_t s)
+{
+    switch (cmax) {
+    case 8: return launch_strided_t<8, METHOD>(a, s);
+    case 16: return launch_strided_t<16, METHOD>(a, s);
+    case 24: return launch_strided_t<24, METHOD>(a, s);
+    case 32: return launch_strided_t<32, METHOD>(a, s);
+    case 48: return launch_strided_t<48, METHOD>(a, s);
+    case 64: return launch_strided_t<64, METHOD>(a, s);
+    case 80: return launch_strided_t<80, METHOD>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s)
+{
+    return method == TRI_PDD ? launch_strided_m<TRI_PDD>(a, chunk_max, s)
+                             : launch_strided_m<TRI_PPT>(a, chunk_max, s);
+}
+
+// ===========================================================================
+// Contiguous-direction solve (rows contiguous, s_j = 1).
+// A partition of m rows is spread over Lp lanes (Lp a power of two dividing
+// 64) of C consecutive rows each.  The forward and backward Thomas sweeps of
+// the partition are affine first-order recurrences, so each lane runs its C
+// rows with a zero carry, the carries are combined by a segmented
+// Kogge-Stone scan over the Lp lanes with cross-lane shuffles, and each lane
+// re-runs its rows with the true carry.  The result is the partition's
+// Thomas solution; the tips go through LDS to the other partitions.
+// ===========================================================================
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 8 ? 256 : 1024) k_contig(const SolveArgs A)
+{
+    extern __shared__ double lds[];             // [LPB][2P] tips
+    const int tid = threadIdx.x;
+    const int LL = A.LL, Lp = A.Lp, C = A.C, m = A.m, P = A.P;
+    const int li = tid / LL;
+    const int lt = tid - li * LL;
+    const int r = lt / Lp;
+    const int k = lt - r * Lp;
+    const bool inblk = li < A.LPB;
+    const int64_t L = (int64_t)blockIdx.x * A.LPB + li;
+    const bool active = inblk && L < A.nlines;
+    const int64_t b0 = active ? L % A.nb0 : 0;
+    const int64_t b1 = active ? L / A.nb0 : 0;
+    const int64_t g = b1 * A.g_b1;
+    const int64_t n = A.n;
+    const int row0 = k * C;
+    const int64_t J0 = (int64_t)(inblk ? r : 0) * m + row0;
+    const double *__restrict__ F = A.F + g * (kNumFactors * n) + J0;
+    double *__restrict__ p = A.d + b0 * A.s_b0 + b1 * A.s_b1 + J0;
+
+    double x[CMAX], fb[CMAX], fa[CMAX], fc[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+        const bool valid = inblk && (t < C) && (row0 + t < m);
+        x[t] = (valid && active) ? p[t] : 0.0;
+        fb[t] = valid ? F[t] : 0.0;
+        fa[t] = valid ? F[n + t] : 0.0;
+        fc[t] = valid ? F[2 * n + t] : 0.0;
+    }
+    if (active && r == 0 && k == 0 && (A.flags[g] & 1)) x[0] = 0.0;
+
+    // forward sweep, zero carry: chunk map g_out = Fs + Ps * g_in
+    double gp = 0.0, ps = 1.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < C) {
+            gp = fb[t] * x[t] - fa[t] * gp;
+            ps *= -fa[t];
+        }
+    double Fs = gp, Ps = ps;
+    for (int s = 1; s < Lp; s <<= 1) {
+        const double Fo = __shfl_up(Fs, s, Lp);
+        const double Po = __shfl_up(Ps, s, Lp);
+        if (k >= s) {
+            Fs = Fs + Ps * Fo;
+            Ps = Ps * Po;
+        }
+    }
+    double gin = __shfl_up(Fs, 1, Lp);
+    if (k == 0) gin = 0.0;
+    gp = gin;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < C) {
+            gp = fb[t] * x[t] - fa[t] * gp;
+            x[t] = gp;
+        }
+    const int kl = (m - 1) / C, tl = (m - 1) - kl * C;
+    double tip_last = 0.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t == tl) tip_last = x[t];
+
+    // backward sweep, zero carry: chunk map x_first = Bs + Ss * x_after
+    double xn = 0.0, ss = 1.0;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+        if (t < C) {
+            xn = x[t] - fc[t] * xn;
+            ss *= -fc[t];
+        }
+    double Bs = xn, Ss = ss;
+    for (int s = 1; s < Lp; s <<= 1) {
+        const double Bo = __shfl_down(Bs, s, Lp);
+        const double So = __shfl_down(Ss, s, Lp);
+        if (k + s < Lp) {
+            Bs = Bs + Ss * Bo;
+            Ss = Ss * So;
+        }
+    }
+    double xin = __shfl_down(Bs, 1, Lp);
+    if (k == Lp - 1) xin = 0.0;
+    xn = xin;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+        if (t < C) {
+            xn = x[t] - fc[t] * xn;
+            x[t] = xn;
+        }
+
+    double *tips = lds + (inblk ? li : 0) * 2 * P;
+    if (inblk && k == 0) tips[2 * r] = x[0];
+    if (inblk && k == kl) tips[2 * r + 1] = tip_last;
+    __syncthreads();
+
+    const double *__restrict__ it = A.IT + ((g * P + r) * 2) * (2 * P);
+    double yl = 0.0, yr = 0.0;
+    if (inblk)
+        interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q]; }, yl, yr);
+
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < C && row0 + t < m) p[t] = x[t] - yl * F[3 * n + t] - yr * F[4 * n + t];
+    }
+}
+
+template <int CMAX, int METHOD>
+static hipError_t launch_contig_t(const SolveArgs &a, hipStream_t s)
+{
+    const int64_t blocks = (a.nlines + a.LPB - 1) / a.LPB;
+    int threads = a.LPB * a.LL;
+    threads = ((threads + 63) / 64) * 64;
+    const size_t lds = sizeof(double) * 2 * a.P * a.LPB;
+    hipLaunchKernelGGL((k_contig<CMAX, METHOD>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s)
+{
+    if (a.C <= 4)
+        return method == TRI_PDD ? launch_contig_t<4, TRI_PDD>(a, s) : launch_contig_t<4, TRI_PPT>(a, s);
+    if (a.C <= 8)
+        return method == TRI_PDD ? launch_contig_t<8, TRI_PDD>(a, s) : launch_contig_t<8, TRI_PPT>(a, s);
+    if (a.C <= 16)
+        return method == TRI_PDD ? launch_contig_t<16, TRI_PDD>(a, s) : launch_contig_t<16, TRI_PPT>(a, s);
+    return hipErrorInvalidValue;
+}
+
+// ===========================================================================
+// General kernel: coefficients per line.  Same layout as the strided kernel
+// (wavefront = partition, lane = line); every lane factors its own block,
+// carrying the right-hand side and the a-corner spike through one forward
+// elimination (the paper batches Eq. (6) with Eq. (5) the same way), and
+// keeps x~, the forward-reduced spike and the pivots in VGPRs.
+// ===========================================================================
+constexpr int kGenKMax = 2 * kPMax;        // banded reduced system (non-periodic)
+constexpr int kGenKDense = 8;              // dense reduced system (periodic, P <= 4)
+
+// Tridiagonal Gaussian elimination with partial pivoting (row interchanges
+// between neighbours, one extra superdiagonal of fill), K <= kGenKMax.
+// dl[k]: entry (k+1, k), dd[k]: (k, k), du[k]: (k, k+1).  rhs -> solution.
+__device__ static bool gtsv_pivot(int K, double *dl, double *dd, double *du, double *rhs)
+{
+    double du2[kGenKMax];
+    for (int k = 0; k < K - 1; ++k) {
+        if (fabs(dd[k]) >= fabs(dl[k])) {
+            if (dd[k] == 0.0) return false;
+            const double l = dl[k] / dd[k];
+            dd[k + 1] -= l * du[k];
+            rhs[k + 1] -= l * rhs[k];
+            du2[k] = 0.0;
+        } else {
+            const double l = dd[k] / dl[k];
+            const double old_ddk1 = dd[k + 1];
+            dd[k] = dl[k];
+            dd[k + 1] = du[k] - l * old_ddk1;
+            du[k] = old_ddk1;
+            if (k < K - 2) {
+                du2[k] = du[k + 1];
+                du[k + 1] = -l * du2[k];
+            } else {
+                du2[k] = 0.0;
+            }
+            const double rk = rhs[k];
+            rhs[k] = rhs[k + 1];
+            rhs[k + 1] = rk - l * rhs[k];
+        }
+    }
+    if (dd[K - 1] == 0.0) return false;
+    rhs[K - 1] /= dd[K - 1];
+    if (K >= 2) rhs[K - 2] = (rhs[K - 2] - du[K - 2] * rhs[K - 1]) / dd[K - 2];
+    for (int k = K - 3; k >= 0; --k)
+        rhs[k] = (rhs[k] - du[k] * rhs[k + 1] - du2[k] * rhs[k + 2]) / dd[k];
+    return true;
+}
+
+// Dense Gaussian elimination with partial pivoting, K <= kGenKDense.
+__device__ static bool dense_gepp(int K, double *M, double *rhs)
+{
+    for (int k = 0; k < K; ++k) {
+        int p = k;
+        double best = fabs(M[k * kGenKDense + k]);
+        for (int i = k + 1; i < K; ++i)
+            if (fabs(M[i * kGenKDense + k]) > best) { best = fabs(M[i * kGenKDense + k]); p = i; }
+        if (best == 0.0) return false;
+        if (p != k) {
+            for (int t = k; t < K; ++t) {
+                const double s = M[k * kGenKDense + t];
+                M[k * kGenKDense + t] = M[p * kGenKDense + t];
+                M[p * kGenKDense + t] = s;
+            }
+            const double s = rhs[k]; rhs[k] = rhs[p]; rhs[p] = s;
+        }
+        for (int i = k + 1; i < K; ++i) {
+            const double l = M[i * kGenKDense + k] / M[k * kGenKDense + k];
+            for (int t = k + 1; t < K; ++t) M[i * kGenKDense + t] -= l * M[k * kGenKDense + t];
+            rhs[i] -= l * rhs[k];
+        }
+    }
+    for (int k = K - 1; k >= 0; --k) {
+        double s = rhs[k];
+        for (int t = k + 1; t < K; ++t) s -= M[k * kGenKDense + t] * rhs[t];
+        rhs[k] = s / M[k * kGenKDense + k];
+    }
+    return true;
+}
+
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const GeneralArgs A)
+{
+    extern __shared__ double sh[];              // [6][P][64]
+    const int lane = threadIdx.x & 63;
+    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t blk = blockIdx.x;
+    const int64_t grp = blk % A.ngroups0;
+    const int64_t b1 = blk / A.ngroups0;
+    const int64_t b0raw = grp * 64 + lane;
+    const bool active = b0raw < A.nb0;
+    const int64_t b0 = active ? b0raw : 0;
+    const int m = A.m, P = A.P, periodic = A.periodic;
+    const int64_t sj = A.s_j, csj = A.cs_j;
+    double *__restrict__ p = A.d + b0 * A.s_b0 + b1 * A.s_b1 + (int64_t)r * m * sj;
+    const int64_t cb = (b0 >> A.cplx) * A.cs_b0 + b1 * A.cs_b1 + (int64_t)r * m * csj;
+    const double *__restrict__ ca = A.a + cb;
+    const double *__restrict__ cbp = A.b + cb;
+    const double *__restrict__ cc = A.c + cb;
+
+    double x[CMAX], gv[CMAX], cp[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) { x[t] = 0.0; gv[t] = 0.0; cp[t] = 0.0; }
+    if (active) {
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < m) x[t] = p[t * sj];
+    }
+    const double a_first = (r >= 1 || periodic) ? ca[0] : 0.0;
+    const double c_last = (r <= P - 2 || periodic) ? cc[(int64_t)(m - 1) * csj] : 0.0;
+    double cpp = 0.0, gx = 0.0, gvp = 0.0, beta_last = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < m) {
+            const double aa = (t == 0) ? 0.0 : ca[t * csj];
+            const double ccv = (t == m - 1) ? 0.0 : cc[t * csj];
+            const double den = cbp[t * csj] - aa * cpp;
+            bad |= !(den != 0.0);
+            const double beta = 1.0 / den;
+            gx = (x[t] - aa * gx) * beta;
+            x[t] = gx;
+            gvp = (t == 0) ? a_first * beta : -(aa * beta) * gvp;
+            gv[t] = gvp;
+            cpp = ccv * beta;
+            cp[t] = cpp;
+            beta_last = beta;
+        }
+    if (bad && active) atomicOr(A.status, kStatusZeroPivot);
+    const double xl = gx, vm = gvp;
+    double xn = 0.0, vn = 0.0, cprod = 1.0;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+        if (t < m) {
+            xn = x[t] - cp[t] * xn;
+            x[t] = xn;
+            vn = gv[t] - cp[t] * vn;
+            if (t < m - 1) cprod *= -cp[t];
+        }
+    const double xf = x[0], v0 = vn;
+    const double wm = beta_last * c_last, w0 = wm * cprod;
+
+    auto S = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * 64 + lane]; };
+    S(0, r) = xf; S(1, r) = xl; S(2, r) = v0; S(3, r) = vm; S(4, r) = w0; S(5, r) = wm;
+    __syncthreads();
+
+    double yl = 0.0, yr = 0.0;
+    const bool has_l = (r > 0) || periodic, has_r = (r < P - 1) || periodic;
+    if (METHOD == TRI_PDD) {
+        if (has_l) {
+            const int L = (r > 0) ? r - 1 : P - 1;
+            const double det = 1.0 - S(5, L) * v0;
+            yl = (S(1, L) - S(5, L) * xf) / det;
+        }
+        if (has_r) {
+            const int R = (r < P - 1) ? r + 1 : 0;
+            const double det = 1.0 - wm * S(2, R);
+            yr = (S(0, R) - S(2, R) * xl) / det;
+        }
+    } else {
+        // Zbar (Eq. (10)) of this lane's line: row 2i-1 = [v_m^(L), w_m^(L), 1],
+        // row 2i = [1, v_1^(R), w_1^(R)] around the diagonal; cyclic if periodic.
+        const int NI = periodic ? P : P - 1, K = 2 * NI;
+        double rhs[kGenKMax];
+        bool ok = true;
+        if (!periodic) {
+            double dl[kGenKMax], dd[kGenKMax], du[kGenKMax];
+            for (int i = 1; i <= NI; ++i) {
+                const int Li = i - 1, Ri = i;
+                const int u1 = 2 * i - 2, u2 = 2 * i - 1;
+                if (u1 > 0) dl[u1 - 1] = S(3, Li);   // v_m^(L) (zero for L = 0)
+                dd[u1] = S(5, Li);                    // w_m^(L)
+                du[u1] = 1.0;
+                dl[u1] = 1.0;
+                dd[u2] = S(2, Ri);                    // v_1^(R)
+                if (u2 < K - 1) du[u2] = S(4, Ri);    // w_1^(R)
+                rhs[u1] = S(1, Li);
+                rhs[u2] = S(0, Ri);
+            }
+            if (K > 0) ok = gtsv_pivot(K, dl, dd, du, rhs);
+        } else {
+            double Zm[kGenKDense * kGenKDense];
+            for (int t = 0; t < K * kGenKDense; ++t) Zm[t] = 0.0;
+            for (int i = 1; i <= NI; ++i) {
+                const int Li = i - 1, Ri = i % P;
+                const int u1 = 2 * i - 2, u2 = 2 * i - 1;
+                const int il = (Li >= 1) ? Li : P, ir = Ri + 1;
+                Zm[u1 * kGenKDense + (u1 ^ 1)] += 1.0;
+                Zm[u1 * kGenKDense + (u2 ^ 1)] += S(5, Li);
+                Zm[u1 * kGenKDense + ((2 * il - 2) ^ 1)] += S(3, Li);
+                Zm[u2 * kGenKDense + (u2 ^ 1)] += 1.0;
+                Zm[u2 * kGenKDense + (u1 ^ 1)] += S(2, Ri);
+                Zm[u2 * kGenKDense + ((2 * ir - 1) ^ 1)] += S(4, Ri);
+                rhs[u1] = S(1, Li);
+                rhs[u2] = S(0, Ri);
+            }
+            ok = dense_gepp(K, Zm, rhs);
+        }
+        if (!ok && active) atomicOr(A.status, kStatusZeroPivot);
+        if (has_l) {
+            const int il = (r >= 1) ? r : P;
+            yl = rhs[2 * il - 1];
+        }
+        if (has_r) yr = rhs[2 * r];
+    }
+
+    // x = x~ - (y_left v + y_right w), with v + w reduced by the same pivots
+    if (active) {
+        double dn = 0.0;
+#pragma unroll
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < m) {
+                const double gd = yl * gv[t] + ((t == m - 1) ? yr * wm : 0.0);
+                dn = gd - cp[t] * dn;
+                p[t * sj] = x[t] - dn;
+            }
+    }
+}
+
+template <int CMAX, int METHOD>
+static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
+{
+    const int64_t blocks = a.ngroups0 * a.nb1;
+    const size_t lds = sizeof(double) * 6 * a.P * 64;
+    hipLaunchKernelGGL((k_general<CMAX, METHOD>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s)
+{
+    if (a.m <= 8)
+        return method == TRI_PDD ? launch_general_t<8, TRI_PDD>(a, s) : launch_general_t<8, TRI_PPT>(a, s);
+    if (a.m <= 16)
+        return method == TRI_PDD ? launch_general_t<16, TRI_PDD>(a, s) : launch_general_t<16, TRI_PPT>(a, s);
+    if (a.m <= 32)
+        return method == TRI_PDD ? launch_general_t<32, TRI_PDD>(a, s) : launch_general_t<32, TRI_PPT>(a, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tri
