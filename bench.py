@@ -107,6 +107,7 @@ def main():
             it = dict(kind=direction, field=u, Nx=nx, Ny=ny, Nz=nz, a=a, b=b, c=c, P=P,
                       periodic=int(per), method=T.TRI_PDD if meth == "PDD" else T.TRI_PPT)
         plans[name] = T.tri_plan_create(ctx, [it])
+        log(f"plan {name}: {T.tri_plan_item_describe(plans[name], 0)}")
     T.tri_sync_status(ctx)
 
     unknowns = {"adi_x": nx * ny * nz, "adi_y": nx * ny * nz, "adi_z": nx * ny * nz,
@@ -220,7 +221,8 @@ def main():
                    "Nx": nx, "Ny": ny, "Nz": nz, "Nk": nk,
                    "P": {n: it[2] for n, it in zip(names, ITEMS)},
                    "method": {n: it[4] for n, it in zip(names, ITEMS)},
-                   "unknowns_per_step": total_unknowns},
+                   "unknowns_per_step": total_unknowns,
+                   "launch": {n: T.tri_plan_item_describe(plans[n], 0) for n in names}},
         "hbm_frac_step": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "step_ms_events": step_ms_events,
         "kernels": kernels,

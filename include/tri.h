@@ -187,7 +187,11 @@ typedef struct {
 
 /* Validate the items, allocate the plan's device tables, factor every
  * matrix (partition factors, spikes, reduced-system inverses) and choose
- * the launch shapes.  All allocation happens here. */
+ * the launch shapes.  All allocation happens here.  Unless the environment
+ * sets TRI_AUTOTUNE=0, each item's launch shape (rows per wavefront chunk,
+ * rows per lane) is chosen by timing the candidates on a scratch copy of the
+ * item's layout (never on the caller's data); TRI_AUTOTUNE_CACHE=<file>
+ * keeps the choices across processes.  Synchronises the context stream. */
 tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
                            tri_plan *out);
 /* Queue every item's solve on the context stream (no allocation, no host
@@ -200,6 +204,10 @@ tri_status tri_plan_capture(tri_plan plan, void **graph_exec_out);
 tri_status tri_plan_graph_launch(tri_plan plan);
 /* Partition count the plan uses for item i (after tuning), or -1. */
 int tri_plan_item_partitions(tri_plan plan, int i);
+/* Human-readable launch shape of item i (kernel, chunking, tuned value)
+ * written to buf (at most len bytes, NUL-terminated); returns the length
+ * the full text needs, or -1 on a bad argument. */
+int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len);
 tri_status tri_plan_destroy(tri_plan plan);
 
 #ifdef __cplusplus

@@ -22,7 +22,7 @@ __all__ = [
     "TriError", "lib", "tri_create", "tri_destroy", "tri_set_stream", "tri_sync_status",
     "tri_status_string", "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep",
     "poisson_wavenumber_solve", "tri_plan_create", "tri_plan_execute", "tri_plan_capture",
-    "tri_plan_graph_launch", "tri_plan_item_partitions", "tri_plan_destroy",
+    "tri_plan_graph_launch", "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy",
     "TriLines", "TriCoef", "TriInfo", "TriItem", "EXPORTED",
     "TRI_F64", "TRI_F32_REFINE", "TRI_REAL", "TRI_COMPLEX", "TRI_PDD", "TRI_PPT",
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
@@ -45,7 +45,7 @@ EXPORTED = [
     "tri_create", "tri_destroy", "tri_set_stream", "tri_sync_status", "tri_status_string",
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
-    "tri_plan_item_partitions", "tri_plan_destroy",
+    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy",
 ]
 
 
@@ -115,6 +115,7 @@ def lib():
         "tri_plan_capture": (_I, [_V, ctypes.POINTER(_V)]),
         "tri_plan_graph_launch": (_I, [_V]),
         "tri_plan_item_partitions": (_I, [_V, _I]),
+        "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
         "tri_plan_destroy": (_I, [_V]),
     }
     for name, (res, args) in sig.items():
@@ -264,6 +265,13 @@ def tri_plan_graph_launch(plan) -> None:
 
 def tri_plan_item_partitions(plan, i: int) -> int:
     return int(lib().tri_plan_item_partitions(plan, int(i)))
+
+
+def tri_plan_item_describe(plan, i: int) -> str:
+    buf = ctypes.create_string_buffer(256)
+    if lib().tri_plan_item_describe(plan, int(i), buf, 256) < 0:
+        raise TriError(TRI_E_ARG, "tri_plan_item_describe")
+    return buf.value.decode()
 
 
 def tri_plan_destroy(plan) -> None:

@@ -6,7 +6,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -62,10 +65,39 @@ struct Problem {
 
 // Kernel choice for a shared-matrix problem.
 struct Launch {
-    int kind = 0;          // 0 strided, 1 contiguous
+    int kind = 0;          // 0 strided, 1 contiguous, 2 contiguous staged (persistent)
     int chunk_max = 0;     // strided: CMAX instance
+    int grid = 0;          // staged: persistent grid
     SolveArgs args{};
 };
+
+// Lanes per partition and rows per lane for the staged contiguous kernel:
+// C = m / Lp even, Lp a power of two <= 64 dividing m, C as close to 8 as
+// allowed (<= 16).  Returns false if m has no such split.
+bool staged_split(int m, int &Lp, int &C, int want_c = 0)
+{
+    for (int l = 1; l <= 64; l <<= 1)
+        if (want_c > 0 && m % l == 0 && m / l == want_c && want_c % 2 == 0 && want_c <= 16) {
+            Lp = l;
+            C = want_c;
+            return true;
+        }
+    if (want_c > 0) return false;
+    for (int cap : {8, 16})
+        for (int l = 1; l <= 64; l <<= 1)
+            if (m % l == 0 && (m / l) % 2 == 0 && m / l <= cap) {
+                Lp = l;
+                C = m / l;
+                return true;
+            }
+    return false;
+}
+
+int env_int(const char *name, int dflt)
+{
+    const char *v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
+}
 
 tri_status check_partition(tri_ctx ctx, int64_t n, int P, int periodic)
 {
@@ -81,16 +113,40 @@ tri_status check_partition(tri_ctx ctx, int64_t n, int P, int periodic)
     return TRI_OK;
 }
 
-int pick_chunk(int m)
+int pick_chunk(int c)
 {
-    static const int inst[] = {8, 16, 24, 32, 48, 64, 80};
-    for (int c : inst)
-        if (m <= c) return c;
+    static const int inst[] = {8, 16, 24, 32, 40, 48, 56, 64, 72, 80};
+    for (int v : inst)
+        if (c <= v) return v;
     return 0;
 }
 
-tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out)
+// Chunks per partition for the strided kernel: kc divides m, P*kc <= 16
+// wavefronts, m/kc <= 80 rows per wavefront (<= 40 when P*kc > 8).  With
+// want_kc > 0 that value is used if valid; otherwise the smallest kc giving
+// chunks of at most 40 rows (enough occupancy to saturate HBM), else the
+// smallest valid kc.  Returns 0 if none.
+int pick_kc(int m, int P, int want_kc)
 {
+    auto valid = [&](int kc) {
+        if (kc < 1 || m % kc != 0 || P * kc > 16) return false;
+        const int c = m / kc;
+        return c <= kStridedMaxC && (c <= 40 || P * kc <= 8);
+    };
+    if (want_kc > 0) return valid(want_kc) ? want_kc : 0;
+    for (int kc = 1; kc <= 16; ++kc)
+        if (valid(kc) && m / kc <= 40) return kc;
+    for (int kc = 1; kc <= 16; ++kc)
+        if (valid(kc)) return kc;
+    return 0;
+}
+
+// want: forced tuning value (strided: chunks per partition; contiguous:
+// rows per lane), 0 = heuristic.  TRI_FORCE_KC / TRI_FORCE_C override it.
+tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out, int want = 0)
+{
+    const int want_kc = want ? want : env_int("TRI_FORCE_KC", 0);
+    const int want_c = want ? want : env_int("TRI_FORCE_C", 0);
     const int64_t n = pb.L.n;
     const int P = pb.P;
     const int m = (int)(n / P);
@@ -110,6 +166,30 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
     a.IT = T.IT;
     a.flags = T.flags;
     a.nlines = pb.L.nb0 * pb.L.nb1;
+    int sLp = 0, sC = 0;
+    const bool aligned = ((uintptr_t)pb.L.d % 16 == 0) && pb.L.s_b0 % 2 == 0 &&
+                         (pb.L.nb1 == 1 || pb.L.s_b1 % 2 == 0);
+    if (pb.L.s_j == 1 && n > 1 && pb.g_b1 == 0 && n % 2 == 0 && aligned && staged_split(m, sLp, sC, want_c) &&
+        P * sLp <= 1024) {
+        // contiguous rows, one shared matrix: persistent LDS-staged kernel;
+        // as many lines per workgroup as fit in 1024 lanes and ~150 KB of LDS
+        a.C = sC;
+        a.Lp = sLp;
+        a.LL = P * sLp;
+        for (a.LPB = std::max(1, 1024 / a.LL); a.LPB >= 1; --a.LPB) {
+            const int NT = a.LPB * a.LL;
+            a.stage_stride = NT * 2 + ((8 - (NT * 2) % 32) + 32) % 32;
+            if (contig_staged_lds_bytes(a) <= 150 * 1024) break;
+        }
+        if (a.LPB >= 1) {
+            a.lines_linear = (pb.L.nb1 == 1 || pb.L.s_b1 == pb.L.nb0 * pb.L.s_b0) ? 1 : 0;
+            out.kind = 2;
+            out.args = a;
+            out.grid = contig_staged_grid(a, pb.method);
+            if (out.grid <= 0) return fail(ctx, TRI_E_HIP, "occupancy query for the contiguous kernel failed");
+            return TRI_OK;
+        }
+    }
     if (pb.L.s_j == 1 && n > 1) {
         // contiguous rows: lanes own C consecutive rows, Lp lanes per partition
         int Lp = 1;
@@ -127,11 +207,12 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
         a.LPB = std::max(1, 256 / LL);
         out.kind = 1;
     } else {
-        const int cmax = pick_chunk(m);
-        if (cmax == 0)
-            return fail(ctx, TRI_E_UNSUPPORTED, "strided lines with m = n/P = %d > %d", m, kStridedMaxM);
-        if (cmax > 32 && P > 8)
-            return fail(ctx, TRI_E_UNSUPPORTED, "strided lines with m = %d > 32 need P <= 8", m);
+        const int kc = pick_kc(m, P, want_kc);
+        if (kc == 0)
+            return fail(ctx, TRI_E_UNSUPPORTED, "strided lines: no chunking of m = %d rows over P = %d partitions", m, P);
+        a.kc = kc;
+        a.Cs = m / kc;
+        const int cmax = pick_chunk(a.Cs);
         a.ngroups0 = (pb.L.nb0 + 63) / 64;
         out.kind = 0;
         out.chunk_max = cmax;
@@ -143,6 +224,7 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
 hipError_t run_launch(const Launch &l, int method, hipStream_t s)
 {
     if (l.args.nlines == 0) return hipSuccess;
+    if (l.kind == 2) return launch_contig_staged(l.args, method, l.grid, s);
     return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
 }
 
@@ -462,6 +544,126 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
 }  // extern "C"
 
 // ============================================================================
+// Autotuner: launch shape of one plan item, picked by timing the candidates
+// on a zero-filled scratch field with the item's exact strides (the caller's
+// data is never touched).  Results are cached per process and, if
+// TRI_AUTOTUNE_CACHE names a file, across processes.
+// ============================================================================
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune_cache;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Problem &pb, int kind)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "k%d m%d P%d per%d n%lld nb0 %lld nb1 %lld sj%lld sb0 %lld sb1 %lld g%lld",
+             kind, pb.method, pb.P, pb.periodic, (long long)pb.L.n, (long long)pb.L.nb0,
+             (long long)pb.L.nb1, (long long)pb.L.s_j, (long long)pb.L.s_b0, (long long)pb.L.s_b1,
+             (long long)pb.g_b1);
+    return buf;
+}
+
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *f = getenv("TRI_AUTOTUNE_CACHE");
+    if (!f || !*f) return;
+    FILE *fp = fopen(f, "r");
+    if (!fp) return;
+    char line[512];
+    while (fgets(line, sizeof line, fp)) {
+        char *bar = strrchr(line, '|');
+        if (!bar) continue;
+        *bar = 0;
+        g_tune_cache[line] = atoi(bar + 1);
+    }
+    fclose(fp);
+}
+
+void tune_cache_store(const std::string &key, int v)
+{
+    g_tune_cache[key] = v;
+    const char *f = getenv("TRI_AUTOTUNE_CACHE");
+    if (!f || !*f) return;
+    FILE *fp = fopen(f, "a");
+    if (!fp) return;
+    fprintf(fp, "%s|%d\n", key.c_str(), v);
+    fclose(fp);
+}
+
+// Candidate tuning values for a problem whose default launch is `base`.
+std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
+{
+    std::vector<int> c;
+    const int m = (int)(pb.L.n / pb.P);
+    if (base.kind == 0) {
+        for (int kc = 1; kc <= 16 && (int)c.size() < 4; ++kc)
+            if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8) c.push_back(kc);
+    } else if (base.kind == 2) {
+        int Lp, C;
+        for (int want : {4, 8, 16})
+            if (staged_split(m, Lp, C, want) && pb.P * Lp <= 1024) c.push_back(want);
+    }
+    return c;
+}
+
+}  // namespace
+
+// Returns the chosen tuning value (0 = keep the heuristic launch).
+static int autotune(tri_ctx ctx, const Problem &pb, const Tables &T, const Launch &base)
+{
+    if (env_int("TRI_AUTOTUNE", 1) == 0) return 0;
+    std::vector<int> cands = tune_candidates(pb, base);
+    if (cands.size() < 2) return 0;
+    const std::string key = tune_key(pb, base.kind);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) return it->second;
+    }
+    const LineSet &L = pb.L;
+    const int64_t span = (L.n - 1) * L.s_j + (L.nb0 - 1) * L.s_b0 + (L.nb1 - 1) * L.s_b1 + 1;
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, sizeof(double) * (size_t)span) != hipSuccess) return 0;
+    int best = 0;
+    float best_ms = 1e30f;
+    hipEvent_t e0, e1;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMemsetAsync(scratch, 0, sizeof(double) * (size_t)span, ctx->stream) == hipSuccess;
+    for (int v : cands) {
+        if (!ok) break;
+        Problem q = pb;
+        q.L.d = (double *)scratch;
+        Launch l;
+        if (plan_launch(ctx, q, T, l, v) != TRI_OK) continue;
+        if (run_launch(l, pb.method, ctx->stream) != hipSuccess) { ok = false; break; }
+        float ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            float t = 0.f;
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess || run_launch(l, pb.method, ctx->stream) != hipSuccess ||
+                hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&t, e0, e1) != hipSuccess) { ok = false; break; }
+            ms = std::min(ms, t);
+        }
+        if (ms < best_ms) { best_ms = ms; best = v; }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (ok && best > 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_store(key, best);
+        return best;
+    }
+    return 0;
+}
+
+// ============================================================================
 // Plans
 // ============================================================================
 struct tri_plan_s {
@@ -472,6 +674,7 @@ struct tri_plan_s {
         Tables T;
         Launch launch;
         void *mem = nullptr;
+        int tuned = 0;
     };
     std::vector<Item> items;
     hipStream_t cap_stream = nullptr;
@@ -540,6 +743,11 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
             return st;
         }
         hipError_t e = launch_factor(pb.src, pi.T, ctx->status_dev, ctx->stream);
+        if (e == hipSuccess) {
+            const int v = autotune(ctx, pb, pi.T, pi.launch);
+            if (v > 0 && plan_launch(ctx, pb, pi.T, pi.launch, v) != TRI_OK) st = plan_launch(ctx, pb, pi.T, pi.launch);
+            pi.tuned = v;
+        }
         if (e != hipSuccess) {
             tri_plan_destroy(plan);
             return fail(ctx, TRI_E_HIP, "factor launch: %s", hipGetErrorString(e));
@@ -602,6 +810,16 @@ int tri_plan_item_partitions(tri_plan plan, int i)
 {
     if (!plan || i < 0 || i >= (int)plan->items.size()) return -1;
     return plan->items[(size_t)i].pb.P;
+}
+
+int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
+{
+    if (!plan || i < 0 || i >= (int)plan->items.size() || !buf || len <= 0) return -1;
+    const auto &it = plan->items[(size_t)i];
+    const Launch &l = it.launch;
+    const char *kind = l.kind == 0 ? "strided" : (l.kind == 1 ? "contiguous" : "contiguous-staged");
+    return snprintf(buf, (size_t)len, "%s P=%d m=%d kc=%d Cs=%d C=%d Lp=%d LPB=%d grid=%d tuned=%d", kind,
+                    it.pb.P, l.args.m, l.args.kc, l.args.Cs, l.args.C, l.args.Lp, l.args.LPB, l.grid, it.tuned);
 }
 
 }  // extern "C"

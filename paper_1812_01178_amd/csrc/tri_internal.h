@@ -70,6 +70,9 @@ struct SolveArgs {
     int m, P, periodic;
     int64_t s_j, nb0, nb1, s_b0, s_b1;
     int64_t ngroups0;      // strided kernel: ceil(nb0 / 64)
+    int kc;                // strided kernel: chunks (wavefronts) per partition
+    int Cs;                // strided kernel: rows per chunk, m / kc
+    int64_t zero;          // always 0 (keeps the compiler from caching factor loads across passes)
     int64_t g_b1;          // matrix index = b1 * g_b1 (0: one shared matrix)
     const double *F;
     const double *IT;
@@ -80,6 +83,9 @@ struct SolveArgs {
     int LL;                // lanes per line = P * Lp
     int LPB;               // lines per block
     int64_t nlines;        // nb0 * nb1
+    // persistent LDS-staged contiguous kernel
+    int stage_stride;      // doubles between staging planes
+    int lines_linear;      // 1: line L starts at L * s_b0 (s_b1 == nb0 * s_b0)
 };
 
 // Per-line (general) coefficients.
@@ -97,11 +103,17 @@ struct GeneralArgs {
 // Host launchers (tri_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s);
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
+size_t strided_lds_bytes(const SolveArgs &a);
 hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s);
+// Persistent LDS-staged variant for shared matrices (m % C == 0, C even).
+hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStream_t s);
+size_t contig_staged_lds_bytes(const SolveArgs &a);
+// Persistent grid: resident workgroups per CU x CUs (0 if the query fails).
+int contig_staged_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
 
 // Largest m the register-resident kernels accept.
-constexpr int kStridedMaxM = 80;
+constexpr int kStridedMaxC = 80;     // rows per wavefront chunk
 constexpr int kContigMaxC = 16;
 constexpr int kGeneralMaxM = 32;
 constexpr int kGeneralPPTMaxP = 8;

@@ -14,9 +14,13 @@
 // between its elimination and its correction; no matrix-core work.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "tri_internal.h"
 
 namespace tri {
+
+typedef double v2d __attribute__((ext_vector_type(2)));   // 16-byte vector access
 
 // ===========================================================================
 // Factor kernel: one workgroup per shared matrix g, one thread per partition.
@@ -277,33 +281,47 @@ __device__ __forceinline__ void interface_unknowns(const double *__restrict__ it
 
 // ===========================================================================
 // Strided-direction solve (rows j at stride s_j, lines side by side).
-// Workgroup = P wavefronts; wavefront r holds partition r of 64 neighbouring
-// lines (lane = line), so every row access of a wavefront is one coalesced
-// 512-byte segment and every factor is wavefront-uniform (scalar loads).
-// The m values of each partition stay in VGPRs from load to store.
+// Workgroup = P*kc wavefronts; wavefront w = r*kc + s holds chunk s (Cs =
+// m/kc consecutive rows) of partition r for 64 neighbouring lines (lane =
+// line).  Every row access of a wavefront is one coalesced 512-byte segment,
+// every factor is wavefront-uniform (scalar loads), and the chunk's values
+// stay in VGPRs from load to store.  With kc > 1 the partition's forward and
+// backward Thomas recurrences are carried across its chunks through LDS
+// (zero-carry pass, combine the chunk maps, exact pass), which is the same
+// elimination as one wavefront per partition with a smaller VGPR footprint.
 // ===========================================================================
-template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(CMAX > 32 ? 512 : 1024) k_strided(const SolveArgs A)
+template <int CMAX, int METHOD, bool CHUNKED>
+__global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveArgs A)
 {
-    extern __shared__ double tips[];            // [2P][64]
+    extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
-    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int kc = A.kc, Cs = A.Cs;
+    const int r = w / kc, s = w - r * kc;
+    const int P = A.P, m = A.m;
+    const int nw = P * kc;
+    double *tips = lds;                          // [2P][64]
+    double *fend = lds + 2 * P * 64;             // [nw][64] forward chunk ends
+    double *bbeg = fend + nw * 64;               // [nw][64] backward chunk starts
+    double *pif = bbeg + nw * 64;                // [nw] forward chunk multipliers
+    double *pib = pif + nw;                      // [nw] backward chunk multipliers
+
     const int64_t blk = blockIdx.x;
     const int64_t grp = blk % A.ngroups0;
     const int64_t b1 = blk / A.ngroups0;
     const int64_t b0 = grp * 64 + lane;
     const bool active = b0 < A.nb0;
-    const int m = A.m, P = A.P;
     const int64_t n = A.n;
     const int64_t g = b1 * A.g_b1;
-    const double *__restrict__ F = A.F + g * (kNumFactors * n) + (int64_t)r * m;
+    const int64_t row0 = (int64_t)r * m + (int64_t)s * Cs;
+    const double *__restrict__ F = A.F + g * (kNumFactors * n) + row0;
     const double *__restrict__ Fb = F;
     const double *__restrict__ Fa = F + n;
     const double *__restrict__ Fc = F + 2 * n;
     const double *__restrict__ Fv = F + 3 * n;
     const double *__restrict__ Fw = F + 4 * n;
     const int64_t sj = A.s_j;
-    double *__restrict__ p = A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + (int64_t)r * m * sj;
+    double *__restrict__ p = A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj;
 
     double x[CMAX];
 #pragma unroll
@@ -311,31 +329,78 @@ __global__ void __launch_bounds__(CMAX > 32 ? 512 : 1024) k_strided(const SolveA
     if (active) {
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
-            if (t < m) x[t] = p[t * sj];
+            if (t < Cs) x[t] = __builtin_nontemporal_load(p + t * sj);
     }
-    if (r == 0 && (A.flags[g] & 1)) x[0] = 0.0;   // gauge-pinned row
+    if (r == 0 && s == 0 && (A.flags[g] & 1)) x[0] = 0.0;   // gauge-pinned row
 
     // Eq. (5): A~_r x~ = d with the precomputed pivots
-    double gp = 0.0;
+    double tip_last;
+    if (!CHUNKED) {
+        double gp = 0.0;
 #pragma unroll
-    for (int t = 0; t < CMAX; ++t)
-        if (t < m) {
-            gp = Fb[t] * x[t] - Fa[t] * gp;
-            x[t] = gp;
-        }
-    const double tip_last = gp;
-    double xn = 0.0;
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) {
+                gp = Fb[t] * x[t] - Fa[t] * gp;
+                x[t] = gp;
+            }
+        tip_last = gp;
+        double xn = 0.0;
 #pragma unroll
-    for (int t = CMAX - 1; t >= 0; --t)
-        if (t < m) {
-            xn = x[t] - Fc[t] * xn;
-            x[t] = xn;
-        }
-    const double tip_first = x[0];
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < Cs) {
+                xn = x[t] - Fc[t] * xn;
+                x[t] = xn;
+            }
+    } else {
+        // forward: zero-carry pass, then the carry entering this chunk
+        double gp = 0.0, pf = 1.0;
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) {
+                gp = Fb[t] * x[t] - Fa[t] * gp;
+                pf *= -Fa[t];
+            }
+        fend[w * 64 + lane] = gp;
+        if (lane == 0) pif[w] = pf;
+        __syncthreads();
+        double gin = 0.0;
+        for (int s2 = 0; s2 < s; ++s2) gin = fend[(r * kc + s2) * 64 + lane] + pif[r * kc + s2] * gin;
+        gp = gin;
+        const double *__restrict__ Fb2 = Fb + A.zero;   // reissue, do not keep pass-1 loads live
+        const double *__restrict__ Fa2 = Fa + A.zero;
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) {
+                gp = Fb2[t] * x[t] - Fa2[t] * gp;
+                x[t] = gp;
+            }
+        tip_last = gp;
+        // backward: zero-carry pass, then the carry entering from the right
+        double xn = 0.0, pb = 1.0;
+#pragma unroll
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < Cs) {
+                xn = x[t] - Fc[t] * xn;
+                pb *= -Fc[t];
+            }
+        bbeg[w * 64 + lane] = xn;
+        if (lane == 0) pib[w] = pb;
+        __syncthreads();
+        double xin = 0.0;
+        for (int s2 = kc - 1; s2 > s; --s2) xin = bbeg[(r * kc + s2) * 64 + lane] + pib[r * kc + s2] * xin;
+        xn = xin;
+        const double *__restrict__ Fc2 = Fc + A.zero;
+#pragma unroll
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < Cs) {
+                xn = x[t] - Fc2[t] * xn;
+                x[t] = xn;
+            }
+    }
 
     // exchange the tips of the P partitions (the paper's SENDRECV / ALLGATHER)
-    tips[(2 * r) * 64 + lane] = tip_first;
-    tips[(2 * r + 1) * 64 + lane] = tip_last;
+    if (s == 0) tips[(2 * r) * 64 + lane] = x[0];
+    if (s == kc - 1) tips[(2 * r + 1) * 64 + lane] = tip_last;
     __syncthreads();
 
     const double *__restrict__ it = A.IT + ((g * P + r) * 2) * (2 * P);
@@ -347,16 +412,26 @@ __global__ void __launch_bounds__(CMAX > 32 ? 512 : 1024) k_strided(const SolveA
     if (active) {
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
-            if (t < m) p[t * sj] = x[t] - yl * Fv[t] - yr * Fw[t];
+            if (t < Cs) __builtin_nontemporal_store(x[t] - yl * Fv[t] - yr * Fw[t], p + t * sj);
     }
+}
+
+size_t strided_lds_bytes(const SolveArgs &a)
+{
+    const int nw = a.P * a.kc;
+    return sizeof(double) * ((size_t)(2 * a.P + 2 * nw) * 64 + 2 * nw);
 }
 
 template <int CMAX, int METHOD>
 static hipError_t launch_strided_t(const SolveArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
-    const size_t lds = sizeof(double) * 2 * a.P * 64;
-    hipLaunchKernelGGL((k_strided<CMAX, METHOD>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    if (a.kc > 1)
+        hipLaunchKernelGGL((k_strided<CMAX, METHOD, true>), dim3((unsigned)blocks), dim3(64 * a.P * a.kc),
+                           strided_lds_bytes(a), s, a);
+    else
+        hipLaunchKernelGGL((k_strided<CMAX, METHOD, false>), dim3((unsigned)blocks), dim3(64 * a.P),
+                           strided_lds_bytes(a), s, a);
     return hipGetLastError();
 }
 
@@ -368,8 +443,11 @@ static hipError_t launch_strided_m(const SolveArgs &a, int cmax, hipStream_t s)
     case 16: return launch_strided_t<16, METHOD>(a, s);
     case 24: return launch_strided_t<24, METHOD>(a, s);
     case 32: return launch_strided_t<32, METHOD>(a, s);
+    case 40: return launch_strided_t<40, METHOD>(a, s);
     case 48: return launch_strided_t<48, METHOD>(a, s);
+    case 56: return launch_strided_t<56, METHOD>(a, s);
     case 64: return launch_strided_t<64, METHOD>(a, s);
+    case 72: return launch_strided_t<72, METHOD>(a, s);
     case 80: return launch_strided_t<80, METHOD>(a, s);
     default: return hipErrorInvalidValue;
     }
@@ -519,6 +597,256 @@ hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s)
         return method == TRI_PDD ? launch_contig_t<8, TRI_PDD>(a, s) : launch_contig_t<8, TRI_PPT>(a, s);
     if (a.C <= 16)
         return method == TRI_PDD ? launch_contig_t<16, TRI_PDD>(a, s) : launch_contig_t<16, TRI_PPT>(a, s);
+    return hipErrorInvalidValue;
+}
+
+// ===========================================================================
+// Persistent contiguous-direction solve with LDS staging (one shared matrix).
+// Same algebra as k_contig, rearranged for bandwidth:
+//  * one large workgroup per CU loops over groups of LPB lines; the factors
+//    and spikes of the (single, shared) matrix sit in LDS once, per lane
+//    position in a line ([lane][factor][row], odd stride against bank
+//    conflicts, compile-time offsets), read by every line of the group, and
+//    the line-independent multipliers of the carry scans are formed once;
+//  * lines move between HBM and LDS with coalesced 16-byte accesses (each
+//    wavefront instruction covers 1 KB of a line); a lane then reads its C
+//    consecutive rows from padded staging planes (conflict-free);
+//  * the next group's loads are issued into VGPRs before the current group
+//    is solved, so HBM always has a group in flight per workgroup.
+// Requires m % C == 0, C even, n even and 16-byte aligned lines.
+// ===========================================================================
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(1024) k_contig_staged(const SolveArgs A)
+{
+    extern __shared__ double lds[];
+    constexpr int QMAX = CMAX / 2;
+    const int tid = threadIdx.x;
+    const int NTH = blockDim.x;
+    const int LL = A.LL, Lp = A.Lp, C = A.C, m = A.m, P = A.P, LPB = A.LPB;
+    const int S = A.stage_stride;
+    const int NQ = C / 2;
+    const int NT = LPB * LL;
+    constexpr int FS = 5 * CMAX + 1;             // per-lane factor stride (odd)
+    double *stage = lds;                         // [NQ][S]
+    double *fac = lds + (size_t)NQ * S;          // [LL][5][CMAX] (+1 pad)
+    double *tips = fac + (size_t)FS * LL;        // [LPB][2P]
+    const int li = tid / LL;
+    const int lt = tid - li * LL;
+    const int r = lt / Lp;
+    const int k = lt - r * Lp;
+    const bool inblk = li < LPB;
+    const int64_t n = A.n;
+    const int UPL = (int)(n / 2);
+
+    // the shared matrix's factors and spikes, once per workgroup
+    for (int idx = tid; idx < 5 * C * LL; idx += NTH) {
+        const int l2 = idx / (5 * C), rem = idx - l2 * (5 * C);
+        const int f = rem / C, c = rem - f * C;
+        const int r2 = l2 / Lp, k2 = l2 - r2 * Lp;
+        fac[l2 * FS + f * CMAX + c] = A.F[f * n + (int64_t)r2 * m + (int64_t)k2 * C + c];
+    }
+    // multipliers of the partner's carry at each Kogge-Stone step
+    constexpr int kSteps = 6;
+    double psk[kSteps], ssk[kSteps];
+    {
+        const int64_t J0 = (int64_t)(inblk ? r : 0) * m + (int64_t)k * C;
+        double Ps = 1.0, Ss = 1.0;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < C && inblk) {
+                Ps *= -A.F[n + J0 + c];
+                Ss *= -A.F[2 * n + J0 + c];
+            }
+#pragma unroll
+        for (int si = 0; si < kSteps; ++si) {
+            const int s = 1 << si;
+            psk[si] = Ps;
+            ssk[si] = Ss;
+            if (s < Lp) {
+                const double Po = __shfl_up(Ps, s, Lp);
+                const double So = __shfl_down(Ss, s, Lp);
+                if (k >= s) Ps *= Po;
+                if (k + s < Lp) Ss *= So;
+            }
+        }
+    }
+    // this thread's share of the coalesced line <-> LDS copies
+    int soff[QMAX], srow[QMAX], sline[QMAX];
+#pragma unroll
+    for (int it = 0; it < QMAX; ++it) {
+        const int g = tid + it * NTH;
+        soff[it] = -1;
+        srow[it] = 0;
+        sline[it] = 0;
+        if (it < NQ && g < NT * NQ) {
+            const int l2 = g / UPL, w = g - l2 * UPL;
+            const int row = 2 * w;
+            const int r2 = row / m, rr = row - r2 * m;
+            const int k2 = rr / C, c2 = rr - k2 * C;
+            const int owner = l2 * LL + r2 * Lp + k2;
+            soff[it] = (c2 / 2) * S + owner * 2;
+            srow[it] = row;
+            sline[it] = l2;
+        }
+    }
+    auto line_ptr = [&](int64_t L) -> double * {
+        if (A.lines_linear) return A.d + L * A.s_b0;
+        const int64_t b0 = L % A.nb0, b1 = L / A.nb0;
+        return A.d + b0 * A.s_b0 + b1 * A.s_b1;
+    };
+    const double *__restrict__ it_rows = A.IT + ((int64_t)r * 2) * (2 * P);
+    const bool pinned = (A.flags[0] & 1) && r == 0 && k == 0;
+    double *mytips = tips + (inblk ? li : 0) * 2 * P;
+    const int64_t ngrp = (A.nlines + LPB - 1) / LPB;
+
+    v2d pre[QMAX];
+    auto prefetch = [&](int64_t grp) {
+#pragma unroll
+        for (int it = 0; it < QMAX; ++it)
+            if (soff[it] >= 0 && grp * LPB + sline[it] < A.nlines)
+                pre[it] = __builtin_nontemporal_load((const v2d *)(line_ptr(grp * LPB + sline[it]) + srow[it]));
+    };
+    if (blockIdx.x < ngrp) prefetch(blockIdx.x);
+    __syncthreads();   // factor table complete
+
+    for (int64_t grp = blockIdx.x; grp < ngrp; grp += gridDim.x) {
+        const int64_t Lbase = grp * LPB;
+#pragma unroll
+        for (int it = 0; it < QMAX; ++it)
+            if (soff[it] >= 0 && Lbase + sline[it] < A.nlines) *(v2d *)(stage + soff[it]) = pre[it];
+        __syncthreads();
+        if (grp + gridDim.x < ngrp) prefetch(grp + gridDim.x);
+
+        double x[CMAX];
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            x[c] = (c < C && inblk) ? stage[(c >> 1) * S + tid * 2 + (c & 1)] : 0.0;
+        if (pinned) x[0] = 0.0;
+        const double *myfac = fac + lt * FS;
+        auto F = [&](int f, int c) { return myfac[f * CMAX + c]; };
+
+        // forward sweep: zero-carry pass, carry scan, exact pass
+        double gp = 0.0;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < C) gp = F(0, c) * x[c] - F(1, c) * gp;
+        double Fs = gp;
+#pragma unroll
+        for (int si = 0; si < kSteps; ++si) {
+            const int s = 1 << si;
+            if (s < Lp) {
+                const double Fo = __shfl_up(Fs, s, Lp);
+                if (k >= s) Fs += psk[si] * Fo;
+            }
+        }
+        double gin = __shfl_up(Fs, 1, Lp);
+        if (k == 0) gin = 0.0;
+        gp = gin;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < C) {
+                gp = F(0, c) * x[c] - F(1, c) * gp;
+                x[c] = gp;
+            }
+        const double tip_last = gp;
+
+        // backward sweep
+        double xn = 0.0;
+#pragma unroll
+        for (int c = CMAX - 1; c >= 0; --c)
+            if (c < C) xn = x[c] - F(2, c) * xn;
+        double Bs = xn;
+#pragma unroll
+        for (int si = 0; si < kSteps; ++si) {
+            const int s = 1 << si;
+            if (s < Lp) {
+                const double Bo = __shfl_down(Bs, s, Lp);
+                if (k + s < Lp) Bs += ssk[si] * Bo;
+            }
+        }
+        double xin = __shfl_down(Bs, 1, Lp);
+        if (k == Lp - 1) xin = 0.0;
+        xn = xin;
+#pragma unroll
+        for (int c = CMAX - 1; c >= 0; --c)
+            if (c < C) {
+                xn = x[c] - F(2, c) * xn;
+                x[c] = xn;
+            }
+
+        if (inblk && k == 0) mytips[2 * r] = x[0];
+        if (inblk && k == Lp - 1) mytips[2 * r + 1] = tip_last;
+        __syncthreads();
+        double yl = 0.0, yr = 0.0;
+        if (inblk)
+            interface_unknowns<METHOD>(it_rows, r, P, A.periodic, [&](int q) { return mytips[q]; }, yl, yr);
+        if (inblk) {
+#pragma unroll
+            for (int c = 0; c < CMAX; ++c)
+                if (c < C) stage[(c >> 1) * S + tid * 2 + (c & 1)] = x[c] - yl * F(3, c) - yr * F(4, c);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < QMAX; ++it)
+            if (soff[it] >= 0 && Lbase + sline[it] < A.nlines)
+                __builtin_nontemporal_store(*(const v2d *)(stage + soff[it]),
+                                            (v2d *)(line_ptr(Lbase + sline[it]) + srow[it]));
+        __syncthreads();
+    }
+}
+
+size_t contig_staged_lds_bytes(const SolveArgs &a)
+{
+    const int cmax = a.C <= 4 ? 4 : (a.C <= 8 ? 8 : 16);
+    return sizeof(double) * ((size_t)(a.C / 2) * a.stage_stride + (size_t)(5 * cmax + 1) * a.LL +
+                             (size_t)a.LPB * 2 * a.P);
+}
+
+template <int CMAX, int METHOD>
+static hipError_t launch_contig_staged_t(const SolveArgs &a, int grid, hipStream_t s)
+{
+    int threads = a.LPB * a.LL;
+    threads = ((threads + 63) / 64) * 64;
+    const size_t lds = contig_staged_lds_bytes(a);
+    const int64_t ngrp = (a.nlines + a.LPB - 1) / a.LPB;
+    const int64_t blocks = std::min<int64_t>(std::max(grid, 1), ngrp);
+    hipLaunchKernelGGL((k_contig_staged<CMAX, METHOD>), dim3((unsigned)blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int CMAX, int METHOD>
+static int staged_grid_t(const SolveArgs &a)
+{
+    int threads = ((a.LPB * a.LL + 63) / 64) * 64;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_contig_staged<CMAX, METHOD>), threads,
+            contig_staged_lds_bytes(a)) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return std::max(1, per_cu) * cus;
+}
+
+int contig_staged_grid(const SolveArgs &a, int method)
+{
+    const bool pdd = method == TRI_PDD;
+    if (a.C <= 4) return pdd ? staged_grid_t<4, TRI_PDD>(a) : staged_grid_t<4, TRI_PPT>(a);
+    if (a.C <= 8) return pdd ? staged_grid_t<8, TRI_PDD>(a) : staged_grid_t<8, TRI_PPT>(a);
+    return pdd ? staged_grid_t<16, TRI_PDD>(a) : staged_grid_t<16, TRI_PPT>(a);
+}
+
+hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStream_t s)
+{
+    if (a.C <= 4)
+        return method == TRI_PDD ? launch_contig_staged_t<4, TRI_PDD>(a, grid, s)
+                                 : launch_contig_staged_t<4, TRI_PPT>(a, grid, s);
+    if (a.C <= 8)
+        return method == TRI_PDD ? launch_contig_staged_t<8, TRI_PDD>(a, grid, s)
+                                 : launch_contig_staged_t<8, TRI_PPT>(a, grid, s);
+    if (a.C <= 16)
+        return method == TRI_PDD ? launch_contig_staged_t<16, TRI_PDD>(a, grid, s)
+                                 : launch_contig_staged_t<16, TRI_PPT>(a, grid, s);
     return hipErrorInvalidValue;
 }
 

@@ -309,7 +309,8 @@ def test_pdd_drop_reported(T, ctx):
 # ---------------------------------------------------------------------------
 # Plans and HIP graphs
 # ---------------------------------------------------------------------------
-def test_plan_execute_and_graph_replay(T, ctx, orc):
+def test_plan_execute_and_graph_replay(T, ctx, orc, monkeypatch):
+    monkeypatch.setenv("TRI_AUTOTUNE", "0")     # same launch shapes as the one-shot calls
     Nz, Ny, Nx = 24, 64, 256
     u0 = W.cfg_field(Nx, Ny, Nz, seed=9)
     phi0 = W.cfg_poisson_rhs(Nx, Ny, Nz, seed=9)
@@ -352,5 +353,68 @@ def test_plan_execute_and_graph_replay(T, ctx, orc):
             _ = (up * 2).sum()            # unrelated eager work between replays
             assert np.array_equal(host(up), ue_h), rep
             assert np.array_equal(host(pp), pe_h), rep
+    finally:
+        T.tri_plan_destroy(plan)
+
+
+# ---------------------------------------------------------------------------
+# Every launch shape the tuner can pick (forced through the environment)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("direction,n,P,per,kc", [
+    (1, 256, 4, False, 1), (1, 256, 4, False, 2), (1, 256, 4, False, 4), (1, 128, 2, False, 4),
+    (2, 288, 4, True, 1), (2, 288, 4, True, 2), (2, 288, 4, True, 3), (2, 288, 2, True, 2),
+    (2, 288, 2, True, 4), (1, 96, 16, False, 1), (1, 192, 8, False, 2)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_strided_chunk_counts(T, ctx, orc, monkeypatch, direction, n, P, per, kc, mname):
+    monkeypatch.setenv("TRI_FORCE_KC", str(kc))
+    shape = {1: (3, n, 200), 2: (n, 5, 130)}[direction]
+    assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc) <= TOL
+
+
+@pytest.mark.parametrize("Nx,P,C", [(2048, 8, 4), (2048, 8, 8), (2048, 8, 16), (256, 8, 4), (256, 8, 8),
+                                    (256, 8, 16), (512, 2, 16), (384, 4, 8), (1024, 16, 4)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_contiguous_rows_per_lane(T, ctx, orc, monkeypatch, Nx, P, C, mname):
+    monkeypatch.setenv("TRI_FORCE_C", str(C))
+    assert _sweep_case(0, 5, 7, Nx, P, False, mname, T, ctx, orc) <= TOL
+
+
+def test_poisson_chunked(T, ctx, orc, monkeypatch):
+    monkeypatch.setenv("TRI_FORCE_KC", "2")
+    Nx, Ny, Nz, P = 70, 256, 24, 4
+    phihat = W.cfg_poisson_rhs(Nx, Ny, Nz, seed=2)
+    ay, cy = W.poisson_metric(Ny)
+    lam = W.modified_wavenumbers(Nz)
+    ref = phihat.copy()
+    orc.poisson(ref, ay, cy, lam, P=P)
+    dphi = torch.as_tensor(phihat).cuda()
+    T.poisson_wavenumber_solve(ctx, dphi, dev(ay), dev(cy), dev(lam), P=P)
+    assert line_relerr(host(dphi), ref, axis=1) <= TOL
+
+
+def test_autotuned_plan_matches_oracle(T, ctx, orc, monkeypatch):
+    """Plan creation times the candidate launch shapes on scratch memory and
+    keeps the fastest; the caller's field must be left untouched until execute."""
+    monkeypatch.setenv("TRI_AUTOTUNE", "1")
+    Nz, Ny, Nx = 48, 256, 512
+    u0 = W.cfg_field(Nx, Ny, Nz, seed=11)
+    cy_ = W.momentum_stretched(Ny)
+    cz_ = W.momentum_periodic(Nz)
+    cx_ = W.momentum_uniform(Nx)
+    u = dev(u0)
+    coefs = [tuple(dev(v) for v in c) for c in (cx_, cy_, cz_)]
+    items = [dict(kind=d, field=u, Nx=Nx, Ny=Ny, Nz=Nz, a=coefs[d][0], b=coefs[d][1], c=coefs[d][2],
+                  P=(8, 4, 4)[d], periodic=int(d == 2), method=0) for d in range(3)]
+    plan = T.tri_plan_create(ctx, items)
+    try:
+        assert np.array_equal(host(u), u0)              # tuning never touches the field
+        descr = [T.tri_plan_item_describe(plan, i) for i in range(3)]
+        assert all("tuned=" in d for d in descr), descr
+        T.tri_plan_execute(plan)
+        ref = u0.copy()
+        for d, (a, b, c) in enumerate((cx_, cy_, cz_)):
+            orc.adi_sweep(orc.PDD, d, ref, a, b, c, (8, 4, 4)[d], d == 2)
+        got = host(u)
+        assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= TOL
     finally:
         T.tri_plan_destroy(plan)
