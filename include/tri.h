@@ -96,7 +96,10 @@ typedef struct {
     int sweeps;           /* refinement sweeps done (0 for plain FP64)          */
     double pdd_drop_max;  /* largest |dropped Z entry| (v_m, w_1) over the call; */
                           /* PDD's error is bounded by about 4x this times |x|  */
-    double resid_max;     /* FP32+refine: largest final correction / |x|        */
+    double resid_max;     /* FP32+refine: largest estimated remaining error of a */
+                          /* line relative to |x| (|last update|^2 / |previous| */
+                          /* update| / |x|, max norms); the sweeps stop below   */
+                          /* 1e-13                                               */
 } tri_info;
 
 /* ---- context ------------------------------------------------------------- */
@@ -125,7 +128,9 @@ const char *tri_last_error(tri_ctx ctx);
  * w_1 dropped), and x = x~ - Y y (Eq. (8)).  field: TRI_REAL (d_inout is
  * double*) or TRI_COMPLEX (d_inout is interleaved complex128, s_b0 must be 1).
  * prec: TRI_F64, or TRI_F32_REFINE (FP32 elimination + FP64 residual
- * refinement towards the exact A^{-1} d, at most 3 sweeps). */
+ * refinement towards the exact A^{-1} d, at most 3 refinement sweeps after
+ * the first FP32 solve; TRI_E_NOT_CONVERGED from tri_sync_status if a line's
+ * estimated error is still above 1e-13; strided rows only). */
 tri_status tri_pdd_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines,
                          tri_field field, void *d_inout, int P, int periodic,
                          tri_prec prec, tri_info *info);

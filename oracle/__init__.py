@@ -9,6 +9,8 @@ The arithmetic lives in ``oracle.c`` (plain C, built with gcc
 wraps it for numpy arrays:
 
 * ``thomas`` / ``cyclic`` / ``exact``  -- plain solution x = A^{-1} d
+* ``exact_ld`` -- the same in long double (extended) arithmetic, the
+  reference for results that converge to the exact solution
 * ``pdd``  -- Sec. 3.2, PDD paragraph and Algorithm 1 (depends on P)
 * ``ppt``  -- Sec. 3.2, Eqs. (9)-(11) (exact; periodic wrap as interface P)
 * ``reduced_system`` -- Z (Eq. (7)), Zbar (Eq. (10)), E^T x~ and spikes
@@ -29,7 +31,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-EXACT, PDD, PPT = 0, 1, 2
+EXACT, PDD, PPT, EXACT_LD = 0, 1, 2, 3
 _STATUS = {0: "ok", 1: "invalid argument", 2: "bad shape", 3: "zero pivot", 7: "out of memory"}
 
 
@@ -66,6 +68,8 @@ def lib():
         L.orc_pdd.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D]
         L.orc_ppt.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D]
         L.orc_exact.argtypes = [_I64, ctypes.c_int, _D, _D, _D, _D, _D, _D]
+        L.orc_exact_ld.restype = ctypes.c_int
+        L.orc_exact_ld.argtypes = [_I64, ctypes.c_int, _D, _D, _D, _D, _D]
         L.orc_line_work.restype = _I64
         L.orc_line_work.argtypes = [_I64, ctypes.c_int]
         L.orc_reduced_system.restype = ctypes.c_int
@@ -119,6 +123,14 @@ def cyclic(a, b, c, d) -> np.ndarray:
 
 def exact(a, b, c, d, periodic: bool = False) -> np.ndarray:
     return cyclic(a, b, c, d) if periodic else thomas(a, b, c, d)
+
+
+def exact_ld(a, b, c, d, periodic: bool = False) -> np.ndarray:
+    """x = A^{-1} d by Thomas (or the cyclic Sherman-Morrison solve) in long double."""
+    a, b, c, d = map(_f64, (a, b, c, d))
+    x = np.empty(d.size)
+    _check(lib().orc_exact_ld(d.size, int(bool(periodic)), _p(a), _p(b), _p(c), _p(d), _p(x)), "exact_ld")
+    return x
 
 
 def _line(fn, name, a, b, c, d, P, periodic):

@@ -41,7 +41,7 @@ enum {
     ORC_E_NOMEM = 7
 };
 
-enum { ORC_EXACT = 0, ORC_PDD = 1, ORC_PPT = 2 };
+enum { ORC_EXACT = 0, ORC_PDD = 1, ORC_PPT = 2, ORC_EXACT_LD = 3 };
 
 /* ------------------------------------------------------------------------ */
 /* Thomas algorithm (textbook, no pivoting).                                 */
@@ -103,6 +103,63 @@ int orc_cyclic(int64_t n, const double *a, const double *b, const double *c,
     const double f = vx / den;
     for (int64_t j = 0; j < n; ++j) x[j] = x[j] - f * q[j];
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same two exact solves carried out in long double (x87 extended, a    */
+/* 64-bit significand): the reference for results that converge to the     */
+/* exact A^{-1} d (iterative refinement), whose distance to an FP64 direct  */
+/* solve can reach cond(A) * 1e-16.  Inputs and outputs are FP64.           */
+/* work: 5n long doubles.                                                    */
+/* ------------------------------------------------------------------------ */
+static int thomas_ld(int64_t n, const long double *a, const long double *b, const long double *c,
+                     const long double *d, long double *x, long double *cp)
+{
+    long double den = b[0];
+    if (den == 0.0L) return ORC_E_ZERO_PIVOT;
+    cp[0] = (n > 1 ? c[0] : 0.0L) / den;
+    x[0] = d[0] / den;
+    for (int64_t j = 1; j < n; ++j) {
+        den = b[j] - a[j] * cp[j - 1];
+        if (den == 0.0L) return ORC_E_ZERO_PIVOT;
+        cp[j] = (j < n - 1 ? c[j] : 0.0L) / den;
+        x[j] = (d[j] - a[j] * x[j - 1]) / den;
+    }
+    for (int64_t j = n - 2; j >= 0; --j) x[j] = x[j] - cp[j] * x[j + 1];
+    return ORC_OK;
+}
+
+int orc_exact_ld(int64_t n, int periodic, const double *a, const double *b, const double *c,
+                 const double *d, double *x)
+{
+    if (n < 1 || (periodic && n < 3)) return ORC_E_SHAPE;
+    long double *w = (long double *)malloc(sizeof(long double) * (size_t)(8 * n));
+    if (!w) return ORC_E_NOMEM;
+    long double *A = w, *B = w + n, *C = w + 2 * n, *D = w + 3 * n, *X = w + 4 * n;
+    long double *cp = w + 5 * n, *U = w + 6 * n, *Q = w + 7 * n;
+    for (int64_t j = 0; j < n; ++j) { A[j] = a[j]; B[j] = b[j]; C[j] = c[j]; D[j] = d[j]; }
+    int st;
+    if (!periodic) {
+        st = thomas_ld(n, A, B, C, D, X, cp);
+    } else {   /* Sherman-Morrison, as orc_cyclic */
+        const long double alpha = C[n - 1], beta = A[0], g = -B[0];
+        B[0] -= g;
+        B[n - 1] -= alpha * beta / g;
+        for (int64_t j = 0; j < n; ++j) U[j] = 0.0L;
+        U[0] = g;
+        U[n - 1] = alpha;
+        st = thomas_ld(n, A, B, C, D, X, cp);
+        if (!st) st = thomas_ld(n, A, B, C, U, Q, cp);
+        if (!st) {
+            const long double vx = X[0] + beta / g * X[n - 1], vq = Q[0] + beta / g * Q[n - 1];
+            const long double f = vx / (1.0L + vq);
+            for (int64_t j = 0; j < n; ++j) X[j] -= f * Q[j];
+        }
+    }
+    if (!st)
+        for (int64_t j = 0; j < n; ++j) x[j] = (double)X[j];
+    free(w);
+    return st;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -370,7 +427,7 @@ int orc_solve_batch(int method, int64_t n, int P, int periodic,
                     int64_t s_j, int64_t s_b0, int64_t s_b1, int nthreads)
 {
     if (!a || !b || !c || !d) return ORC_E_ARG;
-    if (method != ORC_EXACT) {
+    if (method != ORC_EXACT && method != ORC_EXACT_LD) {
         int st = check_shape(n, P, periodic);
         if (st) return st;
     } else if (n < 1 || (periodic && n < 3)) {
@@ -406,6 +463,7 @@ int orc_solve_batch(int method, int64_t n, int P, int periodic,
                 int st;
                 if (method == ORC_PDD) st = orc_pdd(n, P, periodic, la, lb, lc, ld, lx, work);
                 else if (method == ORC_PPT) st = orc_ppt(n, P, periodic, la, lb, lc, ld, lx, work);
+                else if (method == ORC_EXACT_LD) st = orc_exact_ld(n, periodic, la, lb, lc, ld, lx);
                 else st = orc_exact(n, periodic, la, lb, lc, ld, lx, work);
                 if (st) {
 #pragma omp critical

@@ -21,7 +21,9 @@ using namespace tri;
 struct tri_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
-    int *status_dev = nullptr;
+    int *status_dev = nullptr;            // sticky status word
+    int *sweeps_dev = nullptr;            // refinement counters (same allocation)
+    unsigned long long *resid_dev = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
     std::string last_error;
@@ -58,6 +60,7 @@ struct Problem {
     // shared / per-b1 matrices
     MatSrc src{};
     int64_t G = 1, g_b1 = 0;
+    int fp64_kmax = -1;   // Poisson: matrices g <= fp64_kmax stay FP64 under TRI_F32_REFINE
     // per-line coefficients
     const double *ga = nullptr, *gb = nullptr, *gc = nullptr;
     int64_t cs_j = 0, cs_b0 = 0, cs_b1 = 0;
@@ -69,6 +72,8 @@ struct Launch {
     int chunk_max = 0;     // strided: CMAX instance
     int grid = 0;          // staged: persistent grid
     SolveArgs args{};
+    bool refine = false;   // FP32 elimination + FP64 refinement (strided)
+    RefineArgs R{};
 };
 
 // Lanes per partition and rows per lane for the staged contiguous kernel:
@@ -97,6 +102,24 @@ int env_int(const char *name, int dflt)
 {
     const char *v = getenv(name);
     return (v && *v) ? atoi(v) : dflt;
+}
+
+// Chunks per partition for the refinement kernel, which keeps d and x in
+// FP64 and the work vector in FP32 (5 VGPRs per row): chunks of at most 16
+// rows when possible, at most 40; more than 8 rows need P*kc <= 8.
+int pick_kc_refine(int m, int P, int want_kc)
+{
+    auto valid = [&](int kc) {
+        if (kc < 1 || m % kc != 0 || P * kc > 16) return false;
+        const int c = m / kc;
+        return c <= 40 && (c <= 8 || P * kc <= 8);
+    };
+    if (want_kc > 0) return valid(want_kc) ? want_kc : 0;
+    for (int kc = 1; kc <= 16; ++kc)
+        if (valid(kc) && m / kc <= 16) return kc;
+    for (int kc = 1; kc <= 16; ++kc)
+        if (valid(kc)) return kc;
+    return 0;
 }
 
 tri_status check_partition(tri_ctx ctx, int64_t n, int P, int periodic)
@@ -224,14 +247,95 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
 hipError_t run_launch(const Launch &l, int method, hipStream_t s)
 {
     if (l.args.nlines == 0) return hipSuccess;
+    if (l.refine) return launch_strided_refine(l.args, l.R, method, l.chunk_max, s);
     if (l.kind == 2) return launch_contig_staged(l.args, method, l.grid, s);
     return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
 }
 
+// Launch of the refinement kernel over a (sub-)problem.
+tri_status plan_refine_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out, int want = 0)
+{
+    const int64_t n = pb.L.n;
+    const int P = pb.P;
+    const int m = (int)(n / P);
+    const int kc = pick_kc_refine(m, P, want ? want : env_int("TRI_FORCE_KC", 0));
+    if (kc == 0)
+        return fail(ctx, TRI_E_UNSUPPORTED, "refinement: no chunking of m = %d rows over P = %d partitions", m, P);
+    SolveArgs a{};
+    a.d = pb.L.d;
+    a.n = n;
+    a.m = m;
+    a.P = P;
+    a.periodic = pb.periodic;
+    a.s_j = pb.L.s_j;
+    a.nb0 = pb.L.nb0;
+    a.nb1 = pb.L.nb1;
+    a.s_b0 = pb.L.s_b0;
+    a.s_b1 = pb.L.s_b1;
+    a.g_b1 = pb.g_b1;
+    a.F = T.F;
+    a.IT = T.IT;
+    a.flags = T.flags;
+    a.nlines = pb.L.nb0 * pb.L.nb1;
+    a.kc = kc;
+    a.Cs = m / kc;
+    a.ngroups0 = (pb.L.nb0 + 63) / 64;
+    out.kind = 0;
+    out.chunk_max = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : 40)));
+    out.refine = true;
+    out.R = RefineArgs{T.F32, T.ORIG, kRefineMaxSweeps, kRefineTol, ctx->status_dev, ctx->sweeps_dev,
+                       ctx->resid_dev};
+    out.args = a;
+    return TRI_OK;
+}
+
+// Restrict a shared-matrix problem to the b1 range [b1_lo, b1_hi).
+Problem sub_b1(const Problem &pb, int64_t b1_lo, int64_t b1_hi)
+{
+    Problem q = pb;
+    q.L.d = pb.L.d + b1_lo * pb.L.s_b1;
+    q.L.nb1 = b1_hi - b1_lo;
+    return q;
+}
+
+// All launches of one solve request (one, or two for Poisson under
+// TRI_F32_REFINE: low wavenumbers in FP64, the rest refined).
+tri_status build_launches(tri_ctx ctx, const Problem &pb, const Tables &T, tri_prec prec,
+                          std::vector<Launch> &out, int want = 0)
+{
+    out.clear();
+    if (prec == TRI_F64) {
+        Launch l;
+        tri_status st = plan_launch(ctx, pb, T, l, want);
+        if (st) return st;
+        out.push_back(l);
+        return TRI_OK;
+    }
+    if (prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
+    if (pb.L.s_j == 1 && pb.L.n > 1)
+        return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE for contiguous rows is not available");
+    int64_t split = 0;
+    if (pb.fp64_kmax >= 0 && pb.g_b1 == 1) split = std::min<int64_t>(pb.L.nb1, (int64_t)pb.fp64_kmax + 1);
+    if (split > 0) {
+        Launch l;
+        tri_status st = plan_launch(ctx, sub_b1(pb, 0, split), T, l);
+        if (st) return st;
+        out.push_back(l);
+    }
+    if (split < pb.L.nb1) {
+        Launch l;
+        tri_status st = plan_refine_launch(ctx, sub_b1(pb, split, pb.L.nb1), T, l, want);
+        if (st) return st;
+        l.args.g_off = split;
+        out.push_back(l);
+    }
+    return TRI_OK;
+}
+
 size_t tables_bytes(int64_t G, int64_t n, int P)
 {
-    return tables_bytes_F(G, n) + tables_bytes_IT(G, P) + sizeof(double) * (size_t)G +
-           sizeof(int) * (size_t)G + 256;
+    return tables_bytes_F(G, n) + tables_bytes_IT(G, P) + tables_bytes_ORIG(G, n) + tables_bytes_F32(G, n) +
+           sizeof(double) * (size_t)G + sizeof(int) * (size_t)G + 256;
 }
 
 Tables carve_tables(void *base, int64_t G, int64_t n, int P, int periodic, int method)
@@ -242,8 +346,12 @@ Tables carve_tables(void *base, int64_t G, int64_t n, int P, int periodic, int m
     p += tables_bytes_F(G, n);
     T.IT = (double *)p;
     p += tables_bytes_IT(G, P);
+    T.ORIG = (double *)p;
+    p += tables_bytes_ORIG(G, n);
     T.drop = (double *)p;
     p += sizeof(double) * (size_t)G;
+    T.F32 = (float *)p;
+    p += tables_bytes_F32(G, n);
     T.flags = (int *)p;
     T.G = G;
     T.n = n;
@@ -267,13 +375,23 @@ tri_status ensure_ws(tri_ctx ctx, size_t bytes)
     return TRI_OK;
 }
 
-tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info)
+tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info, bool refined = false)
 {
     if (!info) return TRI_OK;
     info->sweeps = 0;
     info->resid_max = 0.0;
     info->pdd_drop_max = 0.0;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (refined) {
+        int sw = 0;
+        unsigned long long rb = 0;
+        HIP_TRY(ctx, hipMemcpy(&sw, ctx->sweeps_dev, sizeof(int), hipMemcpyDeviceToHost));
+        HIP_TRY(ctx, hipMemcpy(&rb, ctx->resid_dev, sizeof(rb), hipMemcpyDeviceToHost));
+        double rv;
+        memcpy(&rv, &rb, sizeof rv);
+        info->sweeps = sw;
+        info->resid_max = rv;
+    }
     if (T && T->G > 0) {
         std::vector<double> h((size_t)T->G);
         HIP_TRY(ctx, hipMemcpy(h.data(), T->drop, sizeof(double) * (size_t)T->G, hipMemcpyDeviceToHost));
@@ -285,8 +403,9 @@ tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info)
 // Run one validated problem through the context workspace.
 tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *info)
 {
-    if (prec != TRI_F64)
-        return fail(ctx, TRI_E_UNSUPPORTED, "precision %d not available in this path", (int)prec);
+    if (prec != TRI_F64 && prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
+    if (prec == TRI_F32_REFINE && pb.general)
+        return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE with per-line coefficients is not available");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int64_t nlines = pb.L.nb0 * pb.L.nb1;
     if (nlines == 0) {
@@ -327,12 +446,13 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
     tri_status st = ensure_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
     if (st) return st;
     Tables T = carve_tables(ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
-    Launch l;
-    st = plan_launch(ctx, pb, T, l);
+    std::vector<Launch> ls;
+    st = build_launches(ctx, pb, T, prec, ls);
     if (st) return st;
     HIP_TRY(ctx, launch_factor(pb.src, T, ctx->status_dev, ctx->stream));
-    HIP_TRY(ctx, run_launch(l, pb.method, ctx->stream));
-    return fill_info(ctx, &T, info);
+    if (prec == TRI_F32_REFINE) HIP_TRY(ctx, launch_reset_counters(ctx->sweeps_dev, ctx->resid_dev, ctx->stream));
+    for (const Launch &l : ls) HIP_TRY(ctx, run_launch(l, pb.method, ctx->stream));
+    return fill_info(ctx, &T, info, prec == TRI_F32_REFINE);
 }
 
 // Validate a tri_coef/tri_lines request and build its Problem.
@@ -396,7 +516,8 @@ tri_status adi_problem(tri_ctx ctx, int dir, double *u, int64_t Nx, int64_t Ny, 
 }
 
 tri_status poisson_problem(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
-                           const double *ay, const double *cy, const double *lam, int P, Problem &pb)
+                           const double *ay, const double *cy, const double *lam, int P, Problem &pb,
+                           int fp64_kmax = -1)
 {
     if (Nx < 0 || Ny < 1 || Nk < 0) return fail(ctx, TRI_E_ARG, "bad Poisson extents");
     tri_status st = check_partition(ctx, Ny, P, 0);
@@ -412,6 +533,7 @@ tri_status poisson_problem(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, 
     pb.src = MatSrc{ay, nullptr, cy, 1, 0, lam};
     pb.G = Nk;
     pb.g_b1 = 1;
+    pb.fp64_kmax = fp64_kmax;
     return TRI_OK;
 }
 
@@ -452,11 +574,15 @@ tri_status tri_create(tri_ctx *out, int device, void *hip_stream)
     if (!ctx) return TRI_E_NOMEM;
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
-    if (hipMalloc(&ctx->status_dev, sizeof(int)) != hipSuccess) {
+    void *words = nullptr;
+    if (hipMalloc(&words, 64) != hipSuccess) {
         delete ctx;
         return TRI_E_NOMEM;
     }
-    if (hipMemsetAsync(ctx->status_dev, 0, sizeof(int), ctx->stream) != hipSuccess ||
+    ctx->status_dev = (int *)words;
+    ctx->sweeps_dev = (int *)((char *)words + 16);
+    ctx->resid_dev = (unsigned long long *)((char *)words + 32);
+    if (hipMemsetAsync(words, 0, 64, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         (void)hipFree(ctx->status_dev);
         delete ctx;
@@ -534,9 +660,8 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
                                     tri_info *info)
 {
     if (!ctx) return TRI_E_ARG;
-    (void)fp64_kmax;
     Problem pb;
-    tri_status st = poisson_problem(ctx, phihat_inout, Nx, Ny, Nk, ay, cy, lam, P, pb);
+    tri_status st = poisson_problem(ctx, phihat_inout, Nx, Ny, Nk, ay, cy, lam, P, pb, fp64_kmax);
     if (st) return st;
     return run_problem(ctx, pb, prec, info);
 }
@@ -672,7 +797,7 @@ struct tri_plan_s {
     struct Item {
         Problem pb;
         Tables T;
-        Launch launch;
+        std::vector<Launch> launches;
         void *mem = nullptr;
         int tuned = 0;
     };
@@ -703,7 +828,7 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
 {
     if (!ctx || !out || (n_items > 0 && !items) || n_items < 0) return TRI_E_ARG;
     *out = nullptr;
-    if (prec != TRI_F64) return fail(ctx, TRI_E_UNSUPPORTED, "precision %d not available in plans", (int)prec);
+    if (prec != TRI_F64 && prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     tri_plan plan = new (std::nothrow) tri_plan_s;
     if (!plan) return TRI_E_NOMEM;
@@ -717,7 +842,8 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
         int P = it.P;
         if (it.kind == TRI_ITEM_POISSON) {
             if (P == 0) P = (it.Ny % 4 == 0) ? 4 : ((it.Ny % 2 == 0) ? 2 : 1);
-            st = poisson_problem(ctx, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.c, it.lam, P, pi.pb);
+            st = poisson_problem(ctx, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.c, it.lam, P, pi.pb,
+                                 kPoissonFp64Kmax);
         } else if (it.kind >= TRI_ITEM_ADI_X && it.kind <= TRI_ITEM_ADI_Z) {
             const int64_t n = it.kind == TRI_ITEM_ADI_X ? it.Nx : (it.kind == TRI_ITEM_ADI_Y ? it.Ny : it.Nz);
             if (P == 0) P = (n % 4 == 0 && n / 4 >= 2) ? 4 : ((n % 2 == 0) ? 2 : 1);
@@ -737,15 +863,16 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
             return fail(ctx, TRI_E_NOMEM, "plan tables of %zu bytes", bytes);
         }
         pi.T = carve_tables(pi.mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
-        st = plan_launch(ctx, pb, pi.T, pi.launch);
+        st = build_launches(ctx, pb, pi.T, prec, pi.launches);
         if (st) {
             tri_plan_destroy(plan);
             return st;
         }
         hipError_t e = launch_factor(pb.src, pi.T, ctx->status_dev, ctx->stream);
-        if (e == hipSuccess) {
-            const int v = autotune(ctx, pb, pi.T, pi.launch);
-            if (v > 0 && plan_launch(ctx, pb, pi.T, pi.launch, v) != TRI_OK) st = plan_launch(ctx, pb, pi.T, pi.launch);
+        if (e == hipSuccess && prec == TRI_F64 && pi.launches.size() == 1) {
+            const int v = autotune(ctx, pb, pi.T, pi.launches[0]);
+            if (v > 0 && build_launches(ctx, pb, pi.T, prec, pi.launches, v) != TRI_OK)
+                (void)build_launches(ctx, pb, pi.T, prec, pi.launches);
             pi.tuned = v;
         }
         if (e != hipSuccess) {
@@ -762,7 +889,8 @@ tri_status tri_plan_execute(tri_plan plan)
     if (!plan) return TRI_E_ARG;
     tri_ctx ctx = plan->ctx;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    for (auto &it : plan->items) HIP_TRY(ctx, run_launch(it.launch, it.pb.method, ctx->stream));
+    for (auto &it : plan->items)
+        for (const Launch &l : it.launches) HIP_TRY(ctx, run_launch(l, it.pb.method, ctx->stream));
     return TRI_OK;
 }
 
@@ -784,7 +912,10 @@ tri_status tri_plan_capture(tri_plan plan, void **graph_exec_out)
     HIP_TRY(ctx, hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (auto &it : plan->items) {
-        e = run_launch(it.launch, it.pb.method, plan->cap_stream);
+        for (const Launch &l : it.launches) {
+            e = run_launch(l, it.pb.method, plan->cap_stream);
+            if (e != hipSuccess) break;
+        }
         if (e != hipSuccess) break;
     }
     hipGraph_t g = nullptr;
@@ -816,10 +947,18 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
 {
     if (!plan || i < 0 || i >= (int)plan->items.size() || !buf || len <= 0) return -1;
     const auto &it = plan->items[(size_t)i];
-    const Launch &l = it.launch;
-    const char *kind = l.kind == 0 ? "strided" : (l.kind == 1 ? "contiguous" : "contiguous-staged");
-    return snprintf(buf, (size_t)len, "%s P=%d m=%d kc=%d Cs=%d C=%d Lp=%d LPB=%d grid=%d tuned=%d", kind,
-                    it.pb.P, l.args.m, l.args.kc, l.args.Cs, l.args.C, l.args.Lp, l.args.LPB, l.grid, it.tuned);
+    std::string out;
+    for (const Launch &l : it.launches) {
+        const char *kind = l.refine ? "strided-refine"
+                                    : (l.kind == 0 ? "strided" : (l.kind == 1 ? "contiguous" : "contiguous-staged"));
+        char tmp[200];
+        snprintf(tmp, sizeof tmp, "%s%s P=%d m=%d kc=%d Cs=%d C=%d Lp=%d LPB=%d grid=%d lines=%lld", out.empty() ? "" : " + ",
+                 kind, it.pb.P, l.args.m, l.args.kc, l.args.Cs, l.args.C, l.args.Lp, l.args.LPB, l.grid,
+                 (long long)l.args.nlines);
+        out += tmp;
+    }
+    out += " tuned=" + std::to_string(it.tuned);
+    return snprintf(buf, (size_t)len, "%s", out.c_str());
 }
 
 }  // extern "C"

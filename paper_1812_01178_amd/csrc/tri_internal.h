@@ -36,11 +36,23 @@ constexpr int kNumFactors = 5;   // beta, alpha, cp, v, w
 //           the right-hand side of row 0 is read as 0).
 // drop[g]:  largest |v_m^(L)|, |w_1^(R)| over the interfaces (entries PDD drops).
 // ---------------------------------------------------------------------------
+//
+// F32  [(g*5 + f)*n + J]  the same factors rounded to FP32 (refinement's
+//                          inner solve).
+// ORIG [(g*3 + f)*n + J]  the true matrix rows for the refinement residual,
+//                          as a_J, e_J = a_J + b_J + c_J (rounded once), c_J
+//                          (FP64): the residual is formed as
+//                          d - a (x_{J-1} - x_J) - c (x_{J+1} - x_J) - e x_J,
+//                          which avoids cancelling |b x| against |a x + c x|
+//                          on nearly balanced rows; a_0 and c_{n-1} are zero
+//                          unless periodic; a pinned row reads (0, 1, 0).
 struct Tables {
     double *F = nullptr;
     double *IT = nullptr;
     int *flags = nullptr;
     double *drop = nullptr;
+    float *F32 = nullptr;
+    double *ORIG = nullptr;
     int64_t G = 0, n = 0;
     int P = 0;
     int periodic = 0;
@@ -49,6 +61,8 @@ struct Tables {
 
 inline size_t tables_bytes_F(int64_t G, int64_t n) { return sizeof(double) * (size_t)(G * kNumFactors * n); }
 inline size_t tables_bytes_IT(int64_t G, int P) { return sizeof(double) * (size_t)(G * P * 2 * 2 * P); }
+inline size_t tables_bytes_F32(int64_t G, int64_t n) { return sizeof(float) * (size_t)(G * kNumFactors * n); }
+inline size_t tables_bytes_ORIG(int64_t G, int64_t n) { return sizeof(double) * (size_t)(G * 3 * n); }
 
 // Source of the G matrices for the factor kernel.
 struct MatSrc {
@@ -73,7 +87,8 @@ struct SolveArgs {
     int kc;                // strided kernel: chunks (wavefronts) per partition
     int Cs;                // strided kernel: rows per chunk, m / kc
     int64_t zero;          // always 0 (keeps the compiler from caching factor loads across passes)
-    int64_t g_b1;          // matrix index = b1 * g_b1 (0: one shared matrix)
+    int64_t g_b1;          // matrix index = b1 * g_b1 + g_off (g_b1 = 0: one shared matrix)
+    int64_t g_off;
     const double *F;
     const double *IT;
     const int *flags;
@@ -86,6 +101,17 @@ struct SolveArgs {
     // persistent LDS-staged contiguous kernel
     int stage_stride;      // doubles between staging planes
     int lines_linear;      // 1: line L starts at L * s_b0 (s_b1 == nb0 * s_b0)
+};
+
+// FP32 elimination + FP64 residual refinement (strided layout).
+struct RefineArgs {
+    const float *F32;
+    const double *ORIG;
+    int max_sweeps;        // refinement sweeps after the first FP32 solve
+    double tol;            // converged when max|update| <= tol * max|x| on a line
+    int *status;
+    int *sweeps_used;      // atomicMax of the refinement sweeps done, for tri_info
+    unsigned long long *resid_bits;   // atomicMax of the last relative update (double bits)
 };
 
 // Per-line (general) coefficients.
@@ -111,6 +137,13 @@ size_t contig_staged_lds_bytes(const SolveArgs &a);
 // Persistent grid: resident workgroups per CU x CUs (0 if the query fails).
 int contig_staged_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
+hipError_t launch_strided_refine(const SolveArgs &a, const RefineArgs &R, int method, int chunk_max, hipStream_t s);
+size_t strided_refine_lds_bytes(const SolveArgs &a);
+// Zero the refinement counters with a kernel (safe inside graph capture).
+hipError_t launch_reset_counters(int *sweeps, unsigned long long *resid, hipStream_t s);
+constexpr int kRefineMaxSweeps = 3;
+constexpr int kPoissonFp64Kmax = 2;     // plans: Poisson modes k <= 2 stay FP64 under TRI_F32_REFINE
+constexpr double kRefineTol = 1e-13;
 
 // Largest m the register-resident kernels accept.
 constexpr int kStridedMaxC = 80;     // rows per wavefront chunk

@@ -16,11 +16,9 @@
 
 #include <algorithm>
 
-#include "tri_internal.h"
+#include "tri_device.h"
 
 namespace tri {
-
-typedef double v2d __attribute__((ext_vector_type(2)));   // 16-byte vector access
 
 // ===========================================================================
 // Factor kernel: one workgroup per shared matrix g, one thread per partition.
@@ -111,6 +109,22 @@ __global__ __launch_bounds__(64) void k_factor(MatSrc S, Tables T, int *status)
             Fw[J] = wn;
         }
         if (bad) atomicOr(status, kStatusZeroPivot);
+        // FP32 copy of the factors and the true rows for the refinement residual
+        float *F32 = T.F32 + g * kNumFactors * n;
+        double *O = T.ORIG + g * 3 * n;
+        for (int t = 0; t < m; ++t) {
+            const int64_t J = o + t;
+            for (int f = 0; f < kNumFactors; ++f) F32[f * n + J] = (float)F[f * n + J];
+            const double aJ = (J == 0 && !periodic) ? 0.0 : M.A(J);
+            const double cJ = (J == n - 1 && !periodic) ? 0.0 : M.Cc(J);
+            // row sum a + b + c to full FP64 accuracy (error-free a + c, then b)
+            const double s1 = aJ + cJ;
+            const double bb = s1 - aJ;
+            const double t1 = (aJ - (s1 - bb)) + (cJ - bb);
+            O[J] = aJ;
+            O[n + J] = (M.B(J) + s1) + t1;
+            O[2 * n + J] = cJ;
+        }
     }
     // zero this matrix's reduced-system rows
     const int rowlen = 2 * P;
@@ -247,39 +261,6 @@ hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStr
 }
 
 // ===========================================================================
-// Reduced-system evaluation shared by the solve kernels: the left and right
-// interface unknowns of partition r from the tips of its line.
-// tip(q): q = 2*partition (first row) or 2*partition + 1 (last row).
-// ===========================================================================
-template <int METHOD, typename TipFn>
-__device__ __forceinline__ void interface_unknowns(const double *__restrict__ it, int r, int P,
-                                                   int periodic, TipFn tip, double &yl, double &yr)
-{
-    yl = 0.0;
-    yr = 0.0;
-    const bool has_l = (r > 0) || periodic;
-    const bool has_r = (r < P - 1) || periodic;
-    const int rowlen = 2 * P;
-    if (METHOD == TRI_PDD) {
-        if (has_l) {
-            const int L = (r > 0) ? r - 1 : P - 1;
-            yl = it[2 * L + 1] * tip(2 * L + 1) + it[2 * r] * tip(2 * r);
-        }
-        if (has_r) {
-            const int R = (r < P - 1) ? r + 1 : 0;
-            yr = it[rowlen + 2 * R] * tip(2 * R) + it[rowlen + 2 * r + 1] * tip(2 * r + 1);
-        }
-    } else {
-        const int q0 = periodic ? 0 : 1;
-        const int q1 = periodic ? rowlen : rowlen - 1;
-        if (has_l)
-            for (int q = q0; q < q1; ++q) yl += it[q] * tip(q);
-        if (has_r)
-            for (int q = q0; q < q1; ++q) yr += it[rowlen + q] * tip(q);
-    }
-}
-
-// ===========================================================================
 // Strided-direction solve (rows j at stride s_j, lines side by side).
 // Workgroup = P*kc wavefronts; wavefront w = r*kc + s holds chunk s (Cs =
 // m/kc consecutive rows) of partition r for 64 neighbouring lines (lane =
@@ -312,7 +293,7 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
     const int64_t b0 = grp * 64 + lane;
     const bool active = b0 < A.nb0;
     const int64_t n = A.n;
-    const int64_t g = b1 * A.g_b1;
+    const int64_t g = b1 * A.g_b1 + A.g_off;
     const int64_t row0 = (int64_t)r * m + (int64_t)s * Cs;
     const double *__restrict__ F = A.F + g * (kNumFactors * n) + row0;
     const double *__restrict__ Fb = F;
@@ -484,7 +465,7 @@ __global__ void __launch_bounds__(CMAX > 8 ? 256 : 1024) k_contig(const SolveArg
     const bool active = inblk && L < A.nlines;
     const int64_t b0 = active ? L % A.nb0 : 0;
     const int64_t b1 = active ? L / A.nb0 : 0;
-    const int64_t g = b1 * A.g_b1;
+    const int64_t g = b1 * A.g_b1 + A.g_off;
     const int64_t n = A.n;
     const int row0 = k * C;
     const int64_t J0 = (int64_t)(inblk ? r : 0) * m + row0;

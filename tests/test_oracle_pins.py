@@ -83,6 +83,37 @@ def test_ppt_is_exact_at_every_P(orc, n, P, periodic):
     assert relerr(orc.ppt(a, b, c, d, P, periodic), ref) < 1e-13
 
 
+@pytest.mark.parametrize("periodic", [False, True])
+def test_exact_ld_matches_rationals(orc, periodic):
+    """The extended-precision solve is the reference for refinement: pinned to
+    exact rational elimination, and (well conditioned) to the FP64 solve."""
+    rng = np.random.default_rng(17)
+    n = 12
+    a, b, c = W.random_tridiag(n, rng, margin=0.05, periodic=periodic)
+    d = rng.uniform(-1, 1, n)
+    xr = _exact_fraction_solve(dense(a, b, c, periodic), d)
+    assert relerr(orc.exact_ld(a, b, c, d, periodic), xr) < 2e-16
+    a, b, c = W.random_tridiag(200, rng, periodic=periodic)
+    d = rng.uniform(-1, 1, 200)
+    assert relerr(orc.exact_ld(a, b, c, d, periodic), orc.exact(a, b, c, d, periodic)) < 1e-14
+
+
+def test_exact_ld_beats_fp64_on_ill_conditioned(orc):
+    """On a near-singular Neumann operator (cond ~ 1e8) the FP64 and long-double
+    solves differ by far more than the long-double solve differs from exact
+    rationals: the extended reference resolves what FP64 cannot."""
+    n = 10
+    eps = 1e-7
+    a = np.full(n, -1.0); c = np.full(n, -1.0); b = np.full(n, 2.0 + eps)
+    a[0] = c[-1] = 0.0
+    b[0] = b[-1] = 1.0 + eps
+    d = np.cos(np.arange(n) * 0.7)
+    xr = _exact_fraction_solve(dense(a, b, c), d)
+    e_ld = relerr(orc.exact_ld(a, b, c, d), xr)
+    e_64 = relerr(orc.thomas(a, b, c, d), xr)
+    assert e_ld < 1e-12 and e_ld < e_64 / 50
+
+
 def test_cyclic_matches_dense(orc):
     rng = np.random.default_rng(3)
     for n in (3, 4, 17, 288):
