@@ -26,6 +26,10 @@
 
 namespace tri {
 
+// max of non-negative values that keeps a NaN once one appears (fmax would
+// drop it and let a failed solve look converged)
+__device__ __forceinline__ double nanmax(double acc, double v) { return (v > acc || v != v) ? v : acc; }
+
 template <int CMAX, int METHOD>
 __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
 {
@@ -200,8 +204,8 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
             if (t < Cs) {
                 const double delta = (double)e[t] - yl * (double)Fv[t] - yr * (double)Fw[t];
                 xv[t] += delta;
-                dmax = fmax(dmax, fabs(delta));
-                xmax = fmax(xmax, fabs(xv[t]));
+                dmax = nanmax(dmax, fabs(delta));
+                xmax = nanmax(xmax, fabs(xv[t]));
             }
         // ---- convergence of every line of the workgroup ------------------
         nrm[(w * 2 + 0) * 64 + lane] = dmax;
@@ -210,8 +214,8 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
         if (w == 0) {
             double D = 0.0, X = 0.0;
             for (int q = 0; q < nw; ++q) {
-                D = fmax(D, nrm[(q * 2 + 0) * 64 + lane]);
-                X = fmax(X, nrm[(q * 2 + 1) * 64 + lane]);
+                D = nanmax(D, nrm[(q * 2 + 0) * 64 + lane]);
+                X = nanmax(X, nrm[(q * 2 + 1) * 64 + lane]);
             }
             // error left after this update if the iteration contracts linearly
             const double Xs = X > 0.0 ? X : 1.0;
