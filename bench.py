@@ -49,6 +49,7 @@ def parse():
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine measurement")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged eight-sub-grid batch")
     ap.add_argument("--nx", type=int, default=NX)
     ap.add_argument("--ny", type=int, default=NY)
     ap.add_argument("--nz", type=int, default=NZ)
@@ -206,6 +207,13 @@ def main():
         refine = refine_section(T, oracle, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef,
                                 u0, phi0, ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, per_item_ms)
 
+    # ---------------- ragged batch: eight sub-grids in one plan -----------
+    ragged = None
+    if not args.no_ragged:
+        del u, phi, du0, dphi0
+        torch.cuda.empty_cache()
+        ragged = ragged_section(T, oracle, ctx, stream, args)
+
     # ---------------- CPU oracle baseline (bounded sample) ----------------
     cpu = None
     if args.cpu_seconds > 0:
@@ -238,6 +246,7 @@ def main():
                      "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4), "traffic": None},
         "parity_max_line_rel_err": parity,
         "fp32_refine": refine,
+        "ragged_batch": ragged,
         "cpu_baseline": cpu,
     }
     for p in plans.values():
@@ -341,6 +350,130 @@ def refine_section(T, oracle, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, 
     out["unknowns_per_s_same_items"] = sum(unknowns[n_] for n_ in names) / (tot_r * 1e-3)
     for p_ in plans.values():
         T.tri_plan_destroy(p_)
+    return out
+
+
+def ragged_section(T, oracle, ctx, stream, args):
+    """The batched ragged workload: eight sub-grids (Nx, Ny, Nz) covering
+    Nx in {256..2048}, Ny in {128, 256}, Nz in {96, 288}, each with an x, y and
+    periodic-z momentum sweep (PDD) and its Poisson wavenumber solves (PPT),
+    all in one plan with P = 0 (the plan times P in {1,2,4,8,16}; PDD only
+    where its dropped entries are <= 1e-15).  Strided solves of a dependency
+    level run as one batched launch; the step is also timed as a HIP graph,
+    without batching, and in FP32 + refinement.  FP64 results are checked
+    against the oracle on every sub-grid at the chosen P; refinement against
+    the exact solution on three sub-grids."""
+    import torch
+    import workloads as W
+    t0 = time.perf_counter()
+    grids = []
+    for s_, (nx, ny, nz) in enumerate(W.RAGGED_SUBGRIDS):
+        grids.append(dict(shape=(nx, ny, nz), u0=W.cfg_field(nx, ny, nz, seed=200 + s_),
+                          phi0=W.cfg_poisson_rhs(nx, ny, nz, seed=300 + s_),
+                          coef=(W.momentum_uniform(nx), W.momentum_stretched(ny), W.momentum_periodic(nz)),
+                          metric=W.poisson_metric(ny), lam=W.modified_wavenumbers(nz)))
+    log(f"ragged inputs generated in {time.perf_counter() - t0:.1f}s")
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x)).cuda()
+    keep = []
+    for g in grids:
+        g["du0"], g["dphi0"] = dev(g["u0"]), torch.as_tensor(g["phi0"]).cuda()
+        g["u"], g["phi"] = g["du0"].clone(), g["dphi0"].clone()
+        g["dcoef"] = [tuple(dev(v) for v in c) for c in g["coef"]]
+        g["dmetric"] = tuple(dev(v) for v in g["metric"])
+        g["dlam"] = dev(g["lam"])
+
+    def items():
+        out = []
+        for g in grids:
+            nx, ny, nz = g["shape"]
+            for d in range(3):
+                a, b, c = g["dcoef"][d]
+                out.append(dict(kind=d, field=g["u"], Nx=nx, Ny=ny, Nz=nz, a=a, b=b, c=c, P=0,
+                                periodic=int(d == 2), method=T.TRI_PDD))
+            out.append(dict(kind=T.TRI_ITEM_POISSON, field=g["phi"], Nx=nx, Ny=ny, Nz=nz // 2 + 1,
+                            a=g["dmetric"][0], c=g["dmetric"][1], lam=g["dlam"], P=0, method=T.TRI_PPT))
+        return out
+
+    def reset():
+        for g in grids:
+            g["u"].copy_(g["du0"])
+            g["phi"].copy_(g["dphi0"])
+        torch.cuda.synchronize()
+
+    def timed(run, steps):
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    unknowns = sum(3 * nx * ny * nz + (nz // 2 + 1) * ny * nx for nx, ny, nz in W.RAGGED_SUBGRIDS)
+    alg_bytes = sum(3 * 16 * nx * ny * nz + 32 * (nz // 2 + 1) * ny * nx for nx, ny, nz in W.RAGGED_SUBGRIDS)
+    out = {"subgrids": W.RAGGED_SUBGRIDS, "unknowns_per_step": unknowns, "alg_bytes_per_step": alg_bytes}
+    for prec_name, prec in (("fp64", T.TRI_F64), ("fp32_refine", T.TRI_F32_REFINE)):
+        t0 = time.perf_counter()
+        plan = T.tri_plan_create(ctx, items(), prec=prec)
+        create_s = time.perf_counter() - t0
+        n_items = 4 * len(grids)
+        Ps = [T.tri_plan_item_partitions(plan, i) for i in range(n_items)]
+        descr = [T.tri_plan_item_describe(plan, i) for i in range(n_items)]
+        batches = sorted({d.split("batch=")[1].split()[0] for d in descr if "batch=" in d})
+        reset()
+        T.tri_plan_execute(plan)
+        T.tri_sync_status(ctx)
+        errs = []
+        check = range(len(grids)) if prec == T.TRI_F64 else (0, 3, 4)
+        for s_ in check:
+            g = grids[s_]
+            ref = g["u0"].copy()
+            for d in range(3):
+                a, b, c = g["coef"][d]
+                if prec == T.TRI_F64 or d == 0:
+                    oracle.adi_sweep(oracle.PDD, d, ref, a, b, c, Ps[4 * s_ + d], d == 2)
+                else:
+                    oracle.adi_sweep(oracle.EXACT_LD, d, ref, a, b, c, 1, d == 2)
+            got = g["u"].cpu().numpy()
+            errs.append(float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+            if prec == T.TRI_F64:
+                pref = g["phi0"].copy()
+                oracle.poisson(pref, *g["metric"], g["lam"], P=Ps[4 * s_ + 3])
+                gp = g["phi"].cpu().numpy()
+                den = np.max(np.abs(pref), axis=1)
+                errs.append(float(np.max(np.max(np.abs(gp - pref), axis=1) / den)))
+        parity = max(errs)
+        ms = timed(lambda: T.tri_plan_execute(plan), args.steps)
+        T.tri_plan_capture(plan)
+        ms_graph = timed(lambda: T.tri_plan_graph_launch(plan), args.steps)
+        try:
+            T.tri_sync_status(ctx)
+            status = "ok"
+        except T.TriError as ex:
+            status = str(ex)
+        T.tri_plan_destroy(plan)
+        res = {"ms_per_step": round(ms, 4), "ms_per_step_graph": round(ms_graph, 4),
+               "unknowns_per_s": unknowns / (ms * 1e-3), "unknowns_per_s_graph": unknowns / (ms_graph * 1e-3),
+               "hbm_frac_graph": round(alg_bytes / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "P": Ps, "batched_launches": len(batches), "plan_create_s": round(create_s, 2),
+               "parity_max_rel_err": parity, "status": status,
+               "reference": "oracle at the chosen P" if prec == T.TRI_F64 else
+                            "x: oracle PDD (FP64 kernel); y, z: exact solution (extended precision), "
+                            "sub-grids 0, 3, 4"}
+        if prec == T.TRI_F64:
+            os.environ["TRI_BATCH"] = "0"
+            plan = T.tri_plan_create(ctx, items(), prec=prec)
+            os.environ.pop("TRI_BATCH")
+            res["ms_per_step_unbatched"] = round(timed(lambda: T.tri_plan_execute(plan), args.steps), 4)
+            T.tri_plan_destroy(plan)
+        out[prec_name] = res
+        log(f"ragged {prec_name}: {ms:.3f} ms/step ({ms_graph:.3f} ms as graph), "
+            f"{unknowns / (ms_graph * 1e-3) / 1e9:.1f} G unknowns/s, {len(batches)} batched launches, "
+            f"parity {parity:.2e}, P={Ps}")
+    out["refine_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step_graph"] / out["fp32_refine"]["ms_per_step_graph"], 3)
     return out
 
 

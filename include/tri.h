@@ -175,11 +175,14 @@ typedef enum { TRI_ITEM_ADI_X = 0, TRI_ITEM_ADI_Y = 1, TRI_ITEM_ADI_Z = 2,
 /* One piece of a time step's tridiagonal work.  field: u (ADI, double
  * [Nz][Ny][Nx]) or phihat (POISSON, complex128 [Nz][Ny][Nx] with Nz = Nk
  * modes).  ADI: a, b, c of the sweep direction; POISSON: a = ay, c = cy,
- * lam = modified wavenumbers, b unused.  P = 0 lets the plan's tuner choose
- * (PPT, or PDD only where the dropped entries are below 1e-15); method is
- * TRI_PDD or TRI_PPT (POISSON always uses PPT).  The coefficient arrays are
- * read once, at creation; the field pointer is kept and solved in place at
- * every execution. */
+ * lam = modified wavenumbers, b unused.  method is TRI_PDD or TRI_PPT
+ * (POISSON always uses PPT).  P = 0 lets the plan choose the partition
+ * count: every P in {1, 2, 4, 8, 16} dividing the line is factored and
+ * timed, and a PDD item only admits a P whose dropped reduced-system
+ * entries (the spike tips PDD neglects) are at most 1e-15, so that its
+ * result is the exact solution to round-off (P = 1 is plain Thomas).
+ * The coefficient arrays are read once, at creation; the field pointer is
+ * kept and solved in place at every execution. */
 typedef struct {
     int kind;
     void *field;
@@ -194,9 +197,16 @@ typedef struct {
  * matrix (partition factors, spikes, reduced-system inverses) and choose
  * the launch shapes.  All allocation happens here.  Unless the environment
  * sets TRI_AUTOTUNE=0, each item's launch shape (rows per wavefront chunk,
- * rows per lane) is chosen by timing the candidates on a scratch copy of the
- * item's layout (never on the caller's data); TRI_AUTOTUNE_CACHE=<file>
- * keeps the choices across processes.  Synchronises the context stream. */
+ * rows per lane, kernel variant) is chosen by timing the candidates on a
+ * scratch copy of the item's layout (never on the caller's data);
+ * TRI_AUTOTUNE_CACHE=<file> keeps the choices across processes.
+ * Execution order: the items behave as if run one after another in the
+ * given order; launches that touch disjoint memory are grouped into
+ * dependency levels, and the strided solves of one level (y and z sweeps,
+ * Poisson modes of different sub-grids) run as one batched launch over the
+ * ragged set unless TRI_BATCH=0.  Under TRI_F32_REFINE, items whose lines
+ * are contiguous (x sweeps) use the FP64 kernel.  Synchronises the context
+ * stream. */
 tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
                            tri_plan *out);
 /* Queue every item's solve on the context stream (no allocation, no host

@@ -68,7 +68,8 @@ struct Problem {
 
 // Kernel choice for a shared-matrix problem.
 struct Launch {
-    int kind = 0;          // 0 strided, 1 contiguous, 2 contiguous staged (persistent)
+    int kind = 0;          // 0 strided, 1 contiguous, 2 contiguous staged (persistent),
+                           // 3 contiguous with register factors (persistent)
     int chunk_max = 0;     // strided: CMAX instance
     int grid = 0;          // staged: persistent grid
     SolveArgs args{};
@@ -97,6 +98,22 @@ bool staged_split(int m, int &Lp, int &C, int want_c = 0)
             }
     return false;
 }
+
+// Split for the register-factor contiguous kernel: C rows per lane (4 or 8),
+// Lp = m / C a power of two <= 64, one line of P * Lp lanes (a multiple of
+// 64, at most 512) per workgroup.
+bool reg_split(int m, int P, int C, int &Lp)
+{
+    if ((C != 4 && C != 8) || m % C != 0) return false;
+    Lp = m / C;
+    if (Lp > 64 || (Lp & (Lp - 1)) != 0) return false;
+    const int LL = P * Lp;
+    return LL % 64 == 0 && LL <= 512;
+}
+
+// Tuning values of the contiguous kernels: C (rows per lane) selects the
+// LDS-staged kernel, kRegTune + C the register-factor kernel.
+constexpr int kRegTune = 100;
 
 int env_int(const char *name, int dflt)
 {
@@ -192,8 +209,38 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
     int sLp = 0, sC = 0;
     const bool aligned = ((uintptr_t)pb.L.d % 16 == 0) && pb.L.s_b0 % 2 == 0 &&
                          (pb.L.nb1 == 1 || pb.L.s_b1 % 2 == 0);
-    if (pb.L.s_j == 1 && n > 1 && pb.g_b1 == 0 && n % 2 == 0 && aligned && staged_split(m, sLp, sC, want_c) &&
-        P * sLp <= 1024) {
+    const bool contig_shared = pb.L.s_j == 1 && n > 1 && pb.g_b1 == 0 && n % 2 == 0 && aligned;
+    a.lines_linear = (pb.L.nb1 == 1 || pb.L.s_b1 == pb.L.nb0 * pb.L.s_b0) ? 1 : 0;
+    int rC = 0, rLp = 0;
+    if (contig_shared) {
+        if (want_c > kRegTune) {
+            if (!reg_split(m, P, want_c - kRegTune, rLp))
+                return fail(ctx, TRI_E_UNSUPPORTED, "register-factor kernel: no split of m = %d with C = %d", m,
+                            want_c - kRegTune);
+            rC = want_c - kRegTune;
+        } else if (want_c == 0) {
+            for (int c : {8, 4})
+                if (reg_split(m, P, c, rLp)) {
+                    rC = c;
+                    break;
+                }
+        }
+    }
+    if (rC > 0) {
+        // contiguous rows, one shared matrix: factors in registers, one line
+        // per workgroup; staging planes padded against LDS bank conflicts
+        a.C = rC;
+        a.Lp = rLp;
+        a.LL = P * rLp;
+        a.LPB = 1;
+        a.stage_stride = 2 * a.LL + (rC == 8 ? 8 : 16);
+        out.kind = 3;
+        out.args = a;
+        out.grid = contig_reg_grid(a, pb.method);
+        if (out.grid <= 0) return fail(ctx, TRI_E_HIP, "occupancy query for the contiguous kernel failed");
+        return TRI_OK;
+    }
+    if (contig_shared && want_c <= kRegTune && staged_split(m, sLp, sC, want_c) && P * sLp <= 1024) {
         // contiguous rows, one shared matrix: persistent LDS-staged kernel;
         // as many lines per workgroup as fit in 1024 lanes and ~150 KB of LDS
         a.C = sC;
@@ -205,7 +252,6 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
             if (contig_staged_lds_bytes(a) <= 150 * 1024) break;
         }
         if (a.LPB >= 1) {
-            a.lines_linear = (pb.L.nb1 == 1 || pb.L.s_b1 == pb.L.nb0 * pb.L.s_b0) ? 1 : 0;
             out.kind = 2;
             out.args = a;
             out.grid = contig_staged_grid(a, pb.method);
@@ -249,6 +295,7 @@ hipError_t run_launch(const Launch &l, int method, hipStream_t s)
     if (l.args.nlines == 0) return hipSuccess;
     if (l.refine) return launch_strided_refine(l.args, l.R, method, l.chunk_max, s);
     if (l.kind == 2) return launch_contig_staged(l.args, method, l.grid, s);
+    if (l.kind == 3) return launch_contig_reg(l.args, method, l.grid, s);
     return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
 }
 
@@ -727,15 +774,50 @@ std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
     if (base.kind == 0) {
         for (int kc = 1; kc <= 16 && (int)c.size() < 4; ++kc)
             if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8) c.push_back(kc);
-    } else if (base.kind == 2) {
+    } else if (base.kind == 2 || base.kind == 3) {
         int Lp, C;
         for (int want : {4, 8, 16})
             if (staged_split(m, Lp, C, want) && pb.P * Lp <= 1024) c.push_back(want);
+        for (int want : {4, 8})
+            if (reg_split(m, pb.P, want, Lp)) c.push_back(kRegTune + want);
     }
     return c;
 }
 
 }  // namespace
+
+// One execution of `ls` (the launches of problem pb) timed on a zero-filled
+// scratch buffer with pb's layout: best of three, in ms, or -1 on failure.
+static float time_on_scratch(tri_ctx ctx, const Problem &pb, std::vector<Launch> ls)
+{
+    const LineSet &L = pb.L;
+    const int64_t span = (L.n - 1) * L.s_j + (L.nb0 - 1) * L.s_b0 + (L.nb1 - 1) * L.s_b1 + 1;
+    void *scratch = nullptr;
+    if (hipMalloc(&scratch, sizeof(double) * (size_t)span) != hipSuccess) return -1.f;
+    for (Launch &l : ls) l.args.d = (double *)scratch + (l.args.d - L.d);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
+              hipMemsetAsync(scratch, 0, sizeof(double) * (size_t)span, ctx->stream) == hipSuccess;
+    auto run_all = [&]() {
+        for (const Launch &l : ls)
+            if (run_launch(l, pb.method, ctx->stream) != hipSuccess) return false;
+        return true;
+    };
+    float best = 1e30f;
+    if (ok) ok = run_all();
+    for (int rep = 0; ok && rep < 3; ++rep) {
+        float t = 0.f;
+        ok = hipEventRecord(e0, ctx->stream) == hipSuccess && run_all() &&
+             hipEventRecord(e1, ctx->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+        if (ok) best = std::min(best, t);
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    return ok ? best : -1.f;
+}
 
 // Returns the chosen tuning value (0 = keep the heuristic launch).
 static int autotune(tri_ctx ctx, const Problem &pb, const Tables &T, const Launch &base)
@@ -750,42 +832,23 @@ static int autotune(tri_ctx ctx, const Problem &pb, const Tables &T, const Launc
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) return it->second;
     }
-    const LineSet &L = pb.L;
-    const int64_t span = (L.n - 1) * L.s_j + (L.nb0 - 1) * L.s_b0 + (L.nb1 - 1) * L.s_b1 + 1;
-    void *scratch = nullptr;
-    if (hipMalloc(&scratch, sizeof(double) * (size_t)span) != hipSuccess) return 0;
     int best = 0;
     float best_ms = 1e30f;
-    hipEvent_t e0, e1;
-    bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
-              hipMemsetAsync(scratch, 0, sizeof(double) * (size_t)span, ctx->stream) == hipSuccess;
     for (int v : cands) {
-        if (!ok) break;
-        Problem q = pb;
-        q.L.d = (double *)scratch;
         Launch l;
-        if (plan_launch(ctx, q, T, l, v) != TRI_OK) continue;
-        if (run_launch(l, pb.method, ctx->stream) != hipSuccess) { ok = false; break; }
-        float ms = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
-            float t = 0.f;
-            if (hipEventRecord(e0, ctx->stream) != hipSuccess || run_launch(l, pb.method, ctx->stream) != hipSuccess ||
-                hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&t, e0, e1) != hipSuccess) { ok = false; break; }
-            ms = std::min(ms, t);
+        if (plan_launch(ctx, pb, T, l, v) != TRI_OK) continue;
+        const float ms = time_on_scratch(ctx, pb, {l});
+        if (ms < 0.f) return 0;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
         }
-        if (ms < best_ms) { best_ms = ms; best = v; }
     }
-    (void)hipStreamSynchronize(ctx->stream);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(scratch);
-    if (ok && best > 0) {
+    if (best > 0) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_cache_store(key, best);
-        return best;
     }
-    return 0;
+    return best;
 }
 
 // ============================================================================
@@ -802,10 +865,215 @@ struct tri_plan_s {
         int tuned = 0;
     };
     std::vector<Item> items;
+    // Execution order: launches grouped into dependency levels (a launch
+    // comes after every earlier launch whose memory it overlaps); inside a
+    // level, strided FP64 launches with the same workgroup shape form one
+    // batched launch.
+    struct Step {
+        int item = -1, launch = -1;                 // a single launch ...
+        std::vector<std::pair<int, int>> members;   // ... or a batch of (item, launch)
+        BatchEntry *dev = nullptr;
+        int count = 0, wavefronts = 0, cmax = 0;
+        int64_t blocks = 0;
+        size_t lds = 0;
+    };
+    std::vector<Step> steps;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
+
+namespace {
+
+constexpr double kPddSafeDrop = 1e-15;   // P = 0: PDD only where the dropped entries are this small
+
+// Problem of plan item `it` at partition count P (P = 0 is not accepted here).
+tri_status item_problem(tri_ctx ctx, const tri_item &it, int P, Problem &pb)
+{
+    if (it.kind == TRI_ITEM_POISSON)
+        return poisson_problem(ctx, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.c, it.lam, P, pb,
+                               kPoissonFp64Kmax);
+    if (it.kind >= TRI_ITEM_ADI_X && it.kind <= TRI_ITEM_ADI_Z)
+        return adi_problem(ctx, it.kind - TRI_ITEM_ADI_X, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.b, it.c,
+                           P, it.periodic, it.method, pb);
+    return fail(ctx, TRI_E_ARG, "bad item kind %d", it.kind);
+}
+
+// Launches of a plan item.  Contiguous rows have no FP32 kernel: inside a
+// plan they run the FP64 kernel under TRI_F32_REFINE too.
+tri_status item_launches(tri_ctx ctx, const Problem &pb, const Tables &T, tri_prec prec,
+                         std::vector<Launch> &out, int want = 0)
+{
+    const bool contiguous = pb.L.s_j == 1 && pb.L.n > 1;
+    return build_launches(ctx, pb, T, contiguous ? TRI_F64 : prec, out, want);
+}
+
+double max_drop(const Tables &T)
+{
+    std::vector<double> h((size_t)T.G);
+    if (hipMemcpy(h.data(), T.drop, sizeof(double) * h.size(), hipMemcpyDeviceToHost) != hipSuccess) return 1e300;
+    double d = 0.0;
+    for (double v : h) d = std::max(d, v);
+    return d;
+}
+
+// P = 0: every partition count in {1, 2, 4, 8, 16} that divides the line is
+// factored and timed on scratch memory; PDD candidates whose dropped
+// reduced-system entries exceed kPddSafeDrop are skipped (P = 1 is plain
+// Thomas and always exact).  Returns the fastest admissible P.
+tri_status choose_partitions(tri_ctx ctx, const tri_item &it, tri_prec prec, int &P_out)
+{
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int P : {1, 2, 4, 8, 16}) {
+        Problem pb;
+        if (item_problem(ctx, it, P, pb) != TRI_OK) continue;
+        void *mem = nullptr;
+        if (hipMalloc(&mem, tables_bytes(pb.G, pb.L.n, pb.P)) != hipSuccess) continue;
+        Tables T = carve_tables(mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+        std::vector<Launch> ls;
+        float ms = -1.f;
+        if (item_launches(ctx, pb, T, prec, ls) == TRI_OK &&
+            launch_factor(pb.src, T, ctx->status_dev, ctx->stream) == hipSuccess &&
+            hipStreamSynchronize(ctx->stream) == hipSuccess &&
+            (pb.method != TRI_PDD || P == 1 || max_drop(T) <= kPddSafeDrop))
+            ms = time_on_scratch(ctx, pb, ls);
+        (void)hipFree(mem);
+        if (ms >= 0.f && ms < best_ms) {
+            best_ms = ms;
+            best = P;
+        }
+    }
+    if (best == 0) return fail(ctx, TRI_E_UNSUPPORTED, "no admissible partition count for item kind %d", it.kind);
+    P_out = best;
+    return TRI_OK;
+}
+
+struct Span {
+    uintptr_t lo, hi;
+};
+
+Span launch_span(const SolveArgs &a)
+{
+    const int64_t span = (a.n - 1) * a.s_j + (a.nb0 - 1) * a.s_b0 + (a.nb1 - 1) * a.s_b1 + 1;
+    return {(uintptr_t)a.d, (uintptr_t)(a.d + span)};
+}
+
+bool batchable(const Launch &l)
+{
+    return !l.refine && l.kind == 0 && l.args.Cs <= 40 && l.args.nlines > 0;
+}
+
+// Level-schedule the plan's launches and batch the strided ones (see Step).
+tri_status build_schedule(tri_plan plan)
+{
+    tri_ctx ctx = plan->ctx;
+    for (auto &st : plan->steps)
+        if (st.dev) (void)hipFree(st.dev);
+    plan->steps.clear();
+    struct Ref {
+        int item, launch, level;
+        Span span;
+    };
+    std::vector<Ref> refs;
+    int nlevels = 0;
+    for (int i = 0; i < (int)plan->items.size(); ++i)
+        for (int j = 0; j < (int)plan->items[(size_t)i].launches.size(); ++j) {
+            const Span sp = launch_span(plan->items[(size_t)i].launches[(size_t)j].args);
+            int level = 0;
+            for (const Ref &r : refs)
+                if (r.span.lo < sp.hi && sp.lo < r.span.hi) level = std::max(level, r.level + 1);
+            refs.push_back({i, j, level, sp});
+            nlevels = std::max(nlevels, level + 1);
+        }
+    const bool batching = env_int("TRI_BATCH", 1) != 0;
+    for (int lev = 0; lev < nlevels; ++lev) {
+        std::vector<Ref> cand;
+        for (const Ref &r : refs) {
+            if (r.level != lev) continue;
+            const Launch &l = plan->items[(size_t)r.item].launches[(size_t)r.launch];
+            if (batching && batchable(l)) {
+                cand.push_back(r);
+            } else {
+                tri_plan_s::Step st;
+                st.item = r.item;
+                st.launch = r.launch;
+                plan->steps.push_back(st);
+            }
+        }
+        // the most common workgroup shape of the level; other launches are
+        // re-chunked to it where their partition count allows
+        std::map<int, int> shapes;
+        for (const Ref &r : cand) {
+            const Launch &l = plan->items[(size_t)r.item].launches[(size_t)r.launch];
+            ++shapes[l.args.P * l.args.kc];
+        }
+        int nw = 0, most = 0;
+        for (auto &kv : shapes)
+            if (kv.second > most) {
+                most = kv.second;
+                nw = kv.first;
+            }
+        for (const Ref &r : cand) {
+            auto &item = plan->items[(size_t)r.item];
+            Launch &l = item.launches[(size_t)r.launch];
+            if (l.args.P * l.args.kc == nw || nw % l.args.P != 0) continue;
+            const int kc = nw / l.args.P;
+            Launch l2;
+            if (item.launches.size() == 1 && pick_kc(l.args.m, l.args.P, kc) == kc &&
+                plan_launch(ctx, item.pb, item.T, l2, kc) == TRI_OK && l2.kind == 0 && l2.args.Cs <= 40)
+                l = l2;
+        }
+        std::map<int, std::vector<Ref>> groups;
+        for (const Ref &r : cand) {
+            const Launch &l = plan->items[(size_t)r.item].launches[(size_t)r.launch];
+            groups[l.args.P * l.args.kc].push_back(r);
+        }
+        for (auto &kv : groups) {
+            tri_plan_s::Step st;
+            if (kv.second.size() == 1) {
+                st.item = kv.second[0].item;
+                st.launch = kv.second[0].launch;
+                plan->steps.push_back(st);
+                continue;
+            }
+            std::vector<BatchEntry> host;
+            int cs = 0;
+            for (const Ref &r : kv.second) {
+                const auto &item = plan->items[(size_t)r.item];
+                const Launch &l = item.launches[(size_t)r.launch];
+                BatchEntry e{};
+                e.a = l.args;
+                e.begin = st.blocks;
+                e.method = item.pb.method;
+                host.push_back(e);
+                st.blocks += l.args.ngroups0 * l.args.nb1;
+                st.lds = std::max(st.lds, strided_lds_bytes(l.args));
+                cs = std::max(cs, l.args.Cs);
+                st.members.push_back({r.item, r.launch});
+            }
+            st.count = (int)host.size();
+            st.wavefronts = kv.first;
+            st.cmax = pick_chunk(cs);
+            const size_t bytes = sizeof(BatchEntry) * host.size();
+            if (hipMalloc((void **)&st.dev, bytes) != hipSuccess) return fail(ctx, TRI_E_NOMEM, "batch table");
+            plan->steps.push_back(st);
+            HIP_TRY(ctx, hipMemcpy(st.dev, host.data(), bytes, hipMemcpyHostToDevice));
+        }
+    }
+    return TRI_OK;
+}
+
+hipError_t run_step(const tri_plan_s &plan, const tri_plan_s::Step &st, hipStream_t s)
+{
+    if (st.members.empty()) {
+        const auto &item = plan.items[(size_t)st.item];
+        return run_launch(item.launches[(size_t)st.launch], item.pb.method, s);
+    }
+    return launch_strided_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.lds, s);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -819,6 +1087,8 @@ tri_status tri_plan_destroy(tri_plan plan)
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     for (auto &it : plan->items)
         if (it.mem) (void)hipFree(it.mem);
+    for (auto &st : plan->steps)
+        if (st.dev) (void)hipFree(st.dev);
     delete plan;
     return TRI_OK;
 }
@@ -838,20 +1108,9 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
     for (int i = 0; i < n_items; ++i) {
         const tri_item &it = items[i];
         tri_plan_s::Item &pi = plan->items[(size_t)i];
-        tri_status st;
         int P = it.P;
-        if (it.kind == TRI_ITEM_POISSON) {
-            if (P == 0) P = (it.Ny % 4 == 0) ? 4 : ((it.Ny % 2 == 0) ? 2 : 1);
-            st = poisson_problem(ctx, (double *)it.field, it.Nx, it.Ny, it.Nz, it.a, it.c, it.lam, P, pi.pb,
-                                 kPoissonFp64Kmax);
-        } else if (it.kind >= TRI_ITEM_ADI_X && it.kind <= TRI_ITEM_ADI_Z) {
-            const int64_t n = it.kind == TRI_ITEM_ADI_X ? it.Nx : (it.kind == TRI_ITEM_ADI_Y ? it.Ny : it.Nz);
-            if (P == 0) P = (n % 4 == 0 && n / 4 >= 2) ? 4 : ((n % 2 == 0) ? 2 : 1);
-            st = adi_problem(ctx, it.kind - TRI_ITEM_ADI_X, (double *)it.field, it.Nx, it.Ny, it.Nz,
-                             it.a, it.b, it.c, P, it.periodic, it.method, pi.pb);
-        } else {
-            st = fail(ctx, TRI_E_ARG, "item %d: bad kind %d", i, it.kind);
-        }
+        tri_status st = P == 0 ? choose_partitions(ctx, it, prec, P) : TRI_OK;
+        if (!st) st = item_problem(ctx, it, P, pi.pb);
         if (st) {
             tri_plan_destroy(plan);
             return st;
@@ -863,22 +1122,27 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
             return fail(ctx, TRI_E_NOMEM, "plan tables of %zu bytes", bytes);
         }
         pi.T = carve_tables(pi.mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
-        st = build_launches(ctx, pb, pi.T, prec, pi.launches);
+        st = item_launches(ctx, pb, pi.T, prec, pi.launches);
         if (st) {
             tri_plan_destroy(plan);
             return st;
         }
         hipError_t e = launch_factor(pb.src, pi.T, ctx->status_dev, ctx->stream);
-        if (e == hipSuccess && prec == TRI_F64 && pi.launches.size() == 1) {
+        if (e == hipSuccess && pi.launches.size() == 1 && !pi.launches[0].refine) {
             const int v = autotune(ctx, pb, pi.T, pi.launches[0]);
-            if (v > 0 && build_launches(ctx, pb, pi.T, prec, pi.launches, v) != TRI_OK)
-                (void)build_launches(ctx, pb, pi.T, prec, pi.launches);
+            if (v > 0 && item_launches(ctx, pb, pi.T, prec, pi.launches, v) != TRI_OK)
+                (void)item_launches(ctx, pb, pi.T, prec, pi.launches);
             pi.tuned = v;
         }
         if (e != hipSuccess) {
             tri_plan_destroy(plan);
             return fail(ctx, TRI_E_HIP, "factor launch: %s", hipGetErrorString(e));
         }
+    }
+    tri_status st = build_schedule(plan);
+    if (st) {
+        tri_plan_destroy(plan);
+        return st;
     }
     *out = plan;
     return TRI_OK;
@@ -889,8 +1153,7 @@ tri_status tri_plan_execute(tri_plan plan)
     if (!plan) return TRI_E_ARG;
     tri_ctx ctx = plan->ctx;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    for (auto &it : plan->items)
-        for (const Launch &l : it.launches) HIP_TRY(ctx, run_launch(l, it.pb.method, ctx->stream));
+    for (const auto &st : plan->steps) HIP_TRY(ctx, run_step(*plan, st, ctx->stream));
     return TRI_OK;
 }
 
@@ -911,11 +1174,8 @@ tri_status tri_plan_capture(tri_plan plan, void **graph_exec_out)
     }
     HIP_TRY(ctx, hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (auto &it : plan->items) {
-        for (const Launch &l : it.launches) {
-            e = run_launch(l, it.pb.method, plan->cap_stream);
-            if (e != hipSuccess) break;
-        }
+    for (const auto &st : plan->steps) {
+        e = run_step(*plan, st, plan->cap_stream);
         if (e != hipSuccess) break;
     }
     hipGraph_t g = nullptr;
@@ -949,8 +1209,8 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
     const auto &it = plan->items[(size_t)i];
     std::string out;
     for (const Launch &l : it.launches) {
-        const char *kind = l.refine ? "strided-refine"
-                                    : (l.kind == 0 ? "strided" : (l.kind == 1 ? "contiguous" : "contiguous-staged"));
+        static const char *const kinds[] = {"strided", "contiguous", "contiguous-staged", "contiguous-reg"};
+        const char *kind = l.refine ? "strided-refine" : kinds[l.kind];
         char tmp[200];
         snprintf(tmp, sizeof tmp, "%s%s P=%d m=%d kc=%d Cs=%d C=%d Lp=%d LPB=%d grid=%d lines=%lld", out.empty() ? "" : " + ",
                  kind, it.pb.P, l.args.m, l.args.kc, l.args.Cs, l.args.C, l.args.Lp, l.args.LPB, l.grid,
@@ -958,6 +1218,11 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
         out += tmp;
     }
     out += " tuned=" + std::to_string(it.tuned);
+    for (size_t b = 0; b < plan->steps.size(); ++b)
+        for (const auto &m : plan->steps[b].members)
+            if (m.first == i)
+                out += " batch=" + std::to_string(b) + "/" + std::to_string(plan->steps[b].count) + "x" +
+                       std::to_string(plan->steps[b].wavefronts) + "w";
     return snprintf(buf, (size_t)len, "%s", out.c_str());
 }
 

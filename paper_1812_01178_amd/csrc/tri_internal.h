@@ -101,6 +101,16 @@ struct SolveArgs {
     // persistent LDS-staged contiguous kernel
     int stage_stride;      // doubles between staging planes
     int lines_linear;      // 1: line L starts at L * s_b0 (s_b1 == nb0 * s_b0)
+    // (the register-factor contiguous kernel uses C, Lp, LL, stage_stride,
+    // nlines and lines_linear, one line per workgroup)
+};
+
+// One entry of a ragged batch of strided solves run by a single launch:
+// workgroups [begin, begin + ngroups0 * nb1) of the launch solve `a`.
+struct BatchEntry {
+    SolveArgs a;
+    int64_t begin;
+    int method;
 };
 
 // FP32 elimination + FP64 residual refinement (strided layout).
@@ -130,12 +140,21 @@ struct GeneralArgs {
 hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s);
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
 size_t strided_lds_bytes(const SolveArgs &a);
+// Ragged batch (device table of `count` entries, sorted by begin; every
+// entry has P * kc == wavefronts and m / kc <= cmax <= 40).
+hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
+                                size_t lds, hipStream_t s);
 hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s);
 // Persistent LDS-staged variant for shared matrices (m % C == 0, C even).
 hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStream_t s);
 size_t contig_staged_lds_bytes(const SolveArgs &a);
 // Persistent grid: resident workgroups per CU x CUs (0 if the query fails).
 int contig_staged_grid(const SolveArgs &a, int method);
+// Persistent contiguous variant with the factors in registers (one line per
+// workgroup; C in {4, 8}, P * Lp a multiple of 64 and <= 512).
+hipError_t launch_contig_reg(const SolveArgs &a, int method, int grid, hipStream_t s);
+size_t contig_reg_lds_bytes(const SolveArgs &a);
+int contig_reg_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
 hipError_t launch_strided_refine(const SolveArgs &a, const RefineArgs &R, int method, int chunk_max, hipStream_t s);
 size_t strided_refine_lds_bytes(const SolveArgs &a);

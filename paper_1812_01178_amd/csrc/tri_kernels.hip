@@ -272,9 +272,8 @@ hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStr
 // elimination as one wavefront per partition with a smaller VGPR footprint.
 // ===========================================================================
 template <int CMAX, int METHOD, bool CHUNKED>
-__global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveArgs A)
+__device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, double *lds)
 {
-    extern __shared__ double lds[];
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int kc = A.kc, Cs = A.Cs;
@@ -287,7 +286,6 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
     double *pif = bbeg + nw * 64;                // [nw] forward chunk multipliers
     double *pib = pif + nw;                      // [nw] backward chunk multipliers
 
-    const int64_t blk = blockIdx.x;
     const int64_t grp = blk % A.ngroups0;
     const int64_t b1 = blk / A.ngroups0;
     const int64_t b0 = grp * 64 + lane;
@@ -395,6 +393,56 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) __builtin_nontemporal_store(x[t] - yl * Fv[t] - yr * Fw[t], p + t * sj);
     }
+}
+
+template <int CMAX, int METHOD, bool CHUNKED>
+__global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveArgs A)
+{
+    extern __shared__ double lds[];
+    strided_solve<CMAX, METHOD, CHUNKED>(A, blockIdx.x, lds);
+}
+
+// ===========================================================================
+// Ragged batch of strided solves in one launch.  Each entry of the device
+// table is a complete strided problem (its own line length, strides,
+// partition count, chunking, method and factor tables); workgroup b runs
+// block b - begin of the entry whose block range holds b.  Every entry uses
+// the same number of wavefronts per workgroup (P * kc) and chunks of at most
+// CMAX rows, so one launch shape serves the whole batch.  The entries must
+// not overlap in memory (they run concurrently).
+// ===========================================================================
+template <int CMAX>
+__global__ void __launch_bounds__(1024) k_strided_batch(const BatchEntry *__restrict__ E, int count)
+{
+    extern __shared__ double lds[];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && E[i + 1].begin <= b) ++i;
+    const BatchEntry &e = E[i];
+    const int64_t lb = b - e.begin;
+    if (e.method == TRI_PDD) {
+        if (e.a.kc > 1) strided_solve<CMAX, TRI_PDD, true>(e.a, lb, lds);
+        else strided_solve<CMAX, TRI_PDD, false>(e.a, lb, lds);
+    } else {
+        if (e.a.kc > 1) strided_solve<CMAX, TRI_PPT, true>(e.a, lb, lds);
+        else strided_solve<CMAX, TRI_PPT, false>(e.a, lb, lds);
+    }
+}
+
+hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
+                                size_t lds, hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(64 * wavefronts);
+    switch (cmax) {
+    case 8: hipLaunchKernelGGL(k_strided_batch<8>, grid, block, lds, s, entries, count); break;
+    case 16: hipLaunchKernelGGL(k_strided_batch<16>, grid, block, lds, s, entries, count); break;
+    case 24: hipLaunchKernelGGL(k_strided_batch<24>, grid, block, lds, s, entries, count); break;
+    case 32: hipLaunchKernelGGL(k_strided_batch<32>, grid, block, lds, s, entries, count); break;
+    case 40: hipLaunchKernelGGL(k_strided_batch<40>, grid, block, lds, s, entries, count); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 size_t strided_lds_bytes(const SolveArgs &a)

@@ -379,6 +379,51 @@ def test_contiguous_rows_per_lane(T, ctx, orc, monkeypatch, Nx, P, C, mname):
     assert _sweep_case(0, 5, 7, Nx, P, False, mname, T, ctx, orc) <= TOL
 
 
+@pytest.mark.parametrize("Nx,P,C,per", [(2048, 8, 8, False), (2048, 8, 4, False), (256, 8, 4, False),
+                                        (512, 2, 8, False), (512, 2, 4, True), (1024, 16, 8, True),
+                                        (1024, 16, 4, False), (2048, 4, 8, True)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_contiguous_register_factor_kernel(T, ctx, orc, monkeypatch, Nx, P, C, per, mname):
+    """Register-factor contiguous kernel (tuning value 100 + C), fewer lines than workgroups."""
+    monkeypatch.setenv("TRI_FORCE_C", str(100 + C))
+    assert _sweep_case(0, 5, 7, Nx, P, per, mname, T, ctx, orc) <= TOL
+
+
+@pytest.mark.parametrize("C", [4, 8])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_contiguous_register_factor_persistent(T, ctx, orc, monkeypatch, C, mname):
+    """Many more lines than resident workgroups, so every workgroup loops over
+    several lines through both staging buffers; the line count is odd."""
+    monkeypatch.setenv("TRI_FORCE_C", str(100 + C))
+    assert _sweep_case(0, 41, 37, 2048, 8, False, mname, T, ctx, orc, coef=W.momentum_uniform(2048)) <= TOL
+
+
+@pytest.mark.parametrize("mname,method", METHODS)
+def test_contiguous_register_factor_padded_batch(T, ctx, orc, monkeypatch, mname, method):
+    """Contiguous lines in a 2-D batch whose outer stride is padded (lines are
+    not evenly spaced), one shared matrix."""
+    monkeypatch.setenv("TRI_FORCE_C", "108")
+    n, P, nb0, nb1, pad = 1024, 8, 30, 23, 6
+    s_b0, s_b1 = n + 2, (n + 2) * nb0 + pad
+    rng = np.random.default_rng(77)
+    a, b, c = W.random_tridiag(n, rng, margin=0.6, periodic=False)
+    buf = rng.standard_normal(s_b1 * nb1)
+    ref = buf.copy()
+    orc.solve_batch(_oracle_method(orc, mname), ref, n, nb0, nb1, s_j=1, s_b0=s_b0, s_b1=s_b1,
+                    a=a, b=b, c=c, cs_j=1, cs_b0=0, cs_b1=0, P=P)
+    dd = dev(buf)
+    fn = T.tri_pdd_solve if method == 0 else T.tri_ppt_solve
+    fn(ctx, dev(a), dev(b), dev(c), dd, (n, nb0, nb1, 1, s_b0, s_b1), coef_strides=(1, 0, 0), P=P)
+    T.tri_sync_status(ctx)
+    got = host(dd)
+    idx = (np.arange(nb1)[:, None, None] * s_b1 + np.arange(nb0)[None, :, None] * s_b0 +
+           np.arange(n)[None, None, :])
+    assert line_relerr(got[idx], ref[idx], axis=2) <= TOL
+    gap = np.ones(buf.size, bool)
+    gap[idx.ravel()] = False
+    assert np.array_equal(got[gap], buf[gap])           # padding untouched
+
+
 def test_poisson_chunked(T, ctx, orc, monkeypatch):
     monkeypatch.setenv("TRI_FORCE_KC", "2")
     Nx, Ny, Nz, P = 70, 256, 24, 4
