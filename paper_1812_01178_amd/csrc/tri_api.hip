@@ -872,6 +872,9 @@ struct tri_plan_s {
     struct Step {
         int item = -1, launch = -1;                 // a single launch ...
         std::vector<std::pair<int, int>> members;   // ... or a batch of (item, launch)
+        bool refine = false;                        // batch of refinement solves
+        bool chunked = false;
+        int method = 0;
         BatchEntry *dev = nullptr;
         int count = 0, wavefronts = 0, cmax = 0;
         int64_t blocks = 0;
@@ -959,9 +962,15 @@ Span launch_span(const SolveArgs &a)
     return {(uintptr_t)a.d, (uintptr_t)(a.d + span)};
 }
 
-bool batchable(const Launch &l)
+// Strided launches can join a batch of launches that run the same kernel
+// instance: the key holds refinement, chunk instance (CMAX), method,
+// chunking and wavefronts per workgroup.
+bool batchable(const Launch &l) { return l.kind == 0 && l.args.nlines > 0; }
+
+int64_t batch_key(const Launch &l, int method)
 {
-    return !l.refine && l.kind == 0 && l.args.Cs <= 40 && l.args.nlines > 0;
+    return (((int64_t)(l.refine ? 1 : 0) * 128 + l.chunk_max) * 2 + method) * 2 * 64 +
+           (int64_t)(l.args.kc > 1 ? 64 : 0) + l.args.P * l.args.kc;
 }
 
 // Level-schedule the plan's launches and batch the strided ones (see Step).
@@ -1001,33 +1010,10 @@ tri_status build_schedule(tri_plan plan)
                 plan->steps.push_back(st);
             }
         }
-        // the most common workgroup shape of the level; other launches are
-        // re-chunked to it where their partition count allows
-        std::map<int, int> shapes;
+        std::map<int64_t, std::vector<Ref>> groups;
         for (const Ref &r : cand) {
-            const Launch &l = plan->items[(size_t)r.item].launches[(size_t)r.launch];
-            ++shapes[l.args.P * l.args.kc];
-        }
-        int nw = 0, most = 0;
-        for (auto &kv : shapes)
-            if (kv.second > most) {
-                most = kv.second;
-                nw = kv.first;
-            }
-        for (const Ref &r : cand) {
-            auto &item = plan->items[(size_t)r.item];
-            Launch &l = item.launches[(size_t)r.launch];
-            if (l.args.P * l.args.kc == nw || nw % l.args.P != 0) continue;
-            const int kc = nw / l.args.P;
-            Launch l2;
-            if (item.launches.size() == 1 && pick_kc(l.args.m, l.args.P, kc) == kc &&
-                plan_launch(ctx, item.pb, item.T, l2, kc) == TRI_OK && l2.kind == 0 && l2.args.Cs <= 40)
-                l = l2;
-        }
-        std::map<int, std::vector<Ref>> groups;
-        for (const Ref &r : cand) {
-            const Launch &l = plan->items[(size_t)r.item].launches[(size_t)r.launch];
-            groups[l.args.P * l.args.kc].push_back(r);
+            const auto &item = plan->items[(size_t)r.item];
+            groups[batch_key(item.launches[(size_t)r.launch], item.pb.method)].push_back(r);
         }
         for (auto &kv : groups) {
             tri_plan_s::Step st;
@@ -1038,23 +1024,26 @@ tri_status build_schedule(tri_plan plan)
                 continue;
             }
             std::vector<BatchEntry> host;
-            int cs = 0;
+            const Launch &l0 = plan->items[(size_t)kv.second[0].item].launches[(size_t)kv.second[0].launch];
+            st.refine = l0.refine;
+            st.cmax = l0.chunk_max;
+            st.chunked = l0.args.kc > 1;
+            st.method = plan->items[(size_t)kv.second[0].item].pb.method;
+            st.wavefronts = l0.args.P * l0.args.kc;
             for (const Ref &r : kv.second) {
                 const auto &item = plan->items[(size_t)r.item];
                 const Launch &l = item.launches[(size_t)r.launch];
                 BatchEntry e{};
                 e.a = l.args;
+                e.R = l.R;
                 e.begin = st.blocks;
                 e.method = item.pb.method;
                 host.push_back(e);
                 st.blocks += l.args.ngroups0 * l.args.nb1;
-                st.lds = std::max(st.lds, strided_lds_bytes(l.args));
-                cs = std::max(cs, l.args.Cs);
+                st.lds = std::max(st.lds, st.refine ? strided_refine_lds_bytes(l.args) : strided_lds_bytes(l.args));
                 st.members.push_back({r.item, r.launch});
             }
             st.count = (int)host.size();
-            st.wavefronts = kv.first;
-            st.cmax = pick_chunk(cs);
             const size_t bytes = sizeof(BatchEntry) * host.size();
             if (hipMalloc((void **)&st.dev, bytes) != hipSuccess) return fail(ctx, TRI_E_NOMEM, "batch table");
             plan->steps.push_back(st);
@@ -1070,7 +1059,10 @@ hipError_t run_step(const tri_plan_s &plan, const tri_plan_s::Step &st, hipStrea
         const auto &item = plan.items[(size_t)st.item];
         return run_launch(item.launches[(size_t)st.launch], item.pb.method, s);
     }
-    return launch_strided_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.lds, s);
+    if (st.refine)
+        return launch_strided_refine_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.lds, s);
+    return launch_strided_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.chunked, st.lds,
+                                s);
 }
 
 }  // namespace

@@ -9,14 +9,22 @@ namespace tri {
 
 typedef double v2d __attribute__((ext_vector_type(2)));   // 16-byte vector access
 
+// Global-address-space views of table and field pointers.  The solve bodies
+// load through these, so the compiler emits global (and, for uniform
+// addresses, scalar) loads even where the pointer was read from memory, as
+// in the batched launches, rather than flat ones.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int gint;
+
 // ===========================================================================
 // Reduced-system evaluation shared by the solve kernels: the left and right
 // interface unknowns of partition r from the tips of its line.
 // tip(q): q = 2*partition (first row) or 2*partition + 1 (last row).
 // ===========================================================================
-template <int METHOD, typename TipFn>
-__device__ __forceinline__ void interface_unknowns(const double *__restrict__ it, int r, int P,
-                                                   int periodic, TipFn tip, double &yl, double &yr)
+template <int METHOD, typename ItPtr, typename TipFn>
+__device__ __forceinline__ void interface_unknowns(ItPtr it, int r, int P, int periodic, TipFn tip, double &yl,
+                                                   double &yr)
 {
     yl = 0.0;
     yr = 0.0;

@@ -105,14 +105,6 @@ struct SolveArgs {
     // nlines and lines_linear, one line per workgroup)
 };
 
-// One entry of a ragged batch of strided solves run by a single launch:
-// workgroups [begin, begin + ngroups0 * nb1) of the launch solve `a`.
-struct BatchEntry {
-    SolveArgs a;
-    int64_t begin;
-    int method;
-};
-
 // FP32 elimination + FP64 residual refinement (strided layout).
 struct RefineArgs {
     const float *F32;
@@ -122,6 +114,16 @@ struct RefineArgs {
     int *status;
     int *sweeps_used;      // atomicMax of the refinement sweeps done, for tri_info
     unsigned long long *resid_bits;   // atomicMax of the last relative update (double bits)
+};
+
+// One entry of a ragged batch of strided solves run by a single launch:
+// workgroups [begin, begin + ngroups0 * nb1) of the launch solve `a` (with
+// refinement arguments R in a refinement batch).
+struct BatchEntry {
+    SolveArgs a;
+    RefineArgs R;
+    int64_t begin;
+    int method;
 };
 
 // Per-line (general) coefficients.
@@ -141,9 +143,10 @@ hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStr
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
 size_t strided_lds_bytes(const SolveArgs &a);
 // Ragged batch (device table of `count` entries, sorted by begin; every
-// entry has P * kc == wavefronts and m / kc <= cmax <= 40).
+// entry would run the single-problem kernel instance <cmax, method,
+// chunked> with P * kc == wavefronts).
 hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
-                                size_t lds, hipStream_t s);
+                                int method, bool chunked, size_t lds, hipStream_t s);
 hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s);
 // Persistent LDS-staged variant for shared matrices (m % C == 0, C even).
 hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStream_t s);
@@ -158,6 +161,9 @@ int contig_reg_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
 hipError_t launch_strided_refine(const SolveArgs &a, const RefineArgs &R, int method, int chunk_max, hipStream_t s);
 size_t strided_refine_lds_bytes(const SolveArgs &a);
+// Ragged batch of refinement solves (same rule with the refinement kernel).
+hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts,
+                                       int cmax, int method, size_t lds, hipStream_t s);
 // Zero the refinement counters with a kernel (safe inside graph capture).
 hipError_t launch_reset_counters(int *sweeps, unsigned long long *resid, hipStream_t s);
 constexpr int kRefineMaxSweeps = 3;

@@ -293,14 +293,14 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     const int64_t n = A.n;
     const int64_t g = b1 * A.g_b1 + A.g_off;
     const int64_t row0 = (int64_t)r * m + (int64_t)s * Cs;
-    const double *__restrict__ F = A.F + g * (kNumFactors * n) + row0;
-    const double *__restrict__ Fb = F;
-    const double *__restrict__ Fa = F + n;
-    const double *__restrict__ Fc = F + 2 * n;
-    const double *__restrict__ Fv = F + 3 * n;
-    const double *__restrict__ Fw = F + 4 * n;
+    const gdouble *__restrict__ F = (const gdouble *)(A.F + g * (kNumFactors * n) + row0);
+    const gdouble *__restrict__ Fb = F;
+    const gdouble *__restrict__ Fa = F + n;
+    const gdouble *__restrict__ Fc = F + 2 * n;
+    const gdouble *__restrict__ Fv = F + 3 * n;
+    const gdouble *__restrict__ Fw = F + 4 * n;
     const int64_t sj = A.s_j;
-    double *__restrict__ p = A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj;
+    gdouble *__restrict__ p = (gdouble *)(A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj);
 
     double x[CMAX];
 #pragma unroll
@@ -310,7 +310,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) x[t] = __builtin_nontemporal_load(p + t * sj);
     }
-    if (r == 0 && s == 0 && (A.flags[g] & 1)) x[0] = 0.0;   // gauge-pinned row
+    if (r == 0 && s == 0 && (((const gint *)A.flags)[g] & 1)) x[0] = 0.0;   // gauge-pinned row
 
     // Eq. (5): A~_r x~ = d with the precomputed pivots
     double tip_last;
@@ -345,8 +345,8 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         double gin = 0.0;
         for (int s2 = 0; s2 < s; ++s2) gin = fend[(r * kc + s2) * 64 + lane] + pif[r * kc + s2] * gin;
         gp = gin;
-        const double *__restrict__ Fb2 = Fb + A.zero;   // reissue, do not keep pass-1 loads live
-        const double *__restrict__ Fa2 = Fa + A.zero;
+        const gdouble *__restrict__ Fb2 = Fb + A.zero;   // reissue, do not keep pass-1 loads live
+        const gdouble *__restrict__ Fa2 = Fa + A.zero;
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) {
@@ -368,7 +368,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         double xin = 0.0;
         for (int s2 = kc - 1; s2 > s; --s2) xin = bbeg[(r * kc + s2) * 64 + lane] + pib[r * kc + s2] * xin;
         xn = xin;
-        const double *__restrict__ Fc2 = Fc + A.zero;
+        const gdouble *__restrict__ Fc2 = Fc + A.zero;
 #pragma unroll
         for (int t = CMAX - 1; t >= 0; --t)
             if (t < Cs) {
@@ -382,7 +382,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     if (s == kc - 1) tips[(2 * r + 1) * 64 + lane] = tip_last;
     __syncthreads();
 
-    const double *__restrict__ it = A.IT + ((g * P + r) * 2) * (2 * P);
+    const gdouble *__restrict__ it = (const gdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
     double yl, yr;
     interface_unknowns<METHOD>(it, r, P, A.periodic,
                                [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
@@ -405,44 +405,57 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
 // ===========================================================================
 // Ragged batch of strided solves in one launch.  Each entry of the device
 // table is a complete strided problem (its own line length, strides,
-// partition count, chunking, method and factor tables); workgroup b runs
-// block b - begin of the entry whose block range holds b.  Every entry uses
-// the same number of wavefronts per workgroup (P * kc) and chunks of at most
-// CMAX rows, so one launch shape serves the whole batch.  The entries must
-// not overlap in memory (they run concurrently).
+// partition count, factor tables); workgroup b runs block b - begin of the
+// entry whose block range holds b.  A batch only joins problems that the
+// single-problem launch would run with this very instance (same CMAX,
+// method, chunking and P * kc), so batching never changes a problem's
+// arithmetic or launch shape.  The entries must not overlap in memory.
 // ===========================================================================
-template <int CMAX>
-__global__ void __launch_bounds__(1024) k_strided_batch(const BatchEntry *__restrict__ E, int count)
+template <int CMAX, int METHOD, bool CHUNKED>
+__global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided_batch(const BatchEntry *__restrict__ E, int count)
 {
     extern __shared__ double lds[];
     const int64_t b = blockIdx.x;
     int i = 0;
     while (i + 1 < count && E[i + 1].begin <= b) ++i;
-    const BatchEntry &e = E[i];
-    const int64_t lb = b - e.begin;
-    if (e.method == TRI_PDD) {
-        if (e.a.kc > 1) strided_solve<CMAX, TRI_PDD, true>(e.a, lb, lds);
-        else strided_solve<CMAX, TRI_PDD, false>(e.a, lb, lds);
-    } else {
-        if (e.a.kc > 1) strided_solve<CMAX, TRI_PPT, true>(e.a, lb, lds);
-        else strided_solve<CMAX, TRI_PPT, false>(e.a, lb, lds);
-    }
+    strided_solve<CMAX, METHOD, CHUNKED>(E[i].a, b - E[i].begin, lds);
 }
 
-hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
-                                size_t lds, hipStream_t s)
+template <int CMAX, int METHOD>
+static void launch_batch_t(const BatchEntry *e, int count, dim3 grid, dim3 block, size_t lds, bool chunked,
+                           hipStream_t s)
 {
-    if (blocks <= 0) return hipSuccess;
-    const dim3 grid((unsigned)blocks), block(64 * wavefronts);
+    if (chunked) hipLaunchKernelGGL((k_strided_batch<CMAX, METHOD, true>), grid, block, lds, s, e, count);
+    else hipLaunchKernelGGL((k_strided_batch<CMAX, METHOD, false>), grid, block, lds, s, e, count);
+}
+
+template <int METHOD>
+static hipError_t launch_batch_m(const BatchEntry *e, int count, dim3 grid, dim3 block, size_t lds, int cmax,
+                                 bool chunked, hipStream_t s)
+{
     switch (cmax) {
-    case 8: hipLaunchKernelGGL(k_strided_batch<8>, grid, block, lds, s, entries, count); break;
-    case 16: hipLaunchKernelGGL(k_strided_batch<16>, grid, block, lds, s, entries, count); break;
-    case 24: hipLaunchKernelGGL(k_strided_batch<24>, grid, block, lds, s, entries, count); break;
-    case 32: hipLaunchKernelGGL(k_strided_batch<32>, grid, block, lds, s, entries, count); break;
-    case 40: hipLaunchKernelGGL(k_strided_batch<40>, grid, block, lds, s, entries, count); break;
+    case 8: launch_batch_t<8, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 16: launch_batch_t<16, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 24: launch_batch_t<24, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 32: launch_batch_t<32, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 40: launch_batch_t<40, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 48: launch_batch_t<48, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 56: launch_batch_t<56, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 64: launch_batch_t<64, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 72: launch_batch_t<72, METHOD>(e, count, grid, block, lds, chunked, s); break;
+    case 80: launch_batch_t<80, METHOD>(e, count, grid, block, lds, chunked, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
+                                int method, bool chunked, size_t lds, hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(64 * wavefronts);
+    return method == TRI_PDD ? launch_batch_m<TRI_PDD>(entries, count, grid, block, lds, cmax, chunked, s)
+                             : launch_batch_m<TRI_PPT>(entries, count, grid, block, lds, cmax, chunked, s);
 }
 
 size_t strided_lds_bytes(const SolveArgs &a)

@@ -15,6 +15,12 @@
 //     is <= tol * |x|; the plain test |delta_s| <= tol |x| would stall at
 //     the FP64 noise floor of the residual on ill-conditioned lines.
 //
+// The FP32 solve is linear, so each line's right-hand side is scaled by a
+// power of two before rounding to FP32 (exact) and the update scaled back:
+// by max|d| of the line for the first solve, by the line's last max|update|
+// afterwards (the next residual is A times an error of about that size).
+// Lines of any magnitude stay inside FP32's range.
+//
 // Layout and chunking as k_strided: workgroup = P*kc wavefronts, wavefront
 // (r, s) holds rows [r*m + s*Cs, +Cs) of 64 neighbouring lines; d and x stay
 // in FP64 VGPRs for the whole iteration, the work vector in FP32.  Chunk
@@ -30,10 +36,18 @@ namespace tri {
 // drop it and let a failed solve look converged)
 __device__ __forceinline__ double nanmax(double acc, double v) { return (v > acc || v != v) ? v : acc; }
 
-template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
+// Binary exponent used to scale a line whose largest magnitude is v (0 for
+// zero or non-finite v; clamped so that 2^(+-E) stays finite).
+__device__ __forceinline__ int line_exponent(double v)
 {
-    extern __shared__ double lds[];
+    if (!(v > 0.0) || !(v <= 1.7976931348623157e308)) return 0;
+    return min(1000, max(-1000, ilogb(v)));
+}
+
+template <int CMAX, int METHOD>
+__device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const RefineArgs &R, int64_t blk,
+                                                     double *lds)
+{
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int kc = A.kc, Cs = A.Cs;
@@ -48,10 +62,10 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
     float *pif = bbeg + nw * 64;                      // [nw]
     float *pib = pif + nw;                            // [nw]
     int *flag = (int *)(pib + nw);
-    double *ofac = (double *)(flag + 4);              // [nw][3][CMAX] true rows a, b, c
+    int *escale = flag + 4;                           // [64] per-line scale exponent
+    double *ofac = (double *)(escale + 64);           // [nw][3][CMAX] true rows a, b, c
     float *ffac = (float *)(ofac + nw * 3 * CMAX);    // [nw][5][CMAX] FP32 factors
 
-    const int64_t blk = blockIdx.x;
     const int64_t grp = blk % A.ngroups0;
     const int64_t b1 = blk / A.ngroups0;
     const int64_t b0 = grp * 64 + lane;
@@ -62,8 +76,8 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
     // this chunk's factors and matrix rows, staged once in LDS (read back with
     // wavefront-uniform addresses inside the sweeps)
     {
-        const float *__restrict__ F0 = R.F32 + g * (kNumFactors * n) + row0;
-        const double *__restrict__ O0 = R.ORIG + g * (3 * n) + row0;
+        const gfloat *__restrict__ F0 = (const gfloat *)(R.F32 + g * (kNumFactors * n) + row0);
+        const gdouble *__restrict__ O0 = (const gdouble *)(R.ORIG + g * (3 * n) + row0);
         for (int idx = lane; idx < kNumFactors * Cs; idx += 64) {
             const int f = idx / Cs, t = idx - f * Cs;
             ffac[(w * kNumFactors + f) * CMAX + t] = F0[f * n + t];
@@ -83,7 +97,7 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
     const float *Fw = ffac + (w * kNumFactors + 4) * CMAX;
     __syncthreads();
     const int64_t sj = A.s_j;
-    double *__restrict__ p = A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj;
+    gdouble *__restrict__ p = (gdouble *)(A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj);
     // neighbouring chunks in line order (wavefronts are numbered along the line)
     const int wprev = (w > 0) ? w - 1 : (A.periodic ? nw - 1 : -1);
     const int wnext = (w < nw - 1) ? w + 1 : (A.periodic ? 0 : -1);
@@ -101,17 +115,31 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) dv[t] = __builtin_nontemporal_load(p + t * sj);
     }
-    if (r == 0 && s == 0 && (A.flags[g] & 1)) dv[0] = 0.0;   // gauge-pinned row
+    if (r == 0 && s == 0 && (((const gint *)A.flags)[g] & 1)) dv[0] = 0.0;   // gauge-pinned row
+    // scale of the first right-hand side: the exponent of max|d| over the line
+    int E;
+    {
+        double dm = 0.0;
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) dm = nanmax(dm, fabs(dv[t]));
+        nrm[(w * 2 + 0) * 64 + lane] = dm;
+        __syncthreads();
+        double D0 = 0.0;
+        for (int q = 0; q < nw; ++q) D0 = nanmax(D0, nrm[(q * 2 + 0) * 64 + lane]);
+        E = line_exponent(D0);
+    }
 
-    const double *__restrict__ it = A.IT + ((g * P + r) * 2) * (2 * P);
+    const gdouble *__restrict__ it = (const gdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
     int sweep = 0;
     bool converged = false;
     double dprev = 0.0, est = 0.0;   // wavefront 0: previous update norm and error estimate of its lane's line
     for (; sweep <= R.max_sweeps; ++sweep) {
         // ---- residual r = d - A x in FP64 (true matrix rows) -------------
+        const double sc = ldexp(1.0, -E);
         if (sweep == 0) {
 #pragma unroll
-            for (int t = 0; t < CMAX; ++t) e[t] = (float)dv[t];
+            for (int t = 0; t < CMAX; ++t) e[t] = (float)(dv[t] * sc);
         } else {
             double xlast = 0.0;
 #pragma unroll
@@ -130,7 +158,7 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
                     // cancellation of b x_t against a x_t + c x_t
                     const double res = dv[t] - (Oa[t] * (xm - xv[t]) + Oc[t] * (xp - xv[t]) + Oe[t] * xv[t]);
                     xm = xv[t];
-                    e[t] = (float)res;
+                    e[t] = (float)(res * sc);
                 }
         }
         // ---- FP32 partitioned elimination of A~ delta~ = r ----------------
@@ -199,10 +227,11 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
         double yl, yr;
         interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
         double dmax = 0.0, xmax = 0.0;
+        const double unscale = ldexp(1.0, E);
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) {
-                const double delta = (double)e[t] - yl * (double)Fv[t] - yr * (double)Fw[t];
+                const double delta = ((double)e[t] - yl * (double)Fv[t] - yr * (double)Fw[t]) * unscale;
                 xv[t] += delta;
                 dmax = nanmax(dmax, fabs(delta));
                 xmax = nanmax(xmax, fabs(xv[t]));
@@ -226,21 +255,25 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
             // is already below the tolerance)
             const bool ok = !active || (sweep >= 1 && D <= R.tol * Xs) || (sweep >= 2 && est <= R.tol);
             dprev = D;
+            escale[lane] = line_exponent(D);
             const bool all = __all(ok);
             if (lane == 0) *flag = all ? 1 : 0;
         }
         __syncthreads();
         converged = (*flag != 0);
+        E = escale[lane];
         if (converged) break;
     }
     if (threadIdx.x == 0) {
         if (!converged) atomicOr(R.status, kStatusNotConverged);
         if (R.sweeps_used) atomicMax(R.sweeps_used, converged ? sweep : R.max_sweeps);
     }
-    if (w == 0 && active && R.resid_bits) {
-        // estimated remaining relative error of this line (non-negative
-        // doubles order like their bit patterns)
-        atomicMax(R.resid_bits, (unsigned long long)__double_as_longlong(fabs(est)));
+    if (w == 0 && R.resid_bits) {
+        // largest estimated remaining relative error of the workgroup's lines
+        // (non-negative doubles order like their bit patterns), one atomic
+        double e = active ? fabs(est) : 0.0;
+        for (int off = 32; off > 0; off >>= 1) e = nanmax(e, __shfl_xor(e, off));
+        if (lane == 0) atomicMax(R.resid_bits, (unsigned long long)__double_as_longlong(e));
     }
     if (active) {
 #pragma unroll
@@ -249,12 +282,56 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
     }
 }
 
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
+{
+    extern __shared__ double lds[];
+    strided_refine_solve<CMAX, METHOD>(A, R, blockIdx.x, lds);
+}
+
+// Ragged batch of refinement solves in one launch (see k_strided_batch):
+// every entry runs with this instance's CMAX, method and P * kc.
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine_batch(const BatchEntry *__restrict__ E,
+                                                                                  int count)
+{
+    extern __shared__ double lds[];
+    const int64_t b = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && E[i + 1].begin <= b) ++i;
+    strided_refine_solve<CMAX, METHOD>(E[i].a, E[i].R, b - E[i].begin, lds);
+}
+
+template <int METHOD>
+static hipError_t launch_refine_batch_m(const BatchEntry *e, int count, dim3 grid, dim3 block, size_t lds,
+                                        int cmax, hipStream_t s)
+{
+    switch (cmax) {
+    case 8: hipLaunchKernelGGL((k_strided_refine_batch<8, METHOD>), grid, block, lds, s, e, count); break;
+    case 16: hipLaunchKernelGGL((k_strided_refine_batch<16, METHOD>), grid, block, lds, s, e, count); break;
+    case 24: hipLaunchKernelGGL((k_strided_refine_batch<24, METHOD>), grid, block, lds, s, e, count); break;
+    case 32: hipLaunchKernelGGL((k_strided_refine_batch<32, METHOD>), grid, block, lds, s, e, count); break;
+    case 40: hipLaunchKernelGGL((k_strided_refine_batch<40, METHOD>), grid, block, lds, s, e, count); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts,
+                                       int cmax, int method, size_t lds, hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    const dim3 grid((unsigned)blocks), block(64 * wavefronts);
+    return method == TRI_PDD ? launch_refine_batch_m<TRI_PDD>(entries, count, grid, block, lds, cmax, s)
+                             : launch_refine_batch_m<TRI_PPT>(entries, count, grid, block, lds, cmax, s);
+}
+
 size_t strided_refine_lds_bytes(const SolveArgs &a)
 {
     const int nw = a.P * a.kc;
     const int cmax = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : 40)));
     return sizeof(double) * ((size_t)2 * a.P * 64 + (size_t)nw * 4 * 64) +
-           sizeof(float) * ((size_t)nw * 2 * 64 + 2 * (size_t)nw) + 16 +
+           sizeof(float) * ((size_t)nw * 2 * 64 + 2 * (size_t)nw) + 16 + 64 * sizeof(int) +
            sizeof(double) * (size_t)nw * 3 * cmax + sizeof(float) * (size_t)nw * kNumFactors * cmax;
 }
 

@@ -116,7 +116,7 @@ def test_ragged_plan_fp64_batched_and_graph(T, ctx, orc):
     plan = T.tri_plan_create(ctx, items)
     try:
         descr = [T.tri_plan_item_describe(plan, i) for i in range(len(items))]
-        assert sum("batch=" in d for d in descr) >= 8, descr       # strided solves of a level batched
+        assert sum("batch=" in d for d in descr) >= 2, descr       # some strided solves share a launch
         Ps = [T.tri_plan_item_partitions(plan, i) for i in range(len(items))]
         assert all(p in (1, 2, 4, 8, 16) for p in Ps)
         T.tri_plan_execute(plan)
@@ -140,19 +140,33 @@ def test_ragged_plan_fp64_batched_and_graph(T, ctx, orc):
 
 
 def test_ragged_plan_batched_matches_unbatched(T, ctx, orc, monkeypatch):
-    """Same items with batching switched off: each result still matches the oracle
-    at the chosen P (the two plans may chunk differently, so compare to the oracle)."""
+    """A batch only joins solves that run the same kernel instance, so with
+    fixed shapes (P = 4, no tuning) the batched plan equals the plan with
+    batching switched off bit for bit, and both match the oracle."""
+    monkeypatch.setenv("TRI_AUTOTUNE", "0")
+    grids = _inputs(SMALL, seed=70)
+    items, keep = _items(T, grids, P=4)
+    plan = T.tri_plan_create(ctx, items)
+    try:
+        descr = [T.tri_plan_item_describe(plan, i) for i in range(len(items))]
+        assert sum("batch=" in d for d in descr) >= 12, descr
+        T.tri_plan_execute(plan)
+        T.tri_sync_status(ctx)
+        batched = [(host(g["u"]), host(g["phi"])) for g in grids]
+    finally:
+        T.tri_plan_destroy(plan)
+    for s, g in enumerate(grids):
+        _check_grid(orc, g, [4, 4, 4, 4])
     monkeypatch.setenv("TRI_BATCH", "0")
-    grids = _inputs(SMALL[:4], seed=70)
-    items, keep = _items(T, grids)
+    items, keep2 = _items(T, grids, P=4)
     plan = T.tri_plan_create(ctx, items)
     try:
         assert not any("batch=" in T.tri_plan_item_describe(plan, i) for i in range(len(items)))
-        Ps = [T.tri_plan_item_partitions(plan, i) for i in range(len(items))]
         T.tri_plan_execute(plan)
         T.tri_sync_status(ctx)
-        for s, g in enumerate(grids):
-            _check_grid(orc, g, Ps[4 * s:4 * s + 4])
+        for g, (ub, pb) in zip(grids, batched):
+            assert np.array_equal(host(g["u"]), ub), g["shape"]
+            assert np.array_equal(host(g["phi"]), pb), g["shape"]
     finally:
         T.tri_plan_destroy(plan)
 

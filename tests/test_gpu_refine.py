@@ -138,6 +138,39 @@ def test_refine_reports_non_convergence(T, ctx, orc):
     assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
 
 
+@pytest.mark.parametrize("direction,method", [(1, 0), (2, 1)])
+def test_refine_any_magnitude(T, ctx, orc, direction, method):
+    """Each line's right-hand side is scaled by a power of two before the FP32
+    solve, so lines whose values lie far outside FP32's range (here 1e-250 to
+    1e250, a different magnitude on every line) still reach the exact solution."""
+    n = {1: 256, 2: 288}[direction]
+    shape = {1: (3, n, 130), 2: (n, 4, 70)}[direction]
+    Nz, Ny, Nx = shape
+    rng = np.random.default_rng(17)
+    u = W.cfg_field(Nx, Ny, Nz, seed=17)
+    mag = 10.0 ** rng.uniform(-250, 250, size=(Ny, Nx) if direction == 2 else (Nz, Nx))
+    u = u * (mag[None] if direction == 2 else mag[:, None, :])
+    a, b, c = W.momentum_stretched(n) if direction == 1 else W.momentum_periodic(n)
+    ref = _exact_sweep(orc, direction, u, a, b, c, direction == 2)
+    du = dev(u)
+    T.adi_sweep(ctx, direction, du, dev(a), dev(b), dev(c), 4, periodic=direction == 2, method=method,
+                prec=T.TRI_F32_REFINE)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(du), ref, axis=2 - direction) <= TOL
+
+
+def test_refine_poisson_large_values(T, ctx, orc):
+    Nx, Ny, Nz = 70, 64, 48
+    phihat = W.cfg_poisson_rhs(Nx, Ny, Nz, seed=19) * 1e200
+    ay, cy = W.poisson_metric(Ny)
+    lam = W.modified_wavenumbers(Nz)
+    ref = _poisson_exact(orc, phihat, ay, cy, lam)
+    dphi = torch.as_tensor(phihat).cuda()
+    T.poisson_wavenumber_solve(ctx, dphi, dev(ay), dev(cy), dev(lam), P=4, prec=T.TRI_F32_REFINE, fp64_kmax=2)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dphi), ref, axis=1) <= TOL
+
+
 @pytest.mark.parametrize("kc", [2, 4, 8])
 def test_refine_chunk_counts(T, ctx, orc, monkeypatch, kc):
     monkeypatch.setenv("TRI_FORCE_KC", str(kc))
