@@ -243,7 +243,8 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(dom, T.tri_plan_item_describe(plans[dom], 0))},
         "parity_max_line_rel_err": parity,
         "fp32_refine": refine,
         "ragged_batch": ragged,
@@ -253,6 +254,46 @@ def main():
         T.tri_plan_destroy(p)
     T.tri_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2048x256x288.md")
+KERNEL_SOURCES = {"strided": ["tri_kernels.hip"], "contiguous-reg": ["tri_contig_reg.hip"],
+                  "contiguous-staged": ["tri_kernels.hip"]}
+
+
+def source_digest(kind):
+    """sha256 over the files a kernel kind is compiled from (its source and the shared headers)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1812_01178_amd", "csrc")
+    for f in KERNEL_SOURCES[kind] + ["tri_device.h", "tri_internal.h"]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(item, launch):
+    """HBM bytes per launch of `item` from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary, or None when the summary was taken for another launch shape or before the
+    kernel's sources last changed."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kind = launch.split()[0]
+    if kind not in KERNEL_SOURCES:
+        return None
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) >= 5 and cells[0] == item:
+            recorded_launch, digest, total_gb = cells[1].strip("`"), cells[2].strip("`"), cells[-2]
+            if recorded_launch != launch or digest != source_digest(kind):
+                return None
+            try:
+                return float(total_gb) * 1e9
+            except ValueError:
+                return None
+    return None
 
 
 def refine_section(T, oracle, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef, u0, phi0,

@@ -387,11 +387,16 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     interface_unknowns<METHOD>(it, r, P, A.periodic,
                                [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
 
-    // Eq. (8) / (11): x = x~ - y_left v^(r) - y_right w^(r), fused with the store
+    // Eq. (8) / (11): x = x~ - y_left v^(r) - y_right w^(r).  Every row is
+    // corrected before the first store, so the spike values are read with
+    // scalar loads (a load after a store to the field could not be).
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < Cs) x[t] = x[t] - yl * Fv[t] - yr * Fw[t];
     if (active) {
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
-            if (t < Cs) __builtin_nontemporal_store(x[t] - yl * Fv[t] - yr * Fw[t], p + t * sj);
+            if (t < Cs) __builtin_nontemporal_store(x[t], p + t * sj);
     }
 }
 
