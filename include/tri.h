@@ -199,7 +199,9 @@ typedef struct {
  * sets TRI_AUTOTUNE=0, each item's launch shape (rows per wavefront chunk,
  * rows per lane, kernel variant) is chosen by timing the candidates on a
  * scratch copy of the item's layout (never on the caller's data);
- * TRI_AUTOTUNE_CACHE=<file> keeps the choices across processes.
+ * TRI_AUTOTUNE_CACHE=<file> keeps the choices across processes, and the
+ * read-only table tune_gfx950.txt next to libtri.so holds the tuner's MI355X
+ * choices for common shapes (listed shapes are not re-timed).
  * Execution order: the items behave as if run one after another in the
  * given order; launches that touch disjoint memory are grouped into
  * dependency levels, and the strided solves of one level (y and z sweeps,

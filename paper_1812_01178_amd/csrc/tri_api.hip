@@ -1,5 +1,6 @@
 // tri_api.hip -- host side of the libtri C ABI (include/tri.h): argument
 // validation, contexts, workspace, kernel selection, plans and HIP graphs.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -737,22 +738,37 @@ std::string tune_key(const Problem &pb, int kind)
     return buf;
 }
 
-void tune_cache_load()
+void tune_cache_read(const char *path)
 {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char *f = getenv("TRI_AUTOTUNE_CACHE");
-    if (!f || !*f) return;
-    FILE *fp = fopen(f, "r");
+    FILE *fp = fopen(path, "r");
     if (!fp) return;
     char line[512];
     while (fgets(line, sizeof line, fp)) {
+        if (line[0] == '#') continue;
         char *bar = strrchr(line, '|');
         if (!bar) continue;
         *bar = 0;
         g_tune_cache[line] = atoi(bar + 1);
     }
     fclose(fp);
+}
+
+// Tuning choices known before any timing: the table shipped next to the
+// library (results of this tuner on MI355X for common shapes, read-only),
+// then TRI_AUTOTUNE_CACHE, whose entries take precedence.
+void tune_cache_load()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    Dl_info info;
+    if (dladdr((void *)&tune_cache_read, &info) && info.dli_fname) {
+        std::string dir(info.dli_fname);
+        const size_t slash = dir.rfind('/');
+        dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
+        tune_cache_read((dir + "/tune_gfx950.txt").c_str());
+    }
+    const char *f = getenv("TRI_AUTOTUNE_CACHE");
+    if (f && *f) tune_cache_read(f);
 }
 
 void tune_cache_store(const std::string &key, int v)
