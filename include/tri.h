@@ -201,7 +201,10 @@ typedef struct {
  * scratch copy of the item's layout (never on the caller's data);
  * TRI_AUTOTUNE_CACHE=<file> keeps the choices across processes, and the
  * read-only table tune_gfx950.txt next to libtri.so holds the tuner's MI355X
- * choices for common shapes (listed shapes are not re-timed).
+ * choices for common shapes (listed shapes are not re-timed;
+ * TRI_TUNE_TABLE=<file> reads another table, TRI_TUNE_TABLE=off none).
+ * Strided candidates: chunks per partition x workgroup order (line groups
+ * in order, or a contiguous range of them per XCD).
  * Execution order: the items behave as if run one after another in the
  * given order; launches that touch disjoint memory are grouped into
  * dependency levels, and the strided solves of one level (y and z sweeps,

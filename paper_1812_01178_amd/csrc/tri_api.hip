@@ -186,7 +186,9 @@ int pick_kc(int m, int P, int want_kc)
 // rows per lane), 0 = heuristic.  TRI_FORCE_KC / TRI_FORCE_C override it.
 tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out, int want = 0)
 {
-    const int want_kc = want ? want : env_int("TRI_FORCE_KC", 0);
+    // strided tuning values: chunks per partition + 100 * workgroup order
+    const int want_kc = want ? want % 100 : env_int("TRI_FORCE_KC", 0);
+    const int want_map = want ? want / 100 : env_int("TRI_BLK_MAP", 0);
     const int want_c = want ? want : env_int("TRI_FORCE_C", 0);
     const int64_t n = pb.L.n;
     const int P = pb.P;
@@ -284,6 +286,7 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
         a.Cs = m / kc;
         const int cmax = pick_chunk(a.Cs);
         a.ngroups0 = (pb.L.nb0 + 63) / 64;
+        a.blk_map = (want_map == 1 || want_map == 2) ? want_map : 0;
         out.kind = 0;
         out.chunk_max = cmax;
     }
@@ -761,7 +764,10 @@ void tune_cache_load()
     if (g_tune_loaded) return;
     g_tune_loaded = true;
     Dl_info info;
-    if (dladdr((void *)&tune_cache_read, &info) && info.dli_fname) {
+    const char *table = getenv("TRI_TUNE_TABLE");   // another table, or "off"
+    if (table && *table) {
+        if (strcmp(table, "off") != 0) tune_cache_read(table);
+    } else if (dladdr((void *)&tune_cache_read, &info) && info.dli_fname) {
         std::string dir(info.dli_fname);
         const size_t slash = dir.rfind('/');
         dir = slash == std::string::npos ? std::string(".") : dir.substr(0, slash);
@@ -788,8 +794,15 @@ std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
     std::vector<int> c;
     const int m = (int)(pb.L.n / pb.P);
     if (base.kind == 0) {
-        for (int kc = 1; kc <= 16 && (int)c.size() < 4; ++kc)
-            if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8) c.push_back(kc);
+        // chunks per partition, each with line groups in order and with
+        // per-XCD contiguous ranges (+200)
+        int nk = 0;
+        for (int kc = 1; kc <= 16 && nk < 4; ++kc)
+            if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8) {
+                c.push_back(kc);
+                c.push_back(kc + 200);
+                ++nk;
+            }
     } else if (base.kind == 2 || base.kind == 3) {
         int Lp, C;
         for (int want : {4, 8, 16})

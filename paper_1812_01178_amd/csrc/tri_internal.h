@@ -85,6 +85,7 @@ struct SolveArgs {
     int64_t s_j, nb0, nb1, s_b0, s_b1;
     int64_t ngroups0;      // strided kernel: ceil(nb0 / 64)
     int kc;                // strided kernel: chunks (wavefronts) per partition
+    int blk_map;           // strided kernel: workgroup -> (line group, b1) order, see strided_block
     int Cs;                // strided kernel: rows per chunk, m / kc
     int64_t zero;          // always 0 (keeps the compiler from caching factor loads across passes)
     int64_t g_b1;          // matrix index = b1 * g_b1 + g_off (g_b1 = 0: one shared matrix)

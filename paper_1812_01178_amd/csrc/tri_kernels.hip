@@ -271,6 +271,25 @@ hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStr
 // (zero-carry pass, combine the chunk maps, exact pass), which is the same
 // elimination as one wavefront per partition with a smaller VGPR footprint.
 // ===========================================================================
+// Workgroup blk -> (line group grp, outer index b1).  Order 0: line groups
+// fastest; 1: outer index fastest; 2: as 0, but workgroups that run on one
+// XCD (dispatched round-robin over the 8 XCDs) take a contiguous range.
+__device__ __forceinline__ void strided_block(const SolveArgs &A, int64_t blk, int64_t &grp, int64_t &b1)
+{
+    int64_t b = blk;
+    if (A.blk_map == 2) {
+        const int64_t nb = A.ngroups0 * A.nb1, per = nb / 8, rem = nb % 8, xcd = blk % 8, idx = blk / 8;
+        b = xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+    }
+    if (A.blk_map == 1) {
+        b1 = b % A.nb1;
+        grp = b / A.nb1;
+    } else {
+        grp = b % A.ngroups0;
+        b1 = b / A.ngroups0;
+    }
+}
+
 template <int CMAX, int METHOD, bool CHUNKED>
 __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, double *lds)
 {
@@ -286,8 +305,8 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     double *pif = bbeg + nw * 64;                // [nw] forward chunk multipliers
     double *pib = pif + nw;                      // [nw] backward chunk multipliers
 
-    const int64_t grp = blk % A.ngroups0;
-    const int64_t b1 = blk / A.ngroups0;
+    int64_t grp, b1;
+    strided_block(A, blk, grp, b1);
     const int64_t b0 = grp * 64 + lane;
     const bool active = b0 < A.nb0;
     const int64_t n = A.n;

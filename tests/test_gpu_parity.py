@@ -371,6 +371,19 @@ def test_strided_chunk_counts(T, ctx, orc, monkeypatch, direction, n, P, per, kc
     assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc) <= TOL
 
 
+@pytest.mark.parametrize("order", [1, 2])
+@pytest.mark.parametrize("direction,n,P,per,kc", [(1, 256, 4, False, 2), (2, 288, 4, True, 1), (1, 96, 3, False, 1)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_strided_workgroup_orders(T, ctx, orc, monkeypatch, order, direction, n, P, per, kc, mname):
+    """Workgroup -> line-group orders the tuner may pick (outer index fastest;
+    contiguous ranges per XCD) on ragged batches (line groups and workgroup
+    counts not multiples of 64 or 8)."""
+    monkeypatch.setenv("TRI_FORCE_KC", str(kc))
+    monkeypatch.setenv("TRI_BLK_MAP", str(order))
+    shape = {1: (7, n, 201), 2: (n, 11, 130)}[direction]
+    assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc) <= TOL
+
+
 @pytest.mark.parametrize("Nx,P,C", [(2048, 8, 4), (2048, 8, 8), (2048, 8, 16), (256, 8, 4), (256, 8, 8),
                                     (256, 8, 16), (512, 2, 16), (384, 4, 8), (1024, 16, 4)])
 @pytest.mark.parametrize("mname", ["PDD", "PPT"])
