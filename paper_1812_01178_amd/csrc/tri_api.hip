@@ -297,6 +297,7 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
 hipError_t run_launch(const Launch &l, int method, hipStream_t s)
 {
     if (l.args.nlines == 0) return hipSuccess;
+    if (l.refine && l.kind == 3) return launch_contig_refine(l.args, l.R, method, l.grid, s);
     if (l.refine) return launch_strided_refine(l.args, l.R, method, l.chunk_max, s);
     if (l.kind == 2) return launch_contig_staged(l.args, method, l.grid, s);
     if (l.kind == 3) return launch_contig_reg(l.args, method, l.grid, s);
@@ -340,6 +341,59 @@ tri_status plan_refine_launch(tri_ctx ctx, const Problem &pb, const Tables &T, L
     return TRI_OK;
 }
 
+// Refinement launch for contiguous rows: the register-factor layout (one line
+// per workgroup, C = 8 or 4 rows per lane), FP32 factors and true rows in
+// registers.
+tri_status plan_contig_refine_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out)
+{
+    const int64_t n = pb.L.n;
+    const int P = pb.P;
+    const int m = (int)(n / P);
+    const bool aligned = ((uintptr_t)pb.L.d % 16 == 0) && pb.L.s_b0 % 2 == 0 &&
+                         (pb.L.nb1 == 1 || pb.L.s_b1 % 2 == 0);
+    if (!(pb.L.s_j == 1 && n > 1 && pb.g_b1 == 0 && n % 2 == 0 && aligned))
+        return fail(ctx, TRI_E_UNSUPPORTED,
+                    "TRI_F32_REFINE for contiguous rows needs one shared matrix and aligned lines of even length");
+    int Lp = 0, C = 0;
+    for (int c : {8, 4})
+        if (reg_split(m, P, c, Lp)) {
+            C = c;
+            break;
+        }
+    if (C == 0)
+        return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE for contiguous rows: no split of m = %d over P = %d", m,
+                    P);
+    SolveArgs a{};
+    a.d = pb.L.d;
+    a.n = n;
+    a.m = m;
+    a.P = P;
+    a.periodic = pb.periodic;
+    a.s_j = 1;
+    a.nb0 = pb.L.nb0;
+    a.nb1 = pb.L.nb1;
+    a.s_b0 = pb.L.s_b0;
+    a.s_b1 = pb.L.s_b1;
+    a.F = T.F;
+    a.IT = T.IT;
+    a.flags = T.flags;
+    a.nlines = pb.L.nb0 * pb.L.nb1;
+    a.lines_linear = (pb.L.nb1 == 1 || pb.L.s_b1 == pb.L.nb0 * pb.L.s_b0) ? 1 : 0;
+    a.C = C;
+    a.Lp = Lp;
+    a.LL = P * Lp;
+    a.LPB = 1;
+    a.stage_stride = 2 * a.LL + (C == 8 ? 8 : 16);
+    out.kind = 3;
+    out.refine = true;
+    out.R = RefineArgs{T.F32, T.ORIG, kRefineMaxSweeps, kRefineTol, ctx->status_dev, ctx->sweeps_dev,
+                       ctx->resid_dev};
+    out.args = a;
+    out.grid = contig_refine_grid(a, pb.method);
+    if (out.grid <= 0) return fail(ctx, TRI_E_HIP, "occupancy query for the contiguous refinement kernel failed");
+    return TRI_OK;
+}
+
 // Restrict a shared-matrix problem to the b1 range [b1_lo, b1_hi).
 Problem sub_b1(const Problem &pb, int64_t b1_lo, int64_t b1_hi)
 {
@@ -363,8 +417,13 @@ tri_status build_launches(tri_ctx ctx, const Problem &pb, const Tables &T, tri_p
         return TRI_OK;
     }
     if (prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
-    if (pb.L.s_j == 1 && pb.L.n > 1)
-        return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE for contiguous rows is not available");
+    if (pb.L.s_j == 1 && pb.L.n > 1) {
+        Launch l;
+        tri_status st = plan_contig_refine_launch(ctx, pb, T, l);
+        if (st) return st;
+        out.push_back(l);
+        return TRI_OK;
+    }
     int64_t split = 0;
     if (pb.fp64_kmax >= 0 && pb.g_b1 == 1) split = std::min<int64_t>(pb.L.nb1, (int64_t)pb.fp64_kmax + 1);
     if (split > 0) {
@@ -931,12 +990,13 @@ tri_status item_problem(tri_ctx ctx, const tri_item &it, int P, Problem &pb)
     return fail(ctx, TRI_E_ARG, "bad item kind %d", it.kind);
 }
 
-// Launches of a plan item.  Contiguous rows have no FP32 kernel: inside a
-// plan they run the FP64 kernel under TRI_F32_REFINE too.
+// Launches of a plan item.  Contiguous rows whose shape the refinement
+// kernel does not take run the FP64 kernel under TRI_F32_REFINE.
 tri_status item_launches(tri_ctx ctx, const Problem &pb, const Tables &T, tri_prec prec,
                          std::vector<Launch> &out, int want = 0)
 {
     const bool contiguous = pb.L.s_j == 1 && pb.L.n > 1;
+    if (prec == TRI_F32_REFINE && contiguous && build_launches(ctx, pb, T, prec, out, want) == TRI_OK) return TRI_OK;
     return build_launches(ctx, pb, T, contiguous ? TRI_F64 : prec, out, want);
 }
 
@@ -1231,7 +1291,7 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
     std::string out;
     for (const Launch &l : it.launches) {
         static const char *const kinds[] = {"strided", "contiguous", "contiguous-staged", "contiguous-reg"};
-        const char *kind = l.refine ? "strided-refine" : kinds[l.kind];
+        const char *kind = l.refine ? (l.kind == 3 ? "contiguous-refine" : "strided-refine") : kinds[l.kind];
         char tmp[200];
         snprintf(tmp, sizeof tmp, "%s%s P=%d m=%d kc=%d Cs=%d C=%d Lp=%d LPB=%d grid=%d lines=%lld", out.empty() ? "" : " + ",
                  kind, it.pb.P, l.args.m, l.args.kc, l.args.Cs, l.args.C, l.args.Lp, l.args.LPB, l.grid,

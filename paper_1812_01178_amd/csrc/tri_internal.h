@@ -165,6 +165,10 @@ size_t strided_refine_lds_bytes(const SolveArgs &a);
 // Ragged batch of refinement solves (same rule with the refinement kernel).
 hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts,
                                        int cmax, int method, size_t lds, hipStream_t s);
+// Refinement for contiguous rows (one shared matrix; register-factor layout).
+hipError_t launch_contig_refine(const SolveArgs &a, const RefineArgs &R, int method, int grid, hipStream_t s);
+size_t contig_refine_lds_bytes(const SolveArgs &a);
+int contig_refine_grid(const SolveArgs &a, int method);
 // Zero the refinement counters with a kernel (safe inside graph capture).
 hipError_t launch_reset_counters(int *sweeps, unsigned long long *resid, hipStream_t s);
 constexpr int kRefineMaxSweeps = 3;

@@ -5,7 +5,7 @@ one by one.  Each solve runs on the pristine input.
 * ADI sweeps on 2048 x 256 x 288: x (PDD, P=8), y (PDD, P=4), periodic z (PDD, P=4)
 * Poisson wavenumber solves 145 x 256 x 2048 complex (PPT, P=4), k = 0 pinned
 * independent systems 4096 x 64 (PDD, P=4, one r per line), all lines
-* FP32 + FP64 refinement of the strided solves, against the exact solution
+* FP32 + FP64 refinement of the x, y, z sweeps and Poisson solves, against the exact solution
 """
 import numpy as np
 import pytest
@@ -58,8 +58,6 @@ def _sample_lines(u_dev, u0, direction, rng, nsamp):
 @pytest.mark.parametrize("prec", ["f64", "refine"])
 @pytest.mark.parametrize("direction", [0, 1, 2])
 def test_fullsize_adi_sweep(T, ctx, orc, field, direction, prec):
-    if prec == "refine" and direction == 0:
-        pytest.skip("contiguous rows have no FP32+refine kernel (TRI_E_UNSUPPORTED)")
     a, b, c = COEF[direction]()
     per = direction == 2
     u = dev(field)

@@ -58,13 +58,16 @@ def _poisson_exact(orc, phihat, ay, cy, lam):
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("direction,n,P,per,coef", [
     (1, 256, 4, False, "stretched"), (2, 288, 4, True, "periodic"), (1, 64, 4, False, "random"),
-    (2, 96, 2, True, "random"), (1, 200, 8, False, "random")])
+    (2, 96, 2, True, "random"), (1, 200, 8, False, "random"),
+    (0, 2048, 8, False, "uniform"), (0, 512, 4, False, "random"), (0, 1024, 16, True, "random"),
+    (0, 256, 8, False, "random")])
 def test_refine_sweeps_match_exact(T, ctx, orc, method, direction, n, P, per, coef):
-    shape = {1: (3, n, 130), 2: (n, 4, 70)}[direction]
+    shape = {0: (5, 7, n), 1: (3, n, 130), 2: (n, 4, 70)}[direction]
     Nz, Ny, Nx = shape
     u = W.cfg_field(Nx, Ny, Nz, seed=21)
     rng = np.random.default_rng(n + P)
     a, b, c = {"stretched": lambda: W.momentum_stretched(n), "periodic": lambda: W.momentum_periodic(n),
+               "uniform": lambda: W.momentum_uniform(n),
                "random": lambda: W.random_tridiag(n, rng, margin=1.0, periodic=per)}[coef]()
     ref = _exact_sweep(orc, direction, u, a, b, c, per)
     du = dev(u)
@@ -138,23 +141,23 @@ def test_refine_reports_non_convergence(T, ctx, orc):
     assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
 
 
-@pytest.mark.parametrize("direction,method", [(1, 0), (2, 1)])
+@pytest.mark.parametrize("direction,method", [(1, 0), (2, 1), (0, 0)])
 def test_refine_any_magnitude(T, ctx, orc, direction, method):
     """Each line's right-hand side is scaled by a power of two before the FP32
     solve, so lines whose values lie far outside FP32's range (here 1e-250 to
     1e250, a different magnitude on every line) still reach the exact solution."""
-    n = {1: 256, 2: 288}[direction]
-    shape = {1: (3, n, 130), 2: (n, 4, 70)}[direction]
+    n = {0: 2048, 1: 256, 2: 288}[direction]
+    shape = {0: (5, 7, n), 1: (3, n, 130), 2: (n, 4, 70)}[direction]
     Nz, Ny, Nx = shape
     rng = np.random.default_rng(17)
     u = W.cfg_field(Nx, Ny, Nz, seed=17)
-    mag = 10.0 ** rng.uniform(-250, 250, size=(Ny, Nx) if direction == 2 else (Nz, Nx))
-    u = u * (mag[None] if direction == 2 else mag[:, None, :])
-    a, b, c = W.momentum_stretched(n) if direction == 1 else W.momentum_periodic(n)
+    mag = 10.0 ** rng.uniform(-250, 250, size={0: (Nz, Ny), 1: (Nz, Nx), 2: (Ny, Nx)}[direction])
+    u = u * {0: mag[:, :, None], 1: mag[:, None, :], 2: mag[None]}[direction]
+    a, b, c = {0: W.momentum_uniform, 1: W.momentum_stretched, 2: W.momentum_periodic}[direction](n)
     ref = _exact_sweep(orc, direction, u, a, b, c, direction == 2)
     du = dev(u)
-    T.adi_sweep(ctx, direction, du, dev(a), dev(b), dev(c), 4, periodic=direction == 2, method=method,
-                prec=T.TRI_F32_REFINE)
+    T.adi_sweep(ctx, direction, du, dev(a), dev(b), dev(c), {0: 8, 1: 4, 2: 4}[direction], periodic=direction == 2,
+                method=method, prec=T.TRI_F32_REFINE)
     T.tri_sync_status(ctx)
     assert line_relerr(host(du), ref, axis=2 - direction) <= TOL
 
