@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-refine", action="store_true", help="skip the FP32+refine measurement")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged eight-sub-grid batch")
+    ap.add_argument("--no-independent", action="store_true", help="skip the independent-systems section")
     ap.add_argument("--nx", type=int, default=NX)
     ap.add_argument("--ny", type=int, default=NY)
     ap.add_argument("--nz", type=int, default=NZ)
@@ -214,6 +215,11 @@ def main():
         torch.cuda.empty_cache()
         ragged = ragged_section(T, oracle, ctx, stream, args)
 
+    # ---------------- independent systems with their own coefficients -----
+    independent = None
+    if not args.no_independent:
+        independent = independent_section(T, oracle, ctx, stream, args)
+
     # ---------------- CPU oracle baseline (bounded sample) ----------------
     cpu = None
     if args.cpu_seconds > 0:
@@ -248,6 +254,7 @@ def main():
         "parity_max_line_rel_err": parity,
         "fp32_refine": refine,
         "ragged_batch": ragged,
+        "independent_systems": independent,
         "cpu_baseline": cpu,
     }
     for p in plans.values():
@@ -394,6 +401,63 @@ def refine_section(T, oracle, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, 
     out["speedup_vs_fp64"] = round(tot_64 / tot_r, 3)
     for p_ in plans.values():
         T.tri_plan_destroy(p_)
+    return out
+
+
+def independent_section(T, oracle, ctx, stream, args):
+    """4096 independent systems of 64 unknowns, a = c = -r, b = 1 + 2r with one
+    r ~ U[0.1, 10] per system, d ~ U[-1, 1] (seed 0), P = 4, lines side by side
+    (row j of system s at j * 4096 + s): FP64 PDD and PPT and FP32 + refinement
+    (PPT inner solver), each checked on every system (PDD against the oracle's
+    PDD at P = 4 and, to show its truncation, against the exact solution; PPT
+    and refinement against the exact solution).  The problem is 2 MB, so the
+    times are launch-level, not bandwidth figures."""
+    import torch
+    import workloads as W
+    n, nlines, P = 64, 4096, 4
+    r, dl = W.cfg_independent(nlines, n, seed=0)
+    d = np.ascontiguousarray(dl.T)
+    a, b, c = -r, 1 + 2 * r, -r
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x)).cuda()
+    da, db, dc, d0 = dev(a), dev(b), dev(c), dev(d)
+    lines = (n, nlines, 1, nlines, 1, 0)
+
+    def ref(method):
+        out = d.copy().ravel()
+        oracle.solve_batch(method, out, n, nlines, 1, nlines, 1, 0, a, b, c, cs_j=0, cs_b0=1, cs_b1=0, P=P)
+        return out.reshape(n, nlines)
+
+    def err(got, want):
+        return float(np.max(np.max(np.abs(got - want), axis=0) / np.max(np.abs(want), axis=0)))
+
+    exact = ref(oracle.EXACT_LD)
+    out = {"systems": nlines, "n": n, "P": P, "unknowns": n * nlines}
+    for name, fn, prec, want in (("pdd_fp64", T.tri_pdd_solve, T.TRI_F64, ref(oracle.PDD)),
+                                 ("ppt_fp64", T.tri_ppt_solve, T.TRI_F64, ref(oracle.PPT)),
+                                 ("ppt_fp32_refine", T.tri_ppt_solve, T.TRI_F32_REFINE, exact)):
+        x = d0.clone()
+        info = fn(ctx, da, db, dc, x, lines, coef_strides=(0, 1, 0), P=P, prec=prec, info=True)
+        T.tri_sync_status(ctx)
+        got = x.cpu().numpy()
+        reps = 50
+        for _ in range(3):
+            fn(ctx, da, db, dc, x, lines, coef_strides=(0, 1, 0), P=P, prec=prec)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn(ctx, da, db, dc, x, lines, coef_strides=(0, 1, 0), P=P, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        res = {"us_per_solve": round(us, 2), "unknowns_per_s": n * nlines / (us * 1e-6),
+               "parity_max_line_rel_err": err(got, want)}
+        if name == "pdd_fp64":
+            res["max_line_rel_err_vs_exact"] = err(got, exact)
+        if prec == T.TRI_F32_REFINE:
+            res["sweeps"] = info["sweeps"]
+        out[name] = res
+        log(f"independent {name}: {us:.1f} us per solve, parity {res['parity_max_line_rel_err']:.2e}")
     return out
 
 

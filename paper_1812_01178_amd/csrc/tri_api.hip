@@ -514,8 +514,6 @@ tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info, bool refined 
 tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *info)
 {
     if (prec != TRI_F64 && prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
-    if (prec == TRI_F32_REFINE && pb.general)
-        return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE with per-line coefficients is not available");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const int64_t nlines = pb.L.nb0 * pb.L.nb1;
     if (nlines == 0) {
@@ -550,6 +548,16 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
         g.cs_b0 = pb.cs_b0;
         g.cs_b1 = pb.cs_b1;
         g.status = ctx->status_dev;
+        if (prec == TRI_F32_REFINE) {
+            if (m > kGeneralRefineMaxM || pb.P > 8)
+                return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE with per-line coefficients needs m <= %d, P <= 8",
+                            kGeneralRefineMaxM);
+            const RefineArgs R{nullptr, nullptr, kRefineMaxSweeps, kRefineTol, ctx->status_dev, ctx->sweeps_dev,
+                               ctx->resid_dev};
+            HIP_TRY(ctx, launch_reset_counters(ctx->sweeps_dev, ctx->resid_dev, ctx->stream));
+            HIP_TRY(ctx, launch_general_refine(g, R, pb.method, ctx->stream));
+            return fill_info(ctx, nullptr, info, true);
+        }
         HIP_TRY(ctx, launch_general(g, pb.method, ctx->stream));
         return fill_info(ctx, nullptr, info);
     }

@@ -50,4 +50,79 @@ __device__ __forceinline__ void interface_unknowns(ItPtr it, int r, int P, int p
     }
 }
 
+// ===========================================================================
+// Reduced systems of per-line coefficients (general kernels): one per lane.
+// ===========================================================================
+constexpr int kGenKMax = 2 * kPMax;        // banded reduced system (non-periodic)
+constexpr int kGenKDense = 8;              // dense reduced system (periodic, P <= 4)
+
+// Tridiagonal Gaussian elimination with partial pivoting (row interchanges
+// between neighbours, one extra superdiagonal of fill), K <= kGenKMax.
+// dl[k]: entry (k+1, k), dd[k]: (k, k), du[k]: (k, k+1).  rhs -> solution.
+__device__ inline bool gtsv_pivot(int K, double *dl, double *dd, double *du, double *rhs)
+{
+    double du2[kGenKMax];
+    for (int k = 0; k < K - 1; ++k) {
+        if (fabs(dd[k]) >= fabs(dl[k])) {
+            if (dd[k] == 0.0) return false;
+            const double l = dl[k] / dd[k];
+            dd[k + 1] -= l * du[k];
+            rhs[k + 1] -= l * rhs[k];
+            du2[k] = 0.0;
+        } else {
+            const double l = dd[k] / dl[k];
+            const double old_ddk1 = dd[k + 1];
+            dd[k] = dl[k];
+            dd[k + 1] = du[k] - l * old_ddk1;
+            du[k] = old_ddk1;
+            if (k < K - 2) {
+                du2[k] = du[k + 1];
+                du[k + 1] = -l * du2[k];
+            } else {
+                du2[k] = 0.0;
+            }
+            const double rk = rhs[k];
+            rhs[k] = rhs[k + 1];
+            rhs[k + 1] = rk - l * rhs[k];
+        }
+    }
+    if (dd[K - 1] == 0.0) return false;
+    rhs[K - 1] /= dd[K - 1];
+    if (K >= 2) rhs[K - 2] = (rhs[K - 2] - du[K - 2] * rhs[K - 1]) / dd[K - 2];
+    for (int k = K - 3; k >= 0; --k)
+        rhs[k] = (rhs[k] - du[k] * rhs[k + 1] - du2[k] * rhs[k + 2]) / dd[k];
+    return true;
+}
+
+// Dense Gaussian elimination with partial pivoting, K <= kGenKDense.
+__device__ inline bool dense_gepp(int K, double *M, double *rhs)
+{
+    for (int k = 0; k < K; ++k) {
+        int p = k;
+        double best = fabs(M[k * kGenKDense + k]);
+        for (int i = k + 1; i < K; ++i)
+            if (fabs(M[i * kGenKDense + k]) > best) { best = fabs(M[i * kGenKDense + k]); p = i; }
+        if (best == 0.0) return false;
+        if (p != k) {
+            for (int t = k; t < K; ++t) {
+                const double s = M[k * kGenKDense + t];
+                M[k * kGenKDense + t] = M[p * kGenKDense + t];
+                M[p * kGenKDense + t] = s;
+            }
+            const double s = rhs[k]; rhs[k] = rhs[p]; rhs[p] = s;
+        }
+        for (int i = k + 1; i < K; ++i) {
+            const double l = M[i * kGenKDense + k] / M[k * kGenKDense + k];
+            for (int t = k + 1; t < K; ++t) M[i * kGenKDense + t] -= l * M[k * kGenKDense + t];
+            rhs[i] -= l * rhs[k];
+        }
+    }
+    for (int k = K - 1; k >= 0; --k) {
+        double s = rhs[k];
+        for (int t = k + 1; t < K; ++t) s -= M[k * kGenKDense + t] * rhs[t];
+        rhs[k] = s / M[k * kGenKDense + k];
+    }
+    return true;
+}
+
 }  // namespace tri

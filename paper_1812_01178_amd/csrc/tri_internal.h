@@ -169,6 +169,8 @@ hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int
 hipError_t launch_contig_refine(const SolveArgs &a, const RefineArgs &R, int method, int grid, hipStream_t s);
 size_t contig_refine_lds_bytes(const SolveArgs &a);
 int contig_refine_grid(const SolveArgs &a, int method);
+// Refinement for per-line coefficients (general layout, m <= kGeneralRefineMaxM, P <= 8).
+hipError_t launch_general_refine(const GeneralArgs &a, const RefineArgs &R, int method, hipStream_t s);
 // Zero the refinement counters with a kernel (safe inside graph capture).
 hipError_t launch_reset_counters(int *sweeps, unsigned long long *resid, hipStream_t s);
 constexpr int kRefineMaxSweeps = 3;
@@ -179,6 +181,7 @@ constexpr double kRefineTol = 1e-13;
 constexpr int kStridedMaxC = 80;     // rows per wavefront chunk
 constexpr int kContigMaxC = 16;
 constexpr int kGeneralMaxM = 32;
+constexpr int kGeneralRefineMaxM = 16;
 constexpr int kGeneralPPTMaxP = 8;
 
 // Status word bits (device).

@@ -174,6 +174,79 @@ def test_refine_poisson_large_values(T, ctx, orc):
     assert line_relerr(host(dphi), ref, axis=1) <= TOL
 
 
+def _cfg1(seed, rmax=None):
+    n, nlines = 64, 4096
+    r, dl = W.cfg_independent(nlines, n, seed=seed)
+    if rmax is not None:
+        r = 0.1 + (r - 0.1) * (rmax - 0.1) / 9.9
+    d = np.ascontiguousarray(dl.T)                       # [j][line]
+    return n, nlines, r, d
+
+
+def _cfg1_exact(orc, n, nlines, r, d):
+    ref = d.copy().ravel()
+    orc.solve_batch(orc.EXACT_LD, ref, n, nlines, 1, nlines, 1, 0, -r, 1 + 2 * r, -r, cs_j=0, cs_b0=1, cs_b1=0)
+    return ref.reshape(n, nlines)
+
+
+def test_refine_independent_lines_ppt(T, ctx, orc):
+    """Independent systems with their own coefficients (4096 x 64, r ~ U[0.1, 10],
+    P = 4): FP32 blocks + FP64 refinement with the PPT inner solver reach the
+    exact solution."""
+    n, nlines, r, d = _cfg1(0)
+    ref = _cfg1_exact(orc, n, nlines, r, d)
+    dd = dev(d)
+    info = T.tri_ppt_solve(ctx, dev(-r), dev(1 + 2 * r), dev(-r), dd, (n, nlines, 1, nlines, 1, 0),
+                           coef_strides=(0, 1, 0), P=4, prec=T.TRI_F32_REFINE, info=True)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dd), ref, axis=0) <= TOL
+    assert 1 <= info["sweeps"] <= 3
+
+
+def test_refine_independent_lines_pdd_inner(T, ctx, orc):
+    """With the PDD inner solver the refinement converges to the exact solution
+    where PDD's dropped entries are small (r <= 1: below 5e-8); on the full
+    r range (dropped entries up to 3e-3) three refinements cannot reach the
+    tolerance and the status says so."""
+    n, nlines, r, d = _cfg1(1, rmax=1.0)
+    ref = _cfg1_exact(orc, n, nlines, r, d)
+    dd = dev(d)
+    T.tri_pdd_solve(ctx, dev(-r), dev(1 + 2 * r), dev(-r), dd, (n, nlines, 1, nlines, 1, 0),
+                    coef_strides=(0, 1, 0), P=4, prec=T.TRI_F32_REFINE)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dd), ref, axis=0) <= TOL
+    n, nlines, r, d = _cfg1(0)
+    dd = dev(d)
+    T.tri_pdd_solve(ctx, dev(-r), dev(1 + 2 * r), dev(-r), dd, (n, nlines, 1, nlines, 1, 0),
+                    coef_strides=(0, 1, 0), P=4, prec=T.TRI_F32_REFINE)
+    with pytest.raises(T.TriError) as e:
+        T.tri_sync_status(ctx)
+    assert e.value.status == T.TRI_E_NOT_CONVERGED
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+@pytest.mark.parametrize("n,P", [(48, 4), (16, 2), (96, 8)])
+def test_refine_general_per_element(T, ctx, orc, periodic, n, P):
+    """Fully general rows (a, b, c per element), PPT inner solver."""
+    if periodic and P > 4:
+        pytest.skip("per-line periodic PPT takes P <= 4")
+    nlines = 130
+    rng = np.random.default_rng(41 + n)
+    A = np.empty((nlines, n)); B = np.empty((nlines, n)); C = np.empty((nlines, n))
+    for s in range(nlines):
+        A[s], B[s], C[s] = W.random_tridiag(n, rng, margin=0.5, periodic=periodic)
+    D = rng.uniform(-1, 1, (n, nlines))
+    At, Bt, Ct = (np.ascontiguousarray(X.T) for X in (A, B, C))
+    ref = D.copy().ravel()
+    orc.solve_batch(orc.EXACT_LD, ref, n, nlines, 1, s_j=nlines, s_b0=1, s_b1=0,
+                    a=At.ravel(), b=Bt.ravel(), c=Ct.ravel(), cs_j=nlines, cs_b0=1, cs_b1=0, periodic=periodic)
+    dd = dev(D)
+    T.tri_ppt_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0), coef_strides=(nlines, 1, 0),
+                    P=P, periodic=periodic, prec=T.TRI_F32_REFINE)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
+
+
 @pytest.mark.parametrize("kc", [2, 4, 8])
 def test_refine_chunk_counts(T, ctx, orc, monkeypatch, kc):
     monkeypatch.setenv("TRI_FORCE_KC", str(kc))
