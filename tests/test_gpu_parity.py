@@ -271,6 +271,34 @@ def test_minimal_partitions(T, ctx, orc, n, P):
         assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
 
 
+@pytest.mark.parametrize("direction,n,P,per", [(1, 640, 4, False), (1, 640, 16, False), (2, 640, 8, True),
+                                           (1, 640, 1, False), (0, 4096, 8, False), (0, 8192, 16, False)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_longest_supported_lines(T, ctx, orc, direction, n, P, per, mname):
+    """The longest lines each layout takes: strided lines of 640 rows (at most
+    16 wavefronts of at most 80 rows, 40 above 8 wavefronts); contiguous lines
+    of 4096 (register-factor kernel, P = 8) and 8192 (1024 lanes of 8 rows,
+    P = 16)."""
+    shape = {0: (3, 5, n), 1: (2, n, 70), 2: (n, 3, 70)}[direction]
+    rng = np.random.default_rng(n + P)
+    coef = W.random_tridiag(n, rng, margin=0.7, periodic=per)
+    assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc, coef=coef) <= TOL
+
+
+@pytest.mark.parametrize("direction,n,P", [(1, 656, 4), (1, 656, 16), (0, 16384, 16)])
+def test_lines_beyond_the_limits_are_refused(T, ctx, direction, n, P):
+    """One step past the longest supported lines: TRI_E_UNSUPPORTED, data untouched."""
+    shape = {0: (1, 2, n), 1: (1, n, 64)}[direction]
+    u0 = np.arange(np.prod(shape), dtype=np.float64).reshape(shape)
+    du = dev(u0)
+    a, b, c = (dev(v) for v in W.momentum_uniform(n))
+    with pytest.raises(T.TriError) as e:
+        T.adi_sweep(ctx, direction, du, a, b, c, P)
+    assert e.value.status == T.TRI_E_UNSUPPORTED
+    T.tri_sync_status(ctx)
+    assert np.array_equal(host(du), u0)
+
+
 def test_shape_errors_leave_data_untouched(T, ctx):
     d0 = np.arange(60.0).reshape(12, 5)
     dd = dev(d0)
