@@ -883,7 +883,7 @@ std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
 }  // namespace
 
 // One execution of `ls` (the launches of problem pb) timed on a zero-filled
-// scratch buffer with pb's layout: best of three, in ms, or -1 on failure.
+// scratch buffer with pb's layout: best of seven, in ms, or -1 on failure.
 static float time_on_scratch(tri_ctx ctx, const Problem &pb, std::vector<Launch> ls)
 {
     const LineSet &L = pb.L;
@@ -901,7 +901,7 @@ static float time_on_scratch(tri_ctx ctx, const Problem &pb, std::vector<Launch>
     };
     float best = 1e30f;
     if (ok) ok = run_all();
-    for (int rep = 0; ok && rep < 3; ++rep) {
+    for (int rep = 0; ok && rep < 7; ++rep) {
         float t = 0.f;
         ok = hipEventRecord(e0, ctx->stream) == hipSuccess && run_all() &&
              hipEventRecord(e1, ctx->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
