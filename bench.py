@@ -5,7 +5,7 @@ Workload (synthetic, seeded, boundary-layer shaped; 2048 x 256 x 288 cells):
   * ADI momentum sweeps over u[Nz][Ny][Nx] (x fastest), FP64, PDD:
       x: lines of 2048, contiguous, P = 8, uniform mesh, r = dt*nu/dx^2
       y: lines of 256, stride Nx, P = 4, tanh-stretched wall-normal mesh
-      z: lines of 288, stride Nx*Ny, periodic, P = 4
+      z: lines of 288, stride Nx*Ny, periodic, P = 16
   * Poisson wavenumber solves, FP64, PPT, P = 4: spanwise rFFT of an N(0,1)
     field (input preparation, host, untimed) -> 145 x 256 x 2048 complex;
     k = 0 gauge pinned.
@@ -72,7 +72,10 @@ def build_inputs(nx, ny, nz):
 ITEMS = [  # name, direction, P, periodic, method
     ("adi_x", 0, 8, False, "PDD"),
     ("adi_y", 1, 4, False, "PDD"),
-    ("adi_z", 2, 4, True, "PDD"),
+    # spanwise lines: 16 partitions of 18 rows (PDD drops entries ~1e-21 at
+    # r = 0.083, so the result is the exact solution to round-off), which lets
+    # the kernel run one 16-byte-access wavefront per partition
+    ("adi_z", 2, 16, True, "PDD"),
     ("poisson", None, 4, False, "PPT"),
 ]
 
@@ -303,13 +306,19 @@ def measured_traffic(item, launch):
     return None
 
 
+REFINE_P = {"adi_z": 4}
+
+
 def refine_section(T, oracle, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef, u0, phi0,
                    ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, fp64_ms):
     """FP32 elimination + FP64 residual refinement (Poisson modes k <= 2 in
     FP64) on the step's four solves, timed like the FP64 step and checked
     against the oracle's exact solution (extended precision) on sampled lines."""
     import torch
-    items = list(ITEMS)
+    # the refined result is the exact solution whatever the inner solver's
+    # partition count; the refinement kernel takes at most 8 wavefronts of
+    # more than 8 rows, so the spanwise lines use P = 4 here
+    items = [(nm, d, REFINE_P.get(nm, P), per, meth) for nm, d, P, per, meth in ITEMS]
     plans, descr = {}, {}
     for name, direction, P, per, meth in items:
         if name == "poisson":
@@ -604,21 +613,21 @@ def cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, target_s):
         qz = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(u0[::qz])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], 8, False, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], ITEMS[0][2], False, nthreads=cores)
         t_item["adi_x"], n_item["adi_x"] = time.perf_counter() - t0, sub.size
         sub = np.ascontiguousarray(u0[::qz])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], 4, False, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], ITEMS[1][2], False, nthreads=cores)
         t_item["adi_y"], n_item["adi_y"] = time.perf_counter() - t0, sub.size
         qy = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(u0[:, ::qy])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], 4, True, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], ITEMS[2][2], True, nthreads=cores)
         t_item["adi_z"], n_item["adi_z"] = time.perf_counter() - t0, sub.size
         qk = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(phi0[::qk])
         t0 = time.perf_counter()
-        oracle.poisson(sub, ay, cy, lam[::qk], P=4, nthreads=cores)
+        oracle.poisson(sub, ay, cy, lam[::qk], P=ITEMS[3][2], nthreads=cores)
         t_item["poisson"], n_item["poisson"] = time.perf_counter() - t0, sub.size
         return t_item, n_item
 

@@ -154,6 +154,14 @@ tri_status check_partition(tri_ctx ctx, int64_t n, int P, int periodic)
     return TRI_OK;
 }
 
+// Two lines per lane (k_strided2): neighbouring lines adjacent in memory,
+// pairs 16-byte aligned, one wavefront per partition of at most 24 rows.
+bool strided2_ok(const Problem &pb, int m)
+{
+    return pb.L.s_b0 == 1 && pb.L.s_j % 2 == 0 && (uintptr_t)pb.L.d % 16 == 0 &&
+           (pb.L.nb1 == 1 || pb.L.s_b1 % 2 == 0) && m <= 24 && pb.P <= 16;
+}
+
 int pick_chunk(int c)
 {
     static const int inst[] = {8, 16, 24, 32, 40, 48, 56, 64, 72, 80};
@@ -187,8 +195,10 @@ int pick_kc(int m, int P, int want_kc)
 tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out, int want = 0)
 {
     // strided tuning values: chunks per partition + 100 * workgroup order
+    // (+ 1000: two lines per lane)
     const int want_kc = want ? want % 100 : env_int("TRI_FORCE_KC", 0);
-    const int want_map = want ? want / 100 : env_int("TRI_BLK_MAP", 0);
+    const int want_map = want ? (want / 100) % 10 : env_int("TRI_BLK_MAP", 0);
+    const int want_lpl = want ? 1 + want / 1000 : 1 + (env_int("TRI_LPL", 1) == 2);
     const int want_c = want ? want : env_int("TRI_FORCE_C", 0);
     const int64_t n = pb.L.n;
     const int P = pb.P;
@@ -285,10 +295,18 @@ tri_status plan_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &
         a.kc = kc;
         a.Cs = m / kc;
         const int cmax = pick_chunk(a.Cs);
-        a.ngroups0 = (pb.L.nb0 + 63) / 64;
+        a.lpl = 1;
+        if (want_lpl == 2) {
+            if (!strided2_ok(pb, m))
+                return fail(ctx, TRI_E_UNSUPPORTED, "two lines per lane need adjacent 16-byte pairs, m = %d <= 24", m);
+            a.lpl = 2;
+            a.kc = 1;
+            a.Cs = m;
+        }
+        a.ngroups0 = (pb.L.nb0 + 64 * a.lpl - 1) / (64 * a.lpl);
         a.blk_map = (want_map == 1 || want_map == 2) ? want_map : 0;
         out.kind = 0;
-        out.chunk_max = cmax;
+        out.chunk_max = a.lpl == 2 ? pick_chunk(m) : cmax;
     }
     out.args = a;
     return TRI_OK;
@@ -301,6 +319,7 @@ hipError_t run_launch(const Launch &l, int method, hipStream_t s)
     if (l.refine) return launch_strided_refine(l.args, l.R, method, l.chunk_max, s);
     if (l.kind == 2) return launch_contig_staged(l.args, method, l.grid, s);
     if (l.kind == 3) return launch_contig_reg(l.args, method, l.grid, s);
+    if (l.kind == 0 && l.args.lpl == 2) return launch_strided2(l.args, method, l.chunk_max, s);
     return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
 }
 
@@ -870,6 +889,10 @@ std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
                 c.push_back(kc + 200);
                 ++nk;
             }
+        if (strided2_ok(pb, m)) {   // two lines per lane, one wavefront per partition
+            c.push_back(1001);
+            c.push_back(1201);
+        }
     } else if (base.kind == 2 || base.kind == 3) {
         int Lp, C;
         for (int want : {4, 8, 16})
@@ -1062,7 +1085,7 @@ Span launch_span(const SolveArgs &a)
 // Strided launches can join a batch of launches that run the same kernel
 // instance: the key holds refinement, chunk instance (CMAX), method,
 // chunking and wavefronts per workgroup.
-bool batchable(const Launch &l) { return l.kind == 0 && l.args.nlines > 0; }
+bool batchable(const Launch &l) { return l.kind == 0 && l.args.nlines > 0 && l.args.lpl <= 1; }
 
 int64_t batch_key(const Launch &l, int method)
 {

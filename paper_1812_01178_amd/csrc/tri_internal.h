@@ -86,6 +86,7 @@ struct SolveArgs {
     int64_t ngroups0;      // strided kernel: ceil(nb0 / 64)
     int kc;                // strided kernel: chunks (wavefronts) per partition
     int blk_map;           // strided kernel: workgroup -> (line group, b1) order, see strided_block
+    int lpl;               // strided kernel: lines per lane (1, or 2 with 16-byte accesses)
     int Cs;                // strided kernel: rows per chunk, m / kc
     int64_t zero;          // always 0 (keeps the compiler from caching factor loads across passes)
     int64_t g_b1;          // matrix index = b1 * g_b1 + g_off (g_b1 = 0: one shared matrix)
@@ -143,6 +144,9 @@ struct GeneralArgs {
 hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s);
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
 size_t strided_lds_bytes(const SolveArgs &a);
+// Two lines per lane (adjacent lines, s_b0 = 1, 16-byte aligned pairs), one
+// chunk per partition (kc = 1), m <= 24.
+hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
 // Ragged batch (device table of `count` entries, sorted by begin; every
 // entry would run the single-problem kernel instance <cmax, method,
 // chunked> with P * kc == wavefronts).

@@ -427,6 +427,131 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
 }
 
 // ===========================================================================
+// Strided solve with two neighbouring lines per lane: every row access of a
+// wavefront is one 1-KB segment of 16-byte lane accesses (the strided
+// kernel's 512-B segments of 8-byte accesses move less per request when rows
+// are far apart, as in the spanwise direction), and each lane runs the two
+// lines' recurrences side by side on the same wavefront-uniform factors.
+// One wavefront per partition (kc = 1), rows kept in VGPRs load -> store.
+// ===========================================================================
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
+{
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x & 63;
+    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int P = A.P, m = A.m;
+    double *tips = lds;                                     // [2P][128]
+    int64_t grp, b1;
+    strided_block(A, blockIdx.x, grp, b1);
+    const int64_t b0 = grp * 128 + 2 * lane;
+    const bool act0 = b0 < A.nb0, act1 = b0 + 1 < A.nb0;
+    const int64_t n = A.n;
+    const int64_t g = b1 * A.g_b1 + A.g_off;
+    const int64_t row0 = (int64_t)r * m;
+    const gdouble *__restrict__ F = (const gdouble *)(A.F + g * (kNumFactors * n) + row0);
+    const gdouble *__restrict__ Fb = F;
+    const gdouble *__restrict__ Fa = F + n;
+    const gdouble *__restrict__ Fc = F + 2 * n;
+    const gdouble *__restrict__ Fv = F + 3 * n;
+    const gdouble *__restrict__ Fw = F + 4 * n;
+    const int64_t sj = A.s_j;
+    gdouble *__restrict__ p = (gdouble *)(A.d + (act0 ? b0 : 0) + b1 * A.s_b1 + row0 * sj);
+
+    double x0[CMAX], x1[CMAX];
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+        x0[t] = 0.0;
+        x1[t] = 0.0;
+        if (t < m) {
+            if (act1) {
+                const v2d v = __builtin_nontemporal_load((const __attribute__((address_space(1))) v2d *)(p + t * sj));
+                x0[t] = v.x;
+                x1[t] = v.y;
+            } else if (act0) {
+                x0[t] = __builtin_nontemporal_load(p + t * sj);
+            }
+        }
+    }
+    if (r == 0 && (((const gint *)A.flags)[g] & 1)) {
+        x0[0] = 0.0;
+        x1[0] = 0.0;
+    }
+    // Eq. (5) for both lines with the shared pivots
+    double g0 = 0.0, g1 = 0.0;
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < m) {
+            g0 = Fb[t] * x0[t] - Fa[t] * g0;
+            g1 = Fb[t] * x1[t] - Fa[t] * g1;
+            x0[t] = g0;
+            x1[t] = g1;
+        }
+    const double l0 = g0, l1 = g1;
+    double n0 = 0.0, n1 = 0.0;
+#pragma unroll
+    for (int t = CMAX - 1; t >= 0; --t)
+        if (t < m) {
+            n0 = x0[t] - Fc[t] * n0;
+            n1 = x1[t] - Fc[t] * n1;
+            x0[t] = n0;
+            x1[t] = n1;
+        }
+    tips[(2 * r) * 128 + 2 * lane] = x0[0];
+    tips[(2 * r) * 128 + 2 * lane + 1] = x1[0];
+    tips[(2 * r + 1) * 128 + 2 * lane] = l0;
+    tips[(2 * r + 1) * 128 + 2 * lane + 1] = l1;
+    __syncthreads();
+    const gdouble *__restrict__ it = (const gdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
+    double yl0, yr0, yl1, yr1;
+    interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 128 + 2 * lane]; }, yl0, yr0);
+    interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 128 + 2 * lane + 1]; }, yl1, yr1);
+    // Eq. (8) / (11), every row corrected before the first store
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < m) {
+            x0[t] = x0[t] - yl0 * Fv[t] - yr0 * Fw[t];
+            x1[t] = x1[t] - yl1 * Fv[t] - yr1 * Fw[t];
+        }
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t)
+        if (t < m) {
+            if (act1) {
+                v2d v;
+                v.x = x0[t];
+                v.y = x1[t];
+                __builtin_nontemporal_store(v, (__attribute__((address_space(1))) v2d *)(p + t * sj));
+            } else if (act0) {
+                __builtin_nontemporal_store(x0[t], p + t * sj);
+            }
+        }
+}
+
+hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStream_t s)
+{
+    const int64_t blocks = a.ngroups0 * a.nb1;
+    const size_t lds = sizeof(double) * 2 * (size_t)a.P * 128;
+    const dim3 grid((unsigned)blocks), block(64 * a.P);
+    const bool pdd = method == TRI_PDD;
+    switch (chunk_max) {
+    case 8:
+        if (pdd) hipLaunchKernelGGL((k_strided2<8, TRI_PDD>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_strided2<8, TRI_PPT>), grid, block, lds, s, a);
+        break;
+    case 16:
+        if (pdd) hipLaunchKernelGGL((k_strided2<16, TRI_PDD>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_strided2<16, TRI_PPT>), grid, block, lds, s, a);
+        break;
+    case 24:
+        if (pdd) hipLaunchKernelGGL((k_strided2<24, TRI_PDD>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_strided2<24, TRI_PPT>), grid, block, lds, s, a);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ===========================================================================
 // Ragged batch of strided solves in one launch.  Each entry of the device
 // table is a complete strided problem (its own line length, strides,
 // partition count, factor tables); workgroup b runs block b - begin of the

@@ -412,6 +412,58 @@ def test_strided_workgroup_orders(T, ctx, orc, monkeypatch, order, direction, n,
     assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc) <= TOL
 
 
+@pytest.mark.parametrize("direction,n,P,per", [(1, 64, 4, False), (2, 288, 16, True), (1, 96, 4, False),
+                                           (2, 48, 2, True), (1, 256, 16, False)])
+@pytest.mark.parametrize("mname", ["PDD", "PPT"])
+def test_strided_two_lines_per_lane(T, ctx, orc, monkeypatch, direction, n, P, per, mname):
+    """Two neighbouring lines per lane (16-byte accesses), one wavefront per
+    partition (line counts that are not multiples of 128)."""
+    monkeypatch.setenv("TRI_LPL", "2")
+    monkeypatch.setenv("TRI_FORCE_KC", "1")
+    shape = {1: (3, n, 130), 2: (n, 5, 130)}[direction]
+    assert _sweep_case(direction, *shape, P, per, mname, T, ctx, orc) <= TOL
+
+
+@pytest.mark.parametrize("mname,method", METHODS)
+def test_strided_two_lines_per_lane_odd_tail(T, ctx, orc, monkeypatch, mname, method):
+    """An odd number of adjacent lines (131) in rows padded to 132: the last
+    lane holds one line and uses 8-byte accesses."""
+    monkeypatch.setenv("TRI_LPL", "2")
+    monkeypatch.setenv("TRI_FORCE_KC", "1")
+    n, P, nb0, nb1, sj = 64, 4, 131, 3, 132
+    rng = np.random.default_rng(91)
+    a, b, c = W.random_tridiag(n, rng, margin=0.6, periodic=False)
+    buf = rng.standard_normal(n * sj * nb1)
+    ref = buf.copy()
+    orc.solve_batch(_oracle_method(orc, mname), ref, n, nb0, nb1, s_j=sj, s_b0=1, s_b1=n * sj,
+                    a=a, b=b, c=c, cs_j=1, cs_b0=0, cs_b1=0, P=P)
+    dd = dev(buf)
+    fn = T.tri_pdd_solve if method == 0 else T.tri_ppt_solve
+    fn(ctx, dev(a), dev(b), dev(c), dd, (n, nb0, nb1, sj, 1, n * sj), coef_strides=(1, 0, 0), P=P)
+    T.tri_sync_status(ctx)
+    got = host(dd)
+    idx = (np.arange(nb1)[:, None, None] * n * sj + np.arange(n)[None, :, None] * sj +
+           np.arange(nb0)[None, None, :])
+    assert line_relerr(got[idx], ref[idx], axis=1) <= TOL
+    pad = np.ones(buf.size, bool)
+    pad[idx.ravel()] = False
+    assert np.array_equal(got[pad], buf[pad])            # padding untouched
+
+
+def test_poisson_two_lines_per_lane(T, ctx, orc, monkeypatch):
+    monkeypatch.setenv("TRI_LPL", "2")
+    monkeypatch.setenv("TRI_FORCE_KC", "1")
+    Nx, Ny, Nz, P = 70, 256, 24, 16
+    phihat = W.cfg_poisson_rhs(Nx, Ny, Nz, seed=5)
+    ay, cy = W.poisson_metric(Ny)
+    lam = W.modified_wavenumbers(Nz)
+    ref = phihat.copy()
+    orc.poisson(ref, ay, cy, lam, P=P)
+    dphi = torch.as_tensor(phihat).cuda()
+    T.poisson_wavenumber_solve(ctx, dphi, dev(ay), dev(cy), dev(lam), P=P)
+    assert line_relerr(host(dphi), ref, axis=1) <= TOL
+
+
 @pytest.mark.parametrize("Nx,P,C", [(2048, 8, 4), (2048, 8, 8), (2048, 8, 16), (256, 8, 4), (256, 8, 8),
                                     (256, 8, 16), (512, 2, 16), (384, 4, 8), (1024, 16, 4)])
 @pytest.mark.parametrize("mname", ["PDD", "PPT"])
