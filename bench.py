@@ -202,8 +202,19 @@ def main():
                       "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
                       "unknowns_per_s": unknowns[n] / (per_item_ms[n] * 1e-3)}
         log(f"{n}: {per_item_ms[n]:.4f} ms  {gbs:.0f} GB/s  ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    for i, n in enumerate(names):
+        kernels[n]["ms_median"] = round(float(np.median([ev[s][i].elapsed_time(ev[s][i + 1])
+                                                         for s in range(args.steps)])), 4)
     dom = max(names, key=lambda n: per_item_ms[n])
     step_bytes = sum(unknowns[n] * bytes_per[n] for n in names)
+
+    # ---------------- copy ceiling: the library's reference copy ----------
+    # (u <- du0 moves the same 16 B per unknown as a solve of the field)
+    copy = copy_ceiling(T, ctx, stream, u, du0, max(args.steps, 20))
+    for n in names:
+        kernels[n]["copy_frac"] = round(kernels[n]["GB_s"] / copy["GB_s"], 4)
+    log(f"reference copy: {copy['GB_s']:.0f} GB/s ({copy['bytes'] / 1e9:.3f} GB per call); "
+        + ", ".join(f"{n} {100 * kernels[n]['copy_frac']:.1f}%" for n in names) + " of it")
 
     # ---------------- FP32 elimination + FP64 refinement -----------------
     refine = None
@@ -253,7 +264,9 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["GB_s"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(kernels[dom]["GB_s"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(dom, T.tri_plan_item_describe(plans[dom], 0))},
+                     "traffic": measured_traffic(dom, T.tri_plan_item_describe(plans[dom], 0)),
+                     "copy_GB_s": copy["GB_s"], "copy_frac": kernels[dom]["copy_frac"]},
+        "copy_ceiling": copy,
         "parity_max_line_rel_err": parity,
         "fp32_refine": refine,
         "ragged_batch": ragged,
@@ -264,6 +277,28 @@ def main():
         T.tri_plan_destroy(p)
     T.tri_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+def copy_ceiling(T, ctx, stream, dst, src, reps):
+    """Median rate of the library's reference copy (tri_stream_copy) of the
+    whole field, read + write bytes per second, HIP events on the context
+    stream."""
+    import torch
+    n = src.numel()
+    for _ in range(3):
+        T.tri_stream_copy(ctx, dst, src, n)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        T.tri_stream_copy(ctx, dst, src, n)
+        b.record(stream)
+    torch.cuda.synchronize()
+    T.tri_sync_status(ctx)
+    ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    nbytes = 2 * n * 8
+    return {"kernel": "tri_stream_copy (one pass, 16-byte non-temporal loads and stores)",
+            "bytes": nbytes, "ms_median": round(ms, 4), "GB_s": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "hbm_frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2048x256x288.md")
@@ -607,27 +642,27 @@ def cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, target_s):
     Nz, Ny, Nx = u0.shape
     Nk = phi0.shape[0]
 
-    def run(frac_outer):
+    def run(frac_outer, threads=cores):
         t_item, n_item = {}, {}
         # x lines: sample z-planes
         qz = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(u0[::qz])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], ITEMS[0][2], False, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], ITEMS[0][2], False, nthreads=threads)
         t_item["adi_x"], n_item["adi_x"] = time.perf_counter() - t0, sub.size
         sub = np.ascontiguousarray(u0[::qz])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], ITEMS[1][2], False, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], ITEMS[1][2], False, nthreads=threads)
         t_item["adi_y"], n_item["adi_y"] = time.perf_counter() - t0, sub.size
         qy = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(u0[:, ::qy])
         t0 = time.perf_counter()
-        oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], ITEMS[2][2], True, nthreads=cores)
+        oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], ITEMS[2][2], True, nthreads=threads)
         t_item["adi_z"], n_item["adi_z"] = time.perf_counter() - t0, sub.size
         qk = max(1, int(round(1 / frac_outer)))
         sub = np.ascontiguousarray(phi0[::qk])
         t0 = time.perf_counter()
-        oracle.poisson(sub, ay, cy, lam[::qk], P=ITEMS[3][2], nthreads=cores)
+        oracle.poisson(sub, ay, cy, lam[::qk], P=ITEMS[3][2], nthreads=threads)
         t_item["poisson"], n_item["poisson"] = time.perf_counter() - t0, sub.size
         return t_item, n_item
 
@@ -642,11 +677,34 @@ def cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, target_s):
     total = sum(full.values())
     log(f"cpu oracle: {sum(t_item.values()):.1f}s on {sum(n_item.values())} unknowns, "
         f"{cores} threads -> full step {step_s:.2f}s")
+    # one thread, on a sample sized for about 3 s (perfect scaling assumed)
+    spent = sum(t_item.values())
+    frac1 = max(1 / 288, min(frac, 3.0 * frac / max(spent * cores, 1e-3)))
+    t1, n1 = run(min(1.0, frac1), threads=1)
+    step1_s = sum(t1[k] / n1[k] * full[k] for k in full)
+    log(f"cpu oracle, 1 thread: {sum(t1.values()):.1f}s on {sum(n1.values())} unknowns -> full step {step1_s:.1f}s")
     return {"value": total / step_s, "unit": "unknowns/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle PDD/PPT (FP64, C, OpenMP {cores} threads) on every "
-                      f"{int(round(1 / frac))}-th outer plane of each of the 4 solves "
-                      f"({sum(n_item.values())} unknowns, {sum(t_item.values()):.1f}s), scaled to the step",
-            "step_seconds_est": step_s}
+            "sample": f"oracle PDD/PPT (FP64, C, OpenMP {cores} threads) on {planes(frac)} of each of the "
+                      f"4 solves ({sum(n_item.values())} unknowns, {sum(t_item.values()):.1f}s), scaled to the step",
+            "step_seconds_est": step_s, "cpu_model": cpu_model(),
+            "one_thread": {"value": total / step1_s, "unit": "unknowns/s",
+                           "sample": f"{planes(min(1.0, frac1))} ({sum(n1.values())} unknowns, "
+                                     f"{sum(t1.values()):.1f}s), scaled to the step"}}
+
+
+def planes(frac):
+    q = int(round(1 / frac))
+    return "every outer plane" if q == 1 else f"every {q}th outer plane"
+
+
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 if __name__ == "__main__":

@@ -230,6 +230,19 @@ int tri_plan_item_partitions(tri_plan plan, int i);
 int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len);
 tri_status tri_plan_destroy(tri_plan plan);
 
+/* Reference copy (measurement aid; not a step of the method).  Every solve
+ * reads each unknown from HBM once and writes it back once (16 B per real
+ * unknown), so the rate of a plain copy on the same device bounds what any
+ * solve kernel can attain; this entry point is that copy, written as the
+ * fastest streaming copy on gfx950 (one pass, 16-byte non-temporal loads and
+ * stores).  Copies n doubles from src to dst on the context stream,
+ * asynchronously.  dst and src are device pointers owned by the caller,
+ * 16-byte aligned, either equal (in place) or non-overlapping.  n = 0 does
+ * nothing.  Errors (returned before any launch): TRI_E_ARG for a null
+ * context, n < 0, a null or misaligned pointer with n > 0, or partially
+ * overlapping ranges; TRI_E_HIP if the launch fails. */
+tri_status tri_stream_copy(tri_ctx ctx, double *dst, const double *src, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

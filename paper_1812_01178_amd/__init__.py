@@ -26,7 +26,7 @@ __all__ = [
     "TriLines", "TriCoef", "TriInfo", "TriItem", "EXPORTED",
     "TRI_F64", "TRI_F32_REFINE", "TRI_REAL", "TRI_COMPLEX", "TRI_PDD", "TRI_PPT",
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
-    "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS",
+    "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -45,7 +45,7 @@ EXPORTED = [
     "tri_create", "tri_destroy", "tri_set_stream", "tri_sync_status", "tri_status_string",
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
-    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy",
+    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
 ]
 
 
@@ -117,6 +117,7 @@ def lib():
         "tri_plan_item_partitions": (_I, [_V, _I]),
         "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
         "tri_plan_destroy": (_I, [_V]),
+        "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -276,3 +277,11 @@ def tri_plan_item_describe(plan, i: int) -> str:
 
 def tri_plan_destroy(plan) -> None:
     _check(lib().tri_plan_destroy(plan), "tri_plan_destroy")
+
+
+def tri_stream_copy(ctx, dst, src, n: int | None = None) -> None:
+    """Reference copy of n doubles (default: all of src) from src to dst on
+    the context stream (measurement aid for bandwidth fractions)."""
+    if n is None:
+        n = src.numel() * (2 if src.is_complex() else 1)
+    _check(lib().tri_stream_copy(ctx, _ptr(dst), _ptr(src), int(n)), "tri_stream_copy", ctx)

@@ -740,6 +740,22 @@ tri_status tri_destroy(tri_ctx ctx)
     return TRI_OK;
 }
 
+tri_status tri_stream_copy(tri_ctx ctx, double *dst, const double *src, int64_t n)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (n < 0) return fail(ctx, TRI_E_ARG, "tri_stream_copy: n = %lld < 0", (long long)n);
+    if (n == 0) return TRI_OK;
+    if (!dst || !src) return fail(ctx, TRI_E_ARG, "tri_stream_copy: null pointer");
+    if (((uintptr_t)dst | (uintptr_t)src) & 15)
+        return fail(ctx, TRI_E_ARG, "tri_stream_copy: pointers must be 16-byte aligned");
+    const uintptr_t d0 = (uintptr_t)dst, s0 = (uintptr_t)src, len = (uintptr_t)n * sizeof(double);
+    if (d0 != s0 && d0 < s0 + len && s0 < d0 + len)
+        return fail(ctx, TRI_E_ARG, "tri_stream_copy: source and destination partially overlap");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_stream_copy(dst, src, n, ctx->stream));
+    return TRI_OK;
+}
+
 tri_status tri_set_stream(tri_ctx ctx, void *hip_stream)
 {
     if (!ctx) return TRI_E_ARG;

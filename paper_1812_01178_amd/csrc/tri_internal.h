@@ -161,6 +161,8 @@ int contig_staged_grid(const SolveArgs &a, int method);
 // Persistent contiguous variant with the factors in registers (one line per
 // workgroup; C in {4, 8}, P * Lp a multiple of 64 and <= 512).
 hipError_t launch_contig_reg(const SolveArgs &a, int method, int grid, hipStream_t s);
+// Reference copy of n doubles (16-byte aligned, disjoint or equal ranges).
+hipError_t launch_stream_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 size_t contig_reg_lds_bytes(const SolveArgs &a);
 int contig_reg_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);

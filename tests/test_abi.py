@@ -55,3 +55,4 @@ def test_null_context_and_status_strings(T):
     assert T.tri_status_string(T.TRI_E_SHAPE).startswith("invalid shape")
     assert T.tri_status_string(99) == "unknown status"
     assert L.tri_plan_item_partitions(None, 0) == -1
+    assert L.tri_stream_copy(None, None, None, 0) == T.TRI_E_ARG
