@@ -34,21 +34,45 @@ def divergence(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float) -> np.nd
     return dv + dw
 
 
-def project(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float, P: int = 4,
-            method: int = PPT, nthreads: int = 0):
-    """Return (v_new, w_new, phi) with div(v_new, w_new) = 0 to round-off."""
-    Nz, Ny, Nx = w.shape
+def spanwise_rfft(x: np.ndarray) -> np.ndarray:
+    """Real DFT along z (axis 0): X_k = sum_n x_n exp(-2 pi i k n/Nz), k = 0..Nz/2."""
+    return np.ascontiguousarray(np.fft.rfft(x, axis=0))
+
+
+def spanwise_irfft(X: np.ndarray, nz: int) -> np.ndarray:
+    """Inverse of spanwise_rfft over the Hermitian extension, 1/Nz scaling."""
+    return np.ascontiguousarray(np.fft.irfft(X, n=nz, axis=0))
+
+
+def metric(dy: np.ndarray, nz: int, dz: float):
+    """Poisson operator of the grid: ay, cy (d2/dy2 off-diagonals) and lam_k."""
+    ny = dy.size
     yc_gap = 0.5 * (dy[:-1] + dy[1:])            # h_{j+1/2}, j = 0..Ny-2
-    ay = np.zeros(Ny)
-    cy = np.zeros(Ny)
+    ay = np.zeros(ny)
+    cy = np.zeros(ny)
     ay[1:] = 1.0 / (dy[1:] * yc_gap)
     cy[:-1] = 1.0 / (dy[:-1] * yc_gap)
-    lam = (4.0 / dz ** 2) * np.sin(np.pi * np.arange(Nz // 2 + 1) / Nz) ** 2
-    D = divergence(v, w, dy, dz)
-    Dhat = np.ascontiguousarray(np.fft.rfft(D, axis=0))
-    poisson(Dhat, ay, cy, lam, P=P, method=method, nthreads=nthreads)
-    phi = np.fft.irfft(Dhat, n=Nz, axis=0)
+    lam = (4.0 / dz ** 2) * np.sin(np.pi * np.arange(nz // 2 + 1) / nz) ** 2
+    return ay, cy, lam
+
+
+def correct(phihat: np.ndarray, v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float):
+    """phi = inverse FFT of phihat; return (v_new, w_new, phi) corrected by grad phi
+    (interior y-faces only, w periodic)."""
+    Nz, Ny, Nx = w.shape
+    yc_gap = 0.5 * (dy[:-1] + dy[1:])
+    phi = spanwise_irfft(phihat, Nz)
     v_new = v.copy()
     v_new[:, 1:Ny, :] -= (phi[:, 1:, :] - phi[:, :-1, :]) / yc_gap[None, :, None]
     w_new = w - (phi - np.roll(phi, 1, axis=0)) / dz
     return v_new, w_new, phi
+
+
+def project(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float, P: int = 4,
+            method: int = PPT, nthreads: int = 0):
+    """Return (v_new, w_new, phi) with div(v_new, w_new) = 0 to round-off."""
+    Nz = w.shape[0]
+    ay, cy, lam = metric(dy, Nz, dz)
+    Dhat = spanwise_rfft(divergence(v, w, dy, dz))
+    poisson(Dhat, ay, cy, lam, P=P, method=method, nthreads=nthreads)
+    return correct(Dhat, v, w, dy, dz)

@@ -48,3 +48,49 @@ def test_projection_pdd_fails_at_low_k(orc):
     div0 = np.max(np.abs(projection.divergence(v, w, dy, dz)))
     v1, w1, _ = projection.project(v, w, dy, dz, P=4, method=orc.PDD)
     assert np.max(np.abs(projection.divergence(v1, w1, dy, dz))) > 1e-6 * div0
+
+
+# ---- the spanwise transform of the pressure step (Sec. 2.2) ---------------
+
+@pytest.mark.parametrize("nz", [2, 6, 10, 24])
+def test_spanwise_rfft_is_the_dft_sum(nz):
+    """Brute force on tiny lines: X_k = sum_n x_n (cos(2 pi k n/N) - i sin(2 pi k n/N))."""
+    import math
+    from oracle import projection
+    rng = np.random.default_rng(nz)
+    x = rng.standard_normal((nz, 3))
+    X = projection.spanwise_rfft(x)
+    assert X.shape == (nz // 2 + 1, 3)
+    for g in range(3):
+        for k in range(nz // 2 + 1):
+            re = sum(x[n, g] * math.cos(2 * math.pi * k * n / nz) for n in range(nz))
+            im = -sum(x[n, g] * math.sin(2 * math.pi * k * n / nz) for n in range(nz))
+            assert abs(X[k, g] - complex(re, im)) < 1e-13 * nz
+
+
+@pytest.mark.parametrize("nz,q", [(288, 1), (288, 7), (96, 48), (120, 0)])
+def test_spanwise_rfft_of_a_cosine(nz, q):
+    """Closed form: cos(2 pi q n/N) has X_q = N/2 (N at q = 0 or N/2), all other modes 0;
+    the inverse returns the cosine."""
+    from oracle import projection
+    n = np.arange(nz)
+    x = np.cos(2 * np.pi * q * n / nz)[:, None]
+    X = projection.spanwise_rfft(x)[:, 0]
+    want = np.zeros(nz // 2 + 1, complex)
+    want[q] = nz if q in (0, nz // 2) else nz / 2
+    assert np.max(np.abs(X - want)) < 1e-12 * nz
+    back = projection.spanwise_irfft(want[:, None], nz)[:, 0]
+    assert np.max(np.abs(back - x[:, 0])) < 1e-14
+
+
+def test_spanwise_rfft_parseval_and_round_trip():
+    """sum x^2 = (|X_0|^2 + 2 sum_{0<k<N/2} |X_k|^2 + |X_{N/2}|^2)/N, and irfft(rfft x) = x."""
+    from oracle import projection
+    rng = np.random.default_rng(5)
+    nz = 288
+    x = rng.standard_normal((nz, 4))
+    X = projection.spanwise_rfft(x)
+    p = np.abs(X) ** 2
+    energy = (p[0] + 2 * p[1:-1].sum(axis=0) + p[-1]) / nz
+    assert np.allclose(energy, (x ** 2).sum(axis=0), rtol=1e-13)
+    assert np.max(np.abs(projection.spanwise_irfft(X, nz) - x)) < 1e-14
