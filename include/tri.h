@@ -167,6 +167,64 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
                                     const double *cy, const double *lam, int P,
                                     tri_prec prec, int fp64_kmax, tri_info *info);
 
+/* ---- the pressure step around the Poisson solves (Sec. 2.2) -------------
+ *
+ * The fractional step ends every sub-step with a projection: the divergence
+ * of the intermediate velocity is Fourier transformed in the periodic
+ * spanwise direction, the wall-normal Poisson systems of every wavenumber
+ * are solved (poisson_wavenumber_solve), and the transformed back
+ * pseudo-pressure phi corrects the velocity by its gradient.  Grid
+ * (staggered in y and z, every x-station independent): cells j < Ny of
+ * widths dy_j, k < Nz (periodic, width dz); v[Nz][Ny+1][Nx] on the y-faces
+ * (face j below cell j; faces 0 and Ny are the walls), w[Nz][Ny][Nx] on the
+ * z-faces (face k between cells k-1 and k), phi[Nz][Ny][Nx] at the cells.
+ * All arrays are FP64 device arrays owned by the caller, x fastest, 8-byte
+ * aligned; spectra are [Nz/2+1][Ny][Nx] complex128 (interleaved re, im).
+ * Nz must be even with Nz/2 = 2^a 3^b 5^c <= 512 (TRI_E_SHAPE for odd or
+ * Nz < 2, TRI_E_UNSUPPORTED otherwise).  Arrays one call reads and writes
+ * must not overlap (TRI_E_ARG), except where stated.  Calls are
+ * asynchronous on the context stream; all but projection_step allocate
+ * nothing. */
+
+/* Real FFT along z of `lines` independent stations: for every station g,
+ * xhat[k][g] = sum_n x[n][g] exp(-2 pi i k n / Nz), k = 0..Nz/2, with x of
+ * shape [Nz][lines] (lines = Ny*Nx for a field). */
+tri_status spanwise_rfft(tri_ctx ctx, const double *x, double *xhat, int64_t lines, int64_t Nz);
+
+/* Inverse of spanwise_rfft: x[n][g] = (1/Nz) sum over the Hermitian
+ * extension of xhat[.][g] (the imaginary parts of modes 0 and Nz/2 are
+ * ignored). */
+tri_status spanwise_irfft(tri_ctx ctx, const double *xhat, double *x, int64_t lines, int64_t Nz);
+
+/* dhat = spanwise_rfft(D), D = (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz at
+ * every cell (w periodic in k): the right-hand side of the Poisson
+ * equation, fused into the transform (D is never stored).  dy: device array
+ * of Ny cell widths. */
+tri_status projection_divergence_rfft(tri_ctx ctx, const double *v, const double *w,
+                                      const double *dy, double dz, double *dhat, int64_t Nx,
+                                      int64_t Ny, int64_t Nz);
+
+/* phi = spanwise_irfft(phihat); then the velocity correction by the
+ * gradient of phi: w_k -= (phi_k - phi_{k-1})/dz (periodic) and, on the
+ * interior y-faces j = 1..Ny-1, v_j -= (phi_j - phi_{j-1})/h_j with
+ * h_j = (dy_{j-1} + dy_j)/2 (the wall faces are left as they are).  v and w
+ * are updated in place; phihat is read only. */
+tri_status projection_correct(tri_ctx ctx, const double *phihat, double *phi, double *v,
+                              double *w, const double *dy, double dz, int64_t Nx, int64_t Ny,
+                              int64_t Nz);
+
+/* The whole projection: projection_divergence_rfft into phihat (workspace
+ * of (Nz/2+1) Ny Nx complex128, owned by the caller), poisson_wavenumber_solve
+ * on it in FP64 with P partitions (ay, cy, lam as there; for the corrected
+ * velocity to be divergence free they must be the metric of this grid:
+ * ay_j = 1/(dy_j h_j), cy_j = 1/(dy_j h_{j+1}), lam_k = (4/dz^2) sin^2(pi k/Nz)),
+ * then projection_correct into phi.  The Poisson factors are computed on
+ * every call, in the context workspace (grown as poisson_wavenumber_solve
+ * grows it); a plan holding a Poisson item avoids both in a time loop. */
+tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, double dz,
+                           const double *ay, const double *cy, const double *lam, double *phihat,
+                           double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P);
+
 /* ---- plans: factor once, execute many times, capture as a HIP graph ------ */
 
 typedef enum { TRI_ITEM_ADI_X = 0, TRI_ITEM_ADI_Y = 1, TRI_ITEM_ADI_Z = 2,

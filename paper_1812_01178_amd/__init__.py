@@ -27,6 +27,7 @@ __all__ = [
     "TRI_F64", "TRI_F32_REFINE", "TRI_REAL", "TRI_COMPLEX", "TRI_PDD", "TRI_PPT",
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy",
+    "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -46,6 +47,7 @@ EXPORTED = [
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
+    "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
 ]
 
 
@@ -118,6 +120,11 @@ def lib():
         "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
         "tri_plan_destroy": (_I, [_V]),
         "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
+        "spanwise_rfft": (_I, [_V, _V, _V, _I64, _I64]),
+        "spanwise_irfft": (_I, [_V, _V, _V, _I64, _I64]),
+        "projection_divergence_rfft": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, _I64, _I64, _I64]),
+        "projection_correct": (_I, [_V, _V, _V, _V, _V, _V, ctypes.c_double, _I64, _I64, _I64]),
+        "projection_step": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, _V, _V, _V, _V, _I64, _I64, _I64, _I]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -234,6 +241,41 @@ def poisson_wavenumber_solve(ctx, phihat, ay, cy, lam, P: int = 4, prec=TRI_F64,
                                         ctypes.byref(inf) if inf else None)
     _check(st, "poisson_wavenumber_solve", ctx)
     return _info_dict(inf)
+
+
+def spanwise_rfft(ctx, x, xhat) -> None:
+    """xhat[Nz/2+1][...] (complex128) = real FFT along axis 0 of x[Nz][...] (float64)."""
+    Nz = x.shape[0]
+    lines = x.numel() // Nz
+    _check(lib().spanwise_rfft(ctx, _ptr(x), _ptr(xhat), lines, Nz), "spanwise_rfft", ctx)
+
+
+def spanwise_irfft(ctx, xhat, x) -> None:
+    """x[Nz][...] (float64) = inverse real FFT along axis 0 of xhat[Nz/2+1][...]."""
+    Nz = x.shape[0]
+    lines = x.numel() // Nz
+    _check(lib().spanwise_irfft(ctx, _ptr(xhat), _ptr(x), lines, Nz), "spanwise_irfft", ctx)
+
+
+def projection_divergence_rfft(ctx, v, w, dy, dz: float, dhat) -> None:
+    """dhat[Nz/2+1][Ny][Nx] = spanwise FFT of div(v, w); v[Nz][Ny+1][Nx], w[Nz][Ny][Nx]."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection_divergence_rfft(ctx, _ptr(v), _ptr(w), _ptr(dy), float(dz), _ptr(dhat),
+                                            Nx, Ny, Nz), "projection_divergence_rfft", ctx)
+
+
+def projection_correct(ctx, phihat, phi, v, w, dy, dz: float) -> None:
+    """phi = inverse spanwise FFT of phihat; v, w corrected in place by grad phi."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection_correct(ctx, _ptr(phihat), _ptr(phi), _ptr(v), _ptr(w), _ptr(dy), float(dz),
+                                    Nx, Ny, Nz), "projection_correct", ctx)
+
+
+def projection_step(ctx, v, w, dy, dz: float, ay, cy, lam, phihat, phi, P: int = 4) -> None:
+    """Divergence + FFT, Poisson wavenumber solves (PPT), inverse FFT + correction."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection_step(ctx, _ptr(v), _ptr(w), _ptr(dy), float(dz), _ptr(ay), _ptr(cy), _ptr(lam),
+                                 _ptr(phihat), _ptr(phi), Nx, Ny, Nz, int(P)), "projection_step", ctx)
 
 
 def tri_plan_create(ctx, items, prec=TRI_F64):

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtri.so")
-SOURCES = ["tri_api.hip", "tri_kernels.hip", "tri_contig_reg.hip", "tri_refine.hip", "tri_contig_refine.hip", "tri_general_refine.hip", "tri_copy.hip"]
+SOURCES = ["tri_api.hip", "tri_kernels.hip", "tri_contig_reg.hip", "tri_refine.hip", "tri_contig_refine.hip", "tri_general_refine.hip", "tri_copy.hip", "tri_fft.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -819,6 +819,151 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
     return run_problem(ctx, pb, prec, info);
 }
 
+// ---- pressure step ---------------------------------------------------------
+
+static bool ranges_overlap(const void *p, int64_t pbytes, const void *q, int64_t qbytes)
+{
+    const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+    return pbytes > 0 && qbytes > 0 && a < b + (uintptr_t)qbytes && b < a + (uintptr_t)pbytes;
+}
+
+static tri_status fft_check(tri_ctx ctx, int64_t lines, int64_t Nz, FftShape &S, const char *who)
+{
+    if (lines < 0) return fail(ctx, TRI_E_ARG, "%s: lines = %lld < 0", who, (long long)lines);
+    if (Nz < 2 || (Nz & 1)) return fail(ctx, TRI_E_SHAPE, "%s: Nz = %lld must be even and >= 2", who, (long long)Nz);
+    if (!fft_shape(Nz, S))
+        return fail(ctx, TRI_E_UNSUPPORTED, "%s: Nz/2 = %lld is not 2^a 3^b 5^c <= %d", who, (long long)(Nz / 2),
+                    kFftMaxM);
+    return TRI_OK;
+}
+
+static bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
+
+tri_status spanwise_rfft(tri_ctx ctx, const double *x, double *xhat, int64_t lines, int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftArgs A;
+    tri_status st = fft_check(ctx, lines, Nz, A.S, "spanwise_rfft");
+    if (st) return st;
+    if (lines == 0) return TRI_OK;
+    if (!x || !xhat || misaligned(x) || misaligned(xhat))
+        return fail(ctx, TRI_E_ARG, "spanwise_rfft: null or misaligned array");
+    if (ranges_overlap(x, 8 * Nz * lines, xhat, 16 * (Nz / 2 + 1) * lines))
+        return fail(ctx, TRI_E_ARG, "spanwise_rfft: x and xhat overlap");
+    A.lines = lines;
+    A.x = x;
+    A.xhat = xhat;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftForward, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status spanwise_irfft(tri_ctx ctx, const double *xhat, double *x, int64_t lines, int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftArgs A;
+    tri_status st = fft_check(ctx, lines, Nz, A.S, "spanwise_irfft");
+    if (st) return st;
+    if (lines == 0) return TRI_OK;
+    if (!x || !xhat || misaligned(x) || misaligned(xhat))
+        return fail(ctx, TRI_E_ARG, "spanwise_irfft: null or misaligned array");
+    if (ranges_overlap(x, 8 * Nz * lines, xhat, 16 * (Nz / 2 + 1) * lines))
+        return fail(ctx, TRI_E_ARG, "spanwise_irfft: x and xhat overlap");
+    A.lines = lines;
+    A.xhat_in = xhat;
+    A.x_out = x;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftInverse, ctx->stream));
+    return TRI_OK;
+}
+
+static tri_status grid_check(tri_ctx ctx, int64_t Nx, int64_t Ny, int64_t Nz, const double *dy, double dz,
+                             FftShape &S, const char *who)
+{
+    if (Nx < 1 || Ny < 1) return fail(ctx, TRI_E_SHAPE, "%s: Nx = %lld, Ny = %lld", who, (long long)Nx, (long long)Ny);
+    if (Nx > INT32_MAX || Ny > INT32_MAX || Nx * Ny > ((int64_t)1 << 40))
+        return fail(ctx, TRI_E_UNSUPPORTED, "%s: grid too large", who);
+    if (!dy || misaligned(dy)) return fail(ctx, TRI_E_ARG, "%s: null or misaligned dy", who);
+    if (!(dz > 0.0)) return fail(ctx, TRI_E_ARG, "%s: dz must be > 0", who);
+    return fft_check(ctx, Nx * Ny, Nz, S, who);
+}
+
+tri_status projection_divergence_rfft(tri_ctx ctx, const double *v, const double *w, const double *dy, double dz,
+                                      double *dhat, int64_t Nx, int64_t Ny, int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftArgs A;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection_divergence_rfft");
+    if (st) return st;
+    if (!v || !w || !dhat || misaligned(v) || misaligned(w) || misaligned(dhat))
+        return fail(ctx, TRI_E_ARG, "projection_divergence_rfft: null or misaligned array");
+    const int64_t lines = Nx * Ny;
+    const int64_t hb = 16 * (Nz / 2 + 1) * lines;
+    if (ranges_overlap(dhat, hb, v, 8 * Nz * (lines + Nx)) || ranges_overlap(dhat, hb, w, 8 * Nz * lines) ||
+        ranges_overlap(dhat, hb, dy, 8 * Ny))
+        return fail(ctx, TRI_E_ARG, "projection_divergence_rfft: dhat overlaps an input");
+    A.lines = lines;
+    A.Nx = Nx;
+    A.v = v;
+    A.w = w;
+    A.dy = dy;
+    A.dz = dz;
+    A.xhat = dhat;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftDivergence, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status projection_correct(tri_ctx ctx, const double *phihat, double *phi, double *v, double *w,
+                              const double *dy, double dz, int64_t Nx, int64_t Ny, int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftArgs A;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection_correct");
+    if (st) return st;
+    if (!phihat || !phi || !v || !w || misaligned(phihat) || misaligned(phi) || misaligned(v) || misaligned(w))
+        return fail(ctx, TRI_E_ARG, "projection_correct: null or misaligned array");
+    const int64_t lines = Nx * Ny;
+    const void *p[5] = {phihat, phi, v, w, dy};
+    const int64_t nb[5] = {16 * (Nz / 2 + 1) * lines, 8 * Nz * lines, 8 * Nz * (lines + Nx), 8 * Nz * lines, 8 * Ny};
+    for (int i = 0; i < 5; ++i)
+        for (int j = i + 1; j < 5; ++j) {
+            if (i == 0 && j == 4) continue;   // phihat and dy are both read only
+            if (ranges_overlap(p[i], nb[i], p[j], nb[j]))
+                return fail(ctx, TRI_E_ARG, "projection_correct: arrays overlap");
+        }
+    A.lines = lines;
+    A.Nx = Nx;
+    A.dz = dz;
+    A.xhat_in = phihat;
+    A.x_out = phi;
+    A.w_io = w;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftInverseCorrect, ctx->stream));
+    HIP_TRY(ctx, launch_grad_y(v, phi, dy, Nx, Ny, Nz, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, double dz, const double *ay,
+                           const double *cy, const double *lam, double *phihat, double *phi, int64_t Nx,
+                           int64_t Ny, int64_t Nz, int P)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftShape S;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, S, "projection_step");
+    if (st) return st;
+    // every argument is validated before the first launch
+    Problem pb;
+    st = poisson_problem(ctx, phihat, Nx, Ny, Nz / 2 + 1, ay, cy, lam, P, pb, 0);
+    if (st) return st;
+    if (!phi || !v || !w) return fail(ctx, TRI_E_ARG, "projection_step: null array");
+    st = projection_divergence_rfft(ctx, v, w, dy, dz, phihat, Nx, Ny, Nz);
+    if (st) return st;
+    st = run_problem(ctx, pb, TRI_F64, nullptr);
+    if (st) return st;
+    return projection_correct(ctx, phihat, phi, v, w, dy, dz, Nx, Ny, Nz);
+}
+
 }  // extern "C"
 
 // ============================================================================

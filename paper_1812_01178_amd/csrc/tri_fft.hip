@@ -1,0 +1,385 @@
+// tri_fft.hip -- the pressure step around the Poisson wavenumber solves
+// (Sec. 2.2): spanwise real FFT of the divergence of the intermediate
+// velocity, inverse FFT of the pseudo-pressure, gradient correction.
+//
+// Layout: fields [Nz][Ny][Nx] FP64, x fastest.  A spanwise line is one
+// (j, i) station; the Ny*Nx stations of a z-plane are contiguous, so the
+// `lines` stations g = j*Nx + i of every plane form one row of `lines`
+// doubles.  Spectra are [Nz/2+1][Ny][Nx] complex (interleaved re, im).
+//
+// Real FFT of N = 2M points through one complex FFT of M points:
+// z_n = x_{2n} + i x_{2n+1}, Z = DFT_M(z), E_k = (Z_k + conj Z_{M-k})/2,
+// O_k = (Z_k - conj Z_{M-k})/(2i), X_k = E_k + W^k O_k and
+// X_{M-k} = conj(E_k - W^k O_k), W = exp(-2 pi i/N).  The inverse runs the
+// same algebra backwards (E_k = (X_k + conj X_{M-k})/2,
+// O_k = (X_k - conj X_{M-k}) W^{-k}/2, Z_k = E_k + i O_k) and an inverse
+// complex FFT as conj(DFT_M(conj Z))/M; the imaginary parts of X_0 and X_M
+// are ignored (they are zero for the spectrum of a real line).
+//
+// The complex FFT is a self-sorting mixed-radix (4, 2, 3, 5) Stockham
+// transform held in LDS: a workgroup takes L neighbouring lines (L doubles
+// per plane row, coalesced), T = 256/L threads per line; in every pass a
+// thread reads its butterflies' inputs into registers, the workgroup
+// synchronises, and the thread writes the outputs to their sorted places
+// (one buffer, two barriers per pass).  The transform is bound by HBM: each
+// element is read once and written once.
+#include "tri_internal.h"
+
+namespace tri {
+namespace {
+
+struct cplx {
+    double re, im;
+};
+
+__device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
+__device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline cplx cconj(cplx a) { return {a.re, -a.im}; }
+__device__ inline cplx cmul_mi(cplx a) { return {a.im, -a.re}; }   // -i * a
+
+// Forward DFTs of length R in place (exp(-2 pi i k m / R)).
+template <int R>
+__device__ inline void dft(cplx *v);
+
+template <>
+__device__ inline void dft<2>(cplx *v)
+{
+    const cplx a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+}
+
+template <>
+__device__ inline void dft<3>(cplx *v)
+{
+    constexpr double s3 = 0.86602540378443864676;   // sin(2 pi/3)
+    const cplx s = cadd(v[1], v[2]);
+    const cplx d = csub(v[1], v[2]);
+    const cplx t = {v[0].re - 0.5 * s.re, v[0].im - 0.5 * s.im};
+    const cplx u = {s3 * d.im, -s3 * d.re};              // -i sin(2 pi/3) (x1 - x2)
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+}
+
+template <>
+__device__ inline void dft<4>(cplx *v)
+{
+    const cplx a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const cplx c = cadd(v[1], v[3]), d = cmul_mi(csub(v[1], v[3]));
+    v[0] = cadd(a, c);
+    v[2] = csub(a, c);
+    v[1] = cadd(b, d);
+    v[3] = csub(b, d);
+}
+
+template <>
+__device__ inline void dft<5>(cplx *v)
+{
+    constexpr double c1 = 0.30901699437494742410;    // cos(2 pi/5)
+    constexpr double c2 = -0.80901699437494742410;   // cos(4 pi/5)
+    constexpr double s1 = 0.95105651629515357212;    // sin(2 pi/5)
+    constexpr double s2 = 0.58778525229247312917;    // sin(4 pi/5)
+    const cplx a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const cplx a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const cplx x0 = v[0];
+    const cplx p1 = {x0.re + c1 * a1.re + c2 * a2.re, x0.im + c1 * a1.im + c2 * a2.im};
+    const cplx p2 = {x0.re + c2 * a1.re + c1 * a2.re, x0.im + c2 * a1.im + c1 * a2.im};
+    const cplx q1 = cmul_mi({s1 * b1.re + s2 * b2.re, s1 * b1.im + s2 * b2.im});
+    const cplx q2 = cmul_mi({s2 * b1.re - s1 * b2.re, s2 * b1.im - s1 * b2.im});
+    v[0] = cadd(x0, cadd(a1, a2));
+    v[1] = cadd(p1, q1);
+    v[4] = csub(p1, q1);
+    v[2] = cadd(p2, q2);
+    v[3] = csub(p2, q2);
+}
+
+constexpr int kFftThreads = 256;
+
+// One Stockham pass of radix R over the M-point transforms of the L lines in
+// buf[M][L].  Butterfly j reads elements j + r M/R, twiddles element r by
+// W_{Ns R}^{(j mod Ns) r} = twM[(j mod Ns) r M/(Ns R)], and writes output r to
+// (j/Ns) Ns R + (j mod Ns) + r Ns.
+template <int R, int IT>
+__device__ inline void fft_pass(cplx *buf, const cplx *twM, int M, int Ns, int L, int ln, int tr, int T)
+{
+    const int nb = M / R;
+    const int tws = M / (Ns * R);
+    cplx v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int j = tr + it * T;
+        if (j < nb) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * nb) * L + ln];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int j = tr + it * T;
+        if (j < nb) {
+            const int jn = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twM[jn * r * tws]);
+            dft<R>(v[it]);
+            const int d = (j / Ns) * Ns * R + jn;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(d + r * Ns) * L + ln] = v[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <int L, int MMAX>
+__device__ inline void fft_lines(cplx *buf, const cplx *twM, const FftShape &S, int ln, int tr)
+{
+    constexpr int T = kFftThreads / L;
+    int Ns = 1;
+    for (int s = 0; s < S.npass; ++s) {
+        switch (S.radix[s]) {
+        case 4: fft_pass<4, (MMAX / 4 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 2: fft_pass<2, (MMAX / 2 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 3: fft_pass<3, (MMAX / 3 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        default: fft_pass<5, (MMAX / 5 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        }
+        Ns *= S.radix[s];
+    }
+}
+
+// twM[q] = W_M^q (q < M), twN[k] = W_N^{k} (k <= M/2), W_n = exp(-2 pi i/n).
+__device__ inline void make_twiddles(cplx *twM, cplx *twN, int M)
+{
+    for (int q = threadIdx.x; q < M; q += kFftThreads) {
+        double s, c;
+        sincospi(2.0 * q / M, &s, &c);
+        twM[q] = {c, -s};
+    }
+    for (int k = threadIdx.x; k <= M / 2; k += kFftThreads) {
+        double s, c;
+        sincospi((double)k / M, &s, &c);
+        twN[k] = {c, -s};
+    }
+}
+
+// Forward: x rows (or the divergence of (v, w), DIV) -> spectrum rows.
+template <int L, int MMAX, bool DIV>
+__global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
+{
+    constexpr int T = kFftThreads / L;
+    extern __shared__ double lds_fft[];
+    const int M = A.S.M;
+    cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [M][L]
+    cplx *twM = buf + (size_t)M * L;                 // [M]
+    cplx *twN = twM + M;                             // [M/2 + 1]
+    const int ln = threadIdx.x % L, tr = threadIdx.x / L;
+    const int64_t g = (int64_t)blockIdx.x * L + ln;
+    const bool act = g < A.lines;
+    const int Nz = 2 * M;
+    make_twiddles(twM, twN, M);
+
+    double *bd = lds_fft;
+    if (DIV) {
+        // D = (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz at cell (k, j, i); v has
+        // Ny+1 faces per plane, w is periodic in k
+        const int64_t sv = A.lines + A.Nx;          // (Ny+1) Nx
+        const double dyj = act ? A.dy[g / A.Nx] : 1.0;
+#pragma unroll 4
+        for (int k = tr; k < Nz; k += T) {
+            double x = 0.0;
+            if (act) {
+                const int k1 = k + 1 == Nz ? 0 : k + 1;
+                const double *vk = A.v + k * sv + g;
+                const double dv = (vk[A.Nx] - vk[0]) / dyj;
+                const double dw = (A.w[k1 * A.lines + g] - A.w[k * A.lines + g]) / A.dz;
+                x = dv + dw;
+            }
+            bd[((k >> 1) * L + ln) * 2 + (k & 1)] = x;
+        }
+    } else {
+#pragma unroll 4
+        for (int k = tr; k < Nz; k += T)
+            bd[((k >> 1) * L + ln) * 2 + (k & 1)] = act ? __builtin_nontemporal_load(A.x + k * A.lines + g) : 0.0;
+    }
+    __syncthreads();
+
+    fft_lines<L, MMAX>(buf, twM, A.S, ln, tr);
+
+    if (!act) return;
+    double *out = A.xhat;
+    for (int k = tr; k <= M / 2; k += T) {
+        const cplx zk = buf[(k == 0 ? 0 : k) * L + ln];
+        const cplx zm = buf[(k == 0 ? 0 : M - k) * L + ln];
+        const cplx e = {0.5 * (zk.re + zm.re), 0.5 * (zk.im - zm.im)};
+        const cplx o = {0.5 * (zk.im + zm.im), -0.5 * (zk.re - zm.re)};
+        const cplx wo = cmul(twN[k], o);
+        const cplx xk = cadd(e, wo);
+        const cplx xm = cconj(csub(e, wo));
+        double *pk = out + 2 * ((int64_t)k * A.lines + g);
+        __builtin_nontemporal_store(xk.re, pk);
+        __builtin_nontemporal_store(xk.im, pk + 1);
+        if (M - k != k) {
+            double *pm = out + 2 * ((int64_t)(M - k) * A.lines + g);
+            __builtin_nontemporal_store(xm.re, pm);
+            __builtin_nontemporal_store(xm.im, pm + 1);
+        }
+    }
+}
+
+// Inverse: spectrum rows -> x rows; CORR also corrects w by the spanwise
+// gradient of x (the pseudo-pressure): w_k -= (x_k - x_{k-1})/dz, periodic.
+template <int L, int MMAX, bool CORR>
+__global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
+{
+    constexpr int T = kFftThreads / L;
+    extern __shared__ double lds_fft[];
+    const int M = A.S.M;
+    cplx *buf = reinterpret_cast<cplx *>(lds_fft);
+    cplx *twM = buf + (size_t)M * L;
+    cplx *twN = twM + M;
+    const int ln = threadIdx.x % L, tr = threadIdx.x / L;
+    const int64_t g = (int64_t)blockIdx.x * L + ln;
+    const bool act = g < A.lines;
+    const int Nz = 2 * M;
+    make_twiddles(twM, twN, M);
+    __syncthreads();
+
+    // Z_k and Z_{M-k} from X_k and X_{M-k}; stored conjugated, so that the
+    // forward passes compute the conjugate of the inverse transform
+    const double *in = A.xhat_in;
+    for (int k = tr; k <= M / 2; k += T) {
+        cplx a = {0.0, 0.0}, b = {0.0, 0.0};
+        if (act) {
+            const double *pk = in + 2 * ((int64_t)k * A.lines + g);
+            const double *pm = in + 2 * ((int64_t)(M - k) * A.lines + g);
+            a = {__builtin_nontemporal_load(pk), __builtin_nontemporal_load(pk + 1)};
+            b = {__builtin_nontemporal_load(pm), __builtin_nontemporal_load(pm + 1)};
+        }
+        if (k == 0) {
+            a.im = 0.0;
+            b.im = 0.0;
+        }
+        const cplx e = {0.5 * (a.re + b.re), 0.5 * (a.im - b.im)};                     // (a + conj b)/2
+        const cplx o = cmul({0.5 * (a.re - b.re), 0.5 * (a.im + b.im)}, cconj(twN[k])); // (a - conj b) W^{-k}/2
+        const cplx zk = {e.re - o.im, e.im + o.re};                                       // e + i o
+        buf[k * L + ln] = cconj(zk);
+        if (k != 0 && M - k != k) {
+            const cplx zm = {e.re + o.im, -e.im + o.re};                                  // conj e + i conj o
+            buf[(M - k) * L + ln] = cconj(zm);
+        }
+    }
+    __syncthreads();
+
+    fft_lines<L, MMAX>(buf, twM, A.S, ln, tr);
+
+    if (!act) return;
+    const double inv_m = 1.0 / M;
+    const double *bd = lds_fft;
+    // x_{2n} = Re z_n, x_{2n+1} = Im z_n, z = conj(buf)/M
+    auto xval = [&](int k) {
+        const double t = bd[((k >> 1) * L + ln) * 2 + (k & 1)];
+        return (k & 1) ? -t * inv_m : t * inv_m;
+    };
+#pragma unroll 4
+    for (int k = tr; k < Nz; k += T) {
+        const double x = xval(k);
+        __builtin_nontemporal_store(x, A.x_out + k * A.lines + g);
+        if (CORR) {
+            const double xm = xval(k == 0 ? Nz - 1 : k - 1);
+            double *wk = A.w_io + k * A.lines + g;
+            const double wv = __builtin_nontemporal_load(wk);
+            __builtin_nontemporal_store(wv - (x - xm) / A.dz, wk);
+        }
+    }
+}
+
+// Wall-normal gradient correction on the interior y-faces:
+// v[k][j][i] -= (phi[k][j][i] - phi[k][j-1][i]) / h_j, h_j = (dy_{j-1} + dy_j)/2,
+// j = 1..Ny-1 (the wall faces j = 0 and j = Ny are left as they are).
+__global__ void __launch_bounds__(256) k_grad_y(double *v, const double *phi, const double *dy, int Nx, int Ny,
+                                                 int nbx)
+{
+    // workgroup -> (plane row, 256-wide x block); row = k (Ny - 1) + (j - 1)
+    const int row = blockIdx.x / nbx;
+    const int i = (blockIdx.x - row * nbx) * 256 + threadIdx.x;
+    if (i >= Nx) return;
+    const int k = row / (Ny - 1);
+    const int j = 1 + (row - k * (Ny - 1));
+    const double h = 0.5 * (dy[j - 1] + dy[j]);
+    const double *p = phi + ((int64_t)k * Ny + j) * Nx + i;
+    double *vp = v + ((int64_t)k * (Ny + 1) + j) * Nx + i;
+    const double grad = (p[0] - p[-Nx]) / h;
+    __builtin_nontemporal_store(__builtin_nontemporal_load(vp) - grad, vp);
+}
+
+template <int L, int MMAX>
+size_t fft_lds_bytes_t(int M)
+{
+    return sizeof(cplx) * ((size_t)M * L + M + M / 2 + 1);
+}
+
+}  // namespace
+
+bool fft_shape(int64_t Nz, FftShape &S)
+{
+    if (Nz < 2 || (Nz & 1) || Nz / 2 > kFftMaxM) return false;
+    S = FftShape{};
+    S.M = (int)(Nz / 2);
+    int m = S.M;
+    const int order[4] = {4, 2, 3, 5};
+    for (int f : order)
+        while (m % f == 0) {
+            if (S.npass == kFftMaxPasses) return false;
+            S.radix[S.npass++] = f;
+            m /= f;
+        }
+    return m == 1;
+}
+
+// Lines per workgroup: as many as the LDS of two workgroups per CU allows.
+static int fft_lines_per_group(int M) { return M <= 144 ? 32 : (M <= 288 ? 16 : 8); }
+
+size_t fft_lds_bytes(int M)
+{
+    const int L = fft_lines_per_group(M);
+    return sizeof(double) * 2 * ((size_t)M * L + M + M / 2 + 1);
+}
+
+template <int L, int MMAX>
+static hipError_t launch_fft_t(const FftArgs &A, int kind, hipStream_t s)
+{
+    const int64_t blocks = (A.lines + L - 1) / L;
+    const size_t lds = fft_lds_bytes_t<L, MMAX>(A.S.M);
+    const dim3 grid((unsigned)blocks), block(kFftThreads);
+    switch (kind) {
+    case kFftForward: hipLaunchKernelGGL((k_rfft_z<L, MMAX, false>), grid, block, lds, s, A); break;
+    case kFftDivergence: hipLaunchKernelGGL((k_rfft_z<L, MMAX, true>), grid, block, lds, s, A); break;
+    case kFftInverse: hipLaunchKernelGGL((k_irfft_z<L, MMAX, false>), grid, block, lds, s, A); break;
+    default: hipLaunchKernelGGL((k_irfft_z<L, MMAX, true>), grid, block, lds, s, A); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s)
+{
+    if (A.lines <= 0) return hipSuccess;
+    if ((A.lines + 7) / 8 > 0x7fffffffLL) return hipErrorInvalidValue;
+    const int L = fft_lines_per_group(A.S.M);
+    if (L == 32) return launch_fft_t<32, 144>(A, kind, s);
+    if (L == 16) return launch_fft_t<16, 288>(A, kind, s);
+    return launch_fft_t<8, kFftMaxM>(A, kind, s);
+}
+
+hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,
+                         hipStream_t s)
+{
+    if (Ny < 2 || Nx <= 0 || Nz <= 0) return hipSuccess;
+    const int64_t nbx = (Nx + 255) / 256;
+    const int64_t blocks = nbx * (Ny - 1) * Nz;
+    if (blocks > 0x7fffffffLL || Nx > 0x7fffffffLL || Ny > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad_y, dim3((unsigned)blocks), dim3(256), 0, s, v, phi, dy, (int)Nx, (int)Ny, (int)nbx);
+    return hipGetLastError();
+}
+
+}  // namespace tri

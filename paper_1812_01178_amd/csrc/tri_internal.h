@@ -161,6 +161,37 @@ int contig_staged_grid(const SolveArgs &a, int method);
 // Persistent contiguous variant with the factors in registers (one line per
 // workgroup; C in {4, 8}, P * Lp a multiple of 64 and <= 512).
 hipError_t launch_contig_reg(const SolveArgs &a, int method, int grid, hipStream_t s);
+// ---------------------------------------------------------------------------
+// Spanwise real FFT and the projection step (tri_fft.hip).  Nz = 2M points,
+// M = 2^a 3^b 5^c <= kFftMaxM; passes in the order 4, 2, 3, 5.
+constexpr int kFftMaxM = 512;
+constexpr int kFftMaxPasses = 12;
+struct FftShape {
+    int M = 0;
+    int npass = 0;
+    int radix[kFftMaxPasses] = {};
+};
+struct FftArgs {
+    FftShape S;
+    int64_t lines = 0;                  // stations per z-plane (Ny Nx)
+    int64_t Nx = 0;                     // divergence producer: stations per y-row
+    const double *x = nullptr;          // forward input rows [Nz][lines]
+    const double *v = nullptr;          // divergence: v[Nz][Ny+1][Nx] (y-faces)
+    const double *w = nullptr;          // divergence: w[Nz][Ny][Nx] (z-faces)
+    const double *dy = nullptr;         // cell widths [Ny]
+    double dz = 0.0;
+    double *xhat = nullptr;             // forward output [M+1][lines] complex
+    const double *xhat_in = nullptr;    // inverse input [M+1][lines] complex
+    double *x_out = nullptr;            // inverse output rows [Nz][lines]
+    double *w_io = nullptr;             // inverse with correction: w, in place
+};
+enum { kFftForward = 0, kFftDivergence = 1, kFftInverse = 2, kFftInverseCorrect = 3 };
+bool fft_shape(int64_t Nz, FftShape &S);
+size_t fft_lds_bytes(int M);
+hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s);
+hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,
+                         hipStream_t s);
+
 // Reference copy of n doubles (16-byte aligned, disjoint or equal ranges).
 hipError_t launch_stream_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 size_t contig_reg_lds_bytes(const SolveArgs &a);

@@ -1,0 +1,191 @@
+"""The pressure step around the Poisson solves (Sec. 2.2) on the GPU, through
+the C ABI, against the oracle's projection pieces:
+
+* spanwise real FFT / inverse: every supported radix mix (4, 2, 3, 5), all
+  three workgroup widths (M <= 144, <= 288, <= 512), line counts that leave
+  a ragged last workgroup; per-line relative error <= 1e-12;
+* divergence fused into the forward transform, inverse transform fused with
+  the spanwise correction, wall-normal correction;
+* the whole projection: same result as the oracle, and the corrected
+  velocity divergence free to round-off (at the benchmark grid too);
+* refusals (odd or unsupported Nz, overlapping arrays) leave data untouched.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_helpers import TOL, dev, host, line_relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_1812_01178_amd as T
+    T.lib()
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    h = T.tri_create(0, torch.cuda.current_stream().cuda_stream)
+    yield h
+    T.tri_destroy(h)
+
+
+def cdev(shape):
+    return torch.empty(shape, dtype=torch.complex128, device="cuda")
+
+
+@pytest.mark.parametrize("nz,lines", [(2, 5), (4, 33), (6, 64), (10, 31), (24, 100), (96, 65), (120, 257),
+                                      (288, 1000), (200, 37), (576, 300), (640, 129), (1024, 95)])
+def test_spanwise_rfft_matches_oracle(T, ctx, nz, lines):
+    from oracle import projection
+    rng = np.random.default_rng(nz * 7 + lines)
+    x = rng.standard_normal((nz, lines))
+    dx = dev(x)
+    xh = cdev((nz // 2 + 1, lines))
+    T.spanwise_rfft(ctx, dx, xh)
+    T.tri_sync_status(ctx)
+    ref = projection.spanwise_rfft(x)
+    assert line_relerr(host(xh), ref, axis=0) <= TOL
+    assert torch.equal(dx.cpu(), torch.as_tensor(x))   # input untouched
+
+
+@pytest.mark.parametrize("nz,lines", [(2, 3), (6, 64), (24, 100), (288, 1000), (200, 37), (576, 300), (1024, 95)])
+def test_spanwise_irfft_matches_oracle(T, ctx, nz, lines):
+    from oracle import projection
+    rng = np.random.default_rng(nz + 11 * lines)
+    X = rng.standard_normal((nz // 2 + 1, lines)) + 1j * rng.standard_normal((nz // 2 + 1, lines))
+    x = torch.empty((nz, lines), dtype=torch.float64, device="cuda")
+    T.spanwise_irfft(ctx, dev(X, torch.complex128), x)
+    T.tri_sync_status(ctx)
+    ref = projection.spanwise_irfft(X, nz)     # imaginary parts of modes 0 and nz/2 ignored
+    assert line_relerr(host(x), ref, axis=0) <= TOL
+
+
+def test_spanwise_round_trip(T, ctx):
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((288, 2049))
+    xh = cdev((145, 2049))
+    back = torch.empty((288, 2049), dtype=torch.float64, device="cuda")
+    T.spanwise_rfft(ctx, dev(x), xh)
+    T.spanwise_irfft(ctx, xh, back)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(back), x, axis=0) <= 1e-14
+
+
+def grid(nx, ny, nz, seed):
+    rng = np.random.default_rng(seed)
+    dy = np.diff(W.tanh_faces(ny))
+    dz = 1.0 / nz
+    v = rng.standard_normal((nz, ny + 1, nx))
+    v[:, 0, :] = 0.0
+    v[:, ny, :] = 0.0
+    w = rng.standard_normal((nz, ny, nx))
+    return dy, dz, v, w
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(5, 32, 24), (33, 17, 96), (64, 16, 288), (7, 9, 10)])
+def test_divergence_rfft_matches_oracle(T, ctx, nx, ny, nz):
+    from oracle import projection
+    dy, dz, v, w = grid(nx, ny, nz, 1)
+    dh = cdev((nz // 2 + 1, ny, nx))
+    T.projection_divergence_rfft(ctx, dev(v), dev(w), dev(dy), dz, dh)
+    T.tri_sync_status(ctx)
+    ref = projection.spanwise_rfft(projection.divergence(v, w, dy, dz))
+    assert line_relerr(host(dh), ref, axis=0) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(5, 32, 24), (33, 17, 96), (64, 16, 288)])
+def test_correct_matches_oracle(T, ctx, nx, ny, nz):
+    from oracle import projection
+    dy, dz, v, w = grid(nx, ny, nz, 2)
+    rng = np.random.default_rng(4)
+    ph = rng.standard_normal((nz // 2 + 1, ny, nx)) + 1j * rng.standard_normal((nz // 2 + 1, ny, nx))
+    dv, dw = dev(v), dev(w)
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.projection_correct(ctx, dev(ph, torch.complex128), phi, dv, dw, dev(dy), dz)
+    T.tri_sync_status(ctx)
+    v1, w1, phi1 = projection.correct(ph, v, w, dy, dz)
+    assert line_relerr(host(phi), phi1, axis=0) <= TOL
+    assert line_relerr(host(dw), w1, axis=0) <= TOL
+    got_v = host(dv)
+    assert line_relerr(got_v, v1, axis=0) <= TOL
+    assert np.all(got_v[:, 0, :] == 0) and np.all(got_v[:, ny, :] == 0)   # walls untouched
+
+
+@pytest.mark.parametrize("nx,ny,nz,P", [(5, 32, 24, 4), (33, 64, 96, 4), (16, 64, 288, 8)])
+def test_projection_step_matches_oracle_and_is_divergence_free(T, ctx, orc, nx, ny, nz, P):
+    from oracle import projection
+    dy, dz, v, w = grid(nx, ny, nz, 3)
+    ay, cy, lam = projection.metric(dy, nz, dz)
+    dv, dw = dev(v), dev(w)
+    ph = cdev((nz // 2 + 1, ny, nx))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.projection_step(ctx, dv, dw, dev(dy), dz, dev(ay), dev(cy), dev(lam), ph, phi, P=P)
+    T.tri_sync_status(ctx)
+    v1, w1, phi1 = projection.project(v, w, dy, dz, P=P, method=orc.PPT)
+    gv, gw = host(dv), host(dw)
+    assert line_relerr(host(phi), phi1, axis=0) <= TOL
+    assert line_relerr(gv, v1, axis=0) <= TOL
+    assert line_relerr(gw, w1, axis=0) <= TOL
+    div0 = np.max(np.abs(projection.divergence(v, w, dy, dz)))
+    assert np.max(np.abs(projection.divergence(gv, gw, dy, dz))) <= 1e-13 * div0
+
+
+def test_refusals_touch_nothing(T, ctx):
+    L = T.lib()
+    x = torch.randn(14 * 8, dtype=torch.float64, device="cuda")
+    xh = torch.zeros(2 * 8 * 8, dtype=torch.float64, device="cuda")
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), 8, 13) == T.TRI_E_SHAPE        # odd
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), 8, 14) == T.TRI_E_UNSUPPORTED  # 7 = prime > 5
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), 1, 2048) == T.TRI_E_UNSUPPORTED  # M = 1024 > 512
+    assert L.spanwise_rfft(ctx, x.data_ptr(), x.data_ptr() + 64, 4, 12) == T.TRI_E_ARG      # overlap
+    assert L.spanwise_irfft(ctx, xh.data_ptr(), xh.data_ptr(), 4, 12) == T.TRI_E_ARG         # in place
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), -1, 12) == T.TRI_E_ARG
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), 0, 12) == T.TRI_OK             # nothing to do
+    T.tri_sync_status(ctx)
+    assert torch.all(xh == 0)
+
+
+def test_projection_at_benchmark_grid(T, ctx):
+    """2048 x 256 x 288: the corrected velocity is divergence free to round-off
+    (divergence of the GPU result formed with plain torch ops), and sampled
+    stations of the transformed divergence match the oracle."""
+    from oracle import projection
+    nx, ny, nz = 2048, 256, 288
+    dy = np.diff(W.tanh_faces(ny))
+    dz = 1.0 / nz
+    ay, cy, lam = projection.metric(dy, nz, dz)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    v = torch.randn((nz, ny + 1, nx), dtype=torch.float64, device="cuda", generator=g)
+    v[:, 0, :] = 0.0
+    v[:, ny, :] = 0.0
+    w = torch.randn((nz, ny, nx), dtype=torch.float64, device="cuda", generator=g)
+    ddy = dev(dy)
+
+    def div(vv, ww):
+        return (vv[:, 1:, :] - vv[:, :-1, :]) / ddy[None, :, None] + (torch.roll(ww, -1, 0) - ww) / dz
+
+    div0 = div(v, w).abs().max().item()
+    ph = cdev((nz // 2 + 1, ny, nx))
+    T.projection_divergence_rfft(ctx, v, w, ddy, dz, ph)
+    T.tri_sync_status(ctx)
+    rng = np.random.default_rng(0)
+    js, iss = rng.integers(0, ny, 16), rng.integers(0, nx, 16)
+    vs = v[:, :, torch.as_tensor(iss)].cpu().numpy()
+    ws = w[:, :, torch.as_tensor(iss)].cpu().numpy()
+    got = ph[:, torch.as_tensor(js), torch.as_tensor(iss)].cpu().numpy()
+    for s in range(16):
+        D = projection.divergence(vs[:, :, s:s + 1], ws[:, :, s:s + 1], dy, dz)[:, js[s], 0]
+        ref = projection.spanwise_rfft(D[:, None])[:, 0]
+        assert np.max(np.abs(got[:, s] - ref)) <= TOL * np.max(np.abs(ref))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.poisson_wavenumber_solve(ctx, ph, dev(ay), dev(cy), dev(lam), P=4)
+    T.projection_correct(ctx, ph, phi, v, w, ddy, dz)
+    T.tri_sync_status(ctx)
+    assert div(v, w).abs().max().item() <= 1e-13 * div0
