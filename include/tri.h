@@ -179,7 +179,8 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
  * (face j below cell j; faces 0 and Ny are the walls), w[Nz][Ny][Nx] on the
  * z-faces (face k between cells k-1 and k), phi[Nz][Ny][Nx] at the cells.
  * All arrays are FP64 device arrays owned by the caller, x fastest, 8-byte
- * aligned; spectra are [Nz/2+1][Ny][Nx] complex128 (interleaved re, im).
+ * aligned; spectra are [Nz/2+1][Ny][Nx] complex128 (interleaved re, im),
+ * 16-byte aligned (they are moved as 16-byte vectors).
  * Nz must be even with Nz/2 = 2^a 3^b 5^c <= 512 (TRI_E_SHAPE for odd or
  * Nz < 2, TRI_E_UNSUPPORTED otherwise).  Arrays one call reads and writes
  * must not overlap (TRI_E_ARG), except where stated.  Calls are

@@ -838,6 +838,7 @@ static tri_status fft_check(tri_ctx ctx, int64_t lines, int64_t Nz, FftShape &S,
 }
 
 static bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
+static bool misaligned16(const void *p) { return ((uintptr_t)p & 15) != 0; }   // complex128 spectra
 
 tri_status spanwise_rfft(tri_ctx ctx, const double *x, double *xhat, int64_t lines, int64_t Nz)
 {
@@ -846,7 +847,7 @@ tri_status spanwise_rfft(tri_ctx ctx, const double *x, double *xhat, int64_t lin
     tri_status st = fft_check(ctx, lines, Nz, A.S, "spanwise_rfft");
     if (st) return st;
     if (lines == 0) return TRI_OK;
-    if (!x || !xhat || misaligned(x) || misaligned(xhat))
+    if (!x || !xhat || misaligned(x) || misaligned16(xhat))
         return fail(ctx, TRI_E_ARG, "spanwise_rfft: null or misaligned array");
     if (ranges_overlap(x, 8 * Nz * lines, xhat, 16 * (Nz / 2 + 1) * lines))
         return fail(ctx, TRI_E_ARG, "spanwise_rfft: x and xhat overlap");
@@ -865,7 +866,7 @@ tri_status spanwise_irfft(tri_ctx ctx, const double *xhat, double *x, int64_t li
     tri_status st = fft_check(ctx, lines, Nz, A.S, "spanwise_irfft");
     if (st) return st;
     if (lines == 0) return TRI_OK;
-    if (!x || !xhat || misaligned(x) || misaligned(xhat))
+    if (!x || !xhat || misaligned(x) || misaligned16(xhat))
         return fail(ctx, TRI_E_ARG, "spanwise_irfft: null or misaligned array");
     if (ranges_overlap(x, 8 * Nz * lines, xhat, 16 * (Nz / 2 + 1) * lines))
         return fail(ctx, TRI_E_ARG, "spanwise_irfft: x and xhat overlap");
@@ -895,7 +896,7 @@ tri_status projection_divergence_rfft(tri_ctx ctx, const double *v, const double
     FftArgs A;
     tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection_divergence_rfft");
     if (st) return st;
-    if (!v || !w || !dhat || misaligned(v) || misaligned(w) || misaligned(dhat))
+    if (!v || !w || !dhat || misaligned(v) || misaligned(w) || misaligned16(dhat))
         return fail(ctx, TRI_E_ARG, "projection_divergence_rfft: null or misaligned array");
     const int64_t lines = Nx * Ny;
     const int64_t hb = 16 * (Nz / 2 + 1) * lines;
@@ -921,7 +922,7 @@ tri_status projection_correct(tri_ctx ctx, const double *phihat, double *phi, do
     FftArgs A;
     tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection_correct");
     if (st) return st;
-    if (!phihat || !phi || !v || !w || misaligned(phihat) || misaligned(phi) || misaligned(v) || misaligned(w))
+    if (!phihat || !phi || !v || !w || misaligned16(phihat) || misaligned(phi) || misaligned(v) || misaligned(w))
         return fail(ctx, TRI_E_ARG, "projection_correct: null or misaligned array");
     const int64_t lines = Nx * Ny;
     const void *p[5] = {phihat, phi, v, w, dy};

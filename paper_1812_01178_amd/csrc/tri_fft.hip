@@ -23,6 +23,9 @@
 // synchronises, and the thread writes the outputs to their sorted places
 // (one buffer, two barriers per pass).  The transform is bound by HBM: each
 // element is read once and written once.
+#include <algorithm>
+#include <cstdlib>
+
 #include "tri_internal.h"
 
 namespace tri {
@@ -31,6 +34,7 @@ namespace {
 struct cplx {
     double re, im;
 };
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ inline cplx cadd(cplx a, cplx b) { return {a.re + b.re, a.im + b.im}; }
 __device__ inline cplx csub(cplx a, cplx b) { return {a.re - b.re, a.im - b.im}; }
@@ -163,11 +167,22 @@ __device__ inline void make_twiddles(cplx *twM, cplx *twN, int M)
     }
 }
 
+// Rows a thread loads (at most) and rows per batch of loads issued together:
+// the loads of a batch are all in flight before the first is used.
+template <int L, int MMAX>
+struct FftTile {
+    static constexpr int T = kFftThreads / L;
+    static constexpr int NPT = (2 * MMAX + T - 1) / T;          // rows k = tr + u T < Nz
+    static constexpr int KP = (MMAX / 2 + 1 + T - 1) / T;        // mode pairs k = tr + u T <= M/2
+    static constexpr int NB = 12;
+};
+
 // Forward: x rows (or the divergence of (v, w), DIV) -> spectrum rows.
 template <int L, int MMAX, bool DIV>
 __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
 {
-    constexpr int T = kFftThreads / L;
+    using TL = FftTile<L, MMAX>;
+    constexpr int T = TL::T, NPT = TL::NPT, NB = TL::NB;
     extern __shared__ double lds_fft[];
     const int M = A.S.M;
     cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [M][L]
@@ -182,32 +197,55 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
     double *bd = lds_fft;
     if (DIV) {
         // D = (v_{j+1} - v_j)/dy_j + (w_{k+1} - w_k)/dz at cell (k, j, i); v has
-        // Ny+1 faces per plane, w is periodic in k
+        // Ny+1 faces per plane, w is periodic in k.  Every face value is read
+        // by two cells (plain loads, so that the second read finds it cached).
         const int64_t sv = A.lines + A.Nx;          // (Ny+1) Nx
         const double dyj = act ? A.dy[g / A.Nx] : 1.0;
-#pragma unroll 4
-        for (int k = tr; k < Nz; k += T) {
-            double x = 0.0;
-            if (act) {
-                const int k1 = k + 1 == Nz ? 0 : k + 1;
-                const double *vk = A.v + k * sv + g;
-                const double dv = (vk[A.Nx] - vk[0]) / dyj;
-                const double dw = (A.w[k1 * A.lines + g] - A.w[k * A.lines + g]) / A.dz;
-                x = dv + dw;
+#pragma unroll
+        for (int b0 = 0; b0 < NPT; b0 += NB) {
+            double v0[NB], v1[NB], w0[NB], w1[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int k = tr + (b0 + u) * T;
+                v0[u] = v1[u] = w0[u] = w1[u] = 0.0;
+                if (b0 + u < NPT && act && k < Nz) {
+                    const int k1 = k + 1 == Nz ? 0 : k + 1;
+                    const double *vk = A.v + k * sv + g;
+                    v0[u] = vk[0];
+                    v1[u] = vk[A.Nx];
+                    w0[u] = A.w[k * A.lines + g];
+                    w1[u] = A.w[k1 * A.lines + g];
+                }
             }
-            bd[((k >> 1) * L + ln) * 2 + (k & 1)] = x;
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int k = tr + (b0 + u) * T;
+                if (b0 + u < NPT && k < Nz)
+                    bd[((k >> 1) * L + ln) * 2 + (k & 1)] = act ? (v1[u] - v0[u]) / dyj + (w1[u] - w0[u]) / A.dz : 0.0;
+            }
         }
     } else {
-#pragma unroll 4
-        for (int k = tr; k < Nz; k += T)
-            bd[((k >> 1) * L + ln) * 2 + (k & 1)] = act ? __builtin_nontemporal_load(A.x + k * A.lines + g) : 0.0;
+#pragma unroll
+        for (int b0 = 0; b0 < NPT; b0 += NB) {
+            double x[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int k = tr + (b0 + u) * T;
+                x[u] = (b0 + u < NPT && act && k < Nz) ? __builtin_nontemporal_load(A.x + k * A.lines + g) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int k = tr + (b0 + u) * T;
+                if (b0 + u < NPT && k < Nz) bd[((k >> 1) * L + ln) * 2 + (k & 1)] = x[u];
+            }
+        }
     }
     __syncthreads();
 
     fft_lines<L, MMAX>(buf, twM, A.S, ln, tr);
 
     if (!act) return;
-    double *out = A.xhat;
+    v2d *out = reinterpret_cast<v2d *>(A.xhat);
     for (int k = tr; k <= M / 2; k += T) {
         const cplx zk = buf[(k == 0 ? 0 : k) * L + ln];
         const cplx zm = buf[(k == 0 ? 0 : M - k) * L + ln];
@@ -216,23 +254,20 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
         const cplx wo = cmul(twN[k], o);
         const cplx xk = cadd(e, wo);
         const cplx xm = cconj(csub(e, wo));
-        double *pk = out + 2 * ((int64_t)k * A.lines + g);
-        __builtin_nontemporal_store(xk.re, pk);
-        __builtin_nontemporal_store(xk.im, pk + 1);
-        if (M - k != k) {
-            double *pm = out + 2 * ((int64_t)(M - k) * A.lines + g);
-            __builtin_nontemporal_store(xm.re, pm);
-            __builtin_nontemporal_store(xm.im, pm + 1);
-        }
+        __builtin_nontemporal_store(v2d{xk.re, xk.im}, out + (int64_t)k * A.lines + g);
+        if (M - k != k) __builtin_nontemporal_store(v2d{xm.re, xm.im}, out + (int64_t)(M - k) * A.lines + g);
     }
 }
 
 // Inverse: spectrum rows -> x rows; CORR also corrects w by the spanwise
 // gradient of x (the pseudo-pressure): w_k -= (x_k - x_{k-1})/dz, periodic.
+// The w rows are loaded before the transform, so that they arrive while it
+// runs.
 template <int L, int MMAX, bool CORR>
 __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
 {
-    constexpr int T = kFftThreads / L;
+    using TL = FftTile<L, MMAX>;
+    constexpr int T = TL::T, NPT = TL::NPT, KP = TL::KP;
     extern __shared__ double lds_fft[];
     const int M = A.S.M;
     cplx *buf = reinterpret_cast<cplx *>(lds_fft);
@@ -242,20 +277,39 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
     const int64_t g = (int64_t)blockIdx.x * L + ln;
     const bool act = g < A.lines;
     const int Nz = 2 * M;
+
+    // X_k and X_{M-k} of the thread's mode pairs, all loads in flight at once;
+    // then the w rows (issued last: loads complete in order, so the spectrum
+    // can be used while the w rows are still on their way)
+    const v2d *in = reinterpret_cast<const v2d *>(A.xhat_in);
+    v2d xa[KP], xb[KP];
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+        const int k = tr + u * T;
+        xa[u] = xb[u] = v2d{0.0, 0.0};
+        if (act && k <= M / 2) {
+            xa[u] = __builtin_nontemporal_load(in + (int64_t)k * A.lines + g);
+            xb[u] = __builtin_nontemporal_load(in + (int64_t)(M - k) * A.lines + g);
+        }
+    }
+    double wpre[CORR ? NPT : 1];
+    if (CORR) {
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int k = tr + u * T;
+            wpre[u] = (act && k < Nz) ? __builtin_nontemporal_load(A.w_io + k * A.lines + g) : 0.0;
+        }
+    }
     make_twiddles(twM, twN, M);
     __syncthreads();
 
     // Z_k and Z_{M-k} from X_k and X_{M-k}; stored conjugated, so that the
     // forward passes compute the conjugate of the inverse transform
-    const double *in = A.xhat_in;
-    for (int k = tr; k <= M / 2; k += T) {
-        cplx a = {0.0, 0.0}, b = {0.0, 0.0};
-        if (act) {
-            const double *pk = in + 2 * ((int64_t)k * A.lines + g);
-            const double *pm = in + 2 * ((int64_t)(M - k) * A.lines + g);
-            a = {__builtin_nontemporal_load(pk), __builtin_nontemporal_load(pk + 1)};
-            b = {__builtin_nontemporal_load(pm), __builtin_nontemporal_load(pm + 1)};
-        }
+#pragma unroll
+    for (int u = 0; u < KP; ++u) {
+        const int k = tr + u * T;
+        if (k > M / 2) continue;
+        cplx a = {xa[u].x, xa[u].y}, b = {xb[u].x, xb[u].y};
         if (k == 0) {
             a.im = 0.0;
             b.im = 0.0;
@@ -281,15 +335,15 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
         const double t = bd[((k >> 1) * L + ln) * 2 + (k & 1)];
         return (k & 1) ? -t * inv_m : t * inv_m;
     };
-#pragma unroll 4
-    for (int k = tr; k < Nz; k += T) {
+#pragma unroll
+    for (int u = 0; u < NPT; ++u) {
+        const int k = tr + u * T;
+        if (k >= Nz) continue;
         const double x = xval(k);
         __builtin_nontemporal_store(x, A.x_out + k * A.lines + g);
         if (CORR) {
             const double xm = xval(k == 0 ? Nz - 1 : k - 1);
-            double *wk = A.w_io + k * A.lines + g;
-            const double wv = __builtin_nontemporal_load(wk);
-            __builtin_nontemporal_store(wv - (x - xm) / A.dz, wk);
+            __builtin_nontemporal_store(wpre[u] - (x - xm) / A.dz, A.w_io + k * A.lines + g);
         }
     }
 }
@@ -337,13 +391,17 @@ bool fft_shape(int64_t Nz, FftShape &S)
     return m == 1;
 }
 
-// Lines per workgroup: as many as the LDS of two workgroups per CU allows.
-static int fft_lines_per_group(int M) { return M <= 144 ? 32 : (M <= 288 ? 16 : 8); }
-
-size_t fft_lds_bytes(int M)
+// Lines per workgroup (measured on MI355X at Nz = 288): 16 for the
+// transforms (three workgroups per CU), 32 for the inverse with the w
+// correction (its prefetched w rows hold two workgroups per CU anyway);
+// TRI_FFT_LINES (8, 16 or 32) overrides where the transform fits that width.
+static int fft_lines_per_group(int M, int kind)
 {
-    const int L = fft_lines_per_group(M);
-    return sizeof(double) * 2 * ((size_t)M * L + M + M / 2 + 1);
+    const int fit = M <= 144 ? 32 : (M <= 288 ? 16 : 8);
+    const char *e = getenv("TRI_FFT_LINES");
+    const int want = e ? atoi(e) : 0;
+    if ((want == 8 || want == 16 || want == 32) && want <= fit) return want;
+    return kind == kFftInverseCorrect ? fit : std::min(fit, 16);
 }
 
 template <int L, int MMAX>
@@ -365,10 +423,10 @@ hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s)
 {
     if (A.lines <= 0) return hipSuccess;
     if ((A.lines + 7) / 8 > 0x7fffffffLL) return hipErrorInvalidValue;
-    const int L = fft_lines_per_group(A.S.M);
+    const int L = fft_lines_per_group(A.S.M, kind);
     if (L == 32) return launch_fft_t<32, 144>(A, kind, s);
-    if (L == 16) return launch_fft_t<16, 288>(A, kind, s);
-    return launch_fft_t<8, kFftMaxM>(A, kind, s);
+    if (L == 16) return A.S.M <= 144 ? launch_fft_t<16, 144>(A, kind, s) : launch_fft_t<16, 288>(A, kind, s);
+    return A.S.M <= 144 ? launch_fft_t<8, 144>(A, kind, s) : launch_fft_t<8, kFftMaxM>(A, kind, s);
 }
 
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,

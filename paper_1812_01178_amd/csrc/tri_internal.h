@@ -187,7 +187,6 @@ struct FftArgs {
 };
 enum { kFftForward = 0, kFftDivergence = 1, kFftInverse = 2, kFftInverseCorrect = 3 };
 bool fft_shape(int64_t Nz, FftShape &S);
-size_t fft_lds_bytes(int M);
 hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s);
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,
                          hipStream_t s);

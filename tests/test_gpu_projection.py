@@ -147,6 +147,7 @@ def test_refusals_touch_nothing(T, ctx):
     assert L.spanwise_rfft(ctx, x.data_ptr(), x.data_ptr() + 64, 4, 12) == T.TRI_E_ARG      # overlap
     assert L.spanwise_irfft(ctx, xh.data_ptr(), xh.data_ptr(), 4, 12) == T.TRI_E_ARG         # in place
     assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), -1, 12) == T.TRI_E_ARG
+    assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr() + 8, 2, 12) == T.TRI_E_ARG      # spectrum not 16-B aligned
     assert L.spanwise_rfft(ctx, x.data_ptr(), xh.data_ptr(), 0, 12) == T.TRI_OK             # nothing to do
     T.tri_sync_status(ctx)
     assert torch.all(xh == 0)
@@ -189,3 +190,24 @@ def test_projection_at_benchmark_grid(T, ctx):
     T.projection_correct(ctx, ph, phi, v, w, ddy, dz)
     T.tri_sync_status(ctx)
     assert div(v, w).abs().max().item() <= 1e-13 * div0
+
+
+@pytest.mark.parametrize("width", ["8", "16", "32"])
+def test_every_workgroup_width(T, ctx, width, monkeypatch):
+    """The transform kernels at each lines-per-workgroup width (TRI_FFT_LINES)."""
+    from oracle import projection
+    monkeypatch.setenv("TRI_FFT_LINES", width)
+    dy, dz, v, w = grid(37, 12, 288, 5)
+    dh = cdev((145, 12, 37))
+    T.projection_divergence_rfft(ctx, dev(v), dev(w), dev(dy), dz, dh)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dh), projection.spanwise_rfft(projection.divergence(v, w, dy, dz)), axis=0) <= TOL
+    ph = host(dh)
+    dv, dw = dev(v), dev(w)
+    phi = torch.empty((288, 12, 37), dtype=torch.float64, device="cuda")
+    T.projection_correct(ctx, dh, phi, dv, dw, dev(dy), dz)
+    T.tri_sync_status(ctx)
+    v1, w1, phi1 = projection.correct(ph, v, w, dy, dz)
+    assert line_relerr(host(phi), phi1, axis=0) <= TOL
+    assert line_relerr(host(dw), w1, axis=0) <= TOL
+    assert line_relerr(host(dv), v1, axis=0) <= TOL
