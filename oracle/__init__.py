@@ -200,5 +200,29 @@ def poisson(phihat: np.ndarray, ay, cy, lam, P: int, method: int = PPT,
                              int(P), int(nthreads)), "poisson")
 
 
+def poisson_shifted(phihat: np.ndarray, ay, cy, lamz, lamx, P: int, method: int = PPT) -> None:
+    """In-place wall-normal solves of phihat[Nk][Ny][Nx] complex128 with one matrix per
+    line (k, i): a = ay, c = cy, b = -(ay + cy) - (lamz_k + lamx_i) -- the Poisson systems
+    once both homogeneous directions are transformed (Sec. 2.2; PPT paragraph of
+    Sec. 3.2).  A line whose shift is 0 is gauge pinned (row 0 becomes x_0 = 0).  Real
+    and imaginary parts are solved as two real lines with the same matrix."""
+    assert phihat.dtype == np.complex128 and phihat.ndim == 3
+    Nk, Ny, Nx = phihat.shape
+    ay, cy, lamz, lamx = map(_f64, (ay, cy, lamz, lamx))
+    if method == EXACT:
+        fn = lambda a, b, c, d, P: exact(a, b, c, d)
+    else:
+        fn = ppt if method == PPT else pdd
+    for k in range(Nk):
+        for i in range(Nx):
+            sigma = lamz[k] + lamx[i]
+            a, c = ay.copy(), cy.copy()
+            b = -(ay + cy) - sigma
+            rhs = phihat[k, :, i].copy()
+            if sigma == 0.0:
+                b[0], c[0], rhs[0] = 1.0, 0.0, 0.0
+            phihat[k, :, i] = fn(a, b, c, rhs.real, P) + 1j * fn(a, b, c, rhs.imag, P)
+
+
 def max_threads() -> int:
     return int(lib().orc_max_threads())

@@ -94,3 +94,52 @@ def test_spanwise_rfft_parseval_and_round_trip():
     energy = (p[0] + 2 * p[1:-1].sum(axis=0) + p[-1]) / nz
     assert np.allclose(energy, (x ** 2).sum(axis=0), rtol=1e-13)
     assert np.max(np.abs(projection.spanwise_irfft(X, nz) - x)) < 1e-14
+
+
+# ---- shifted wall-normal systems (both homogeneous directions transformed) ----
+
+@pytest.mark.parametrize("P,method", [(4, "PPT"), (8, "PPT"), (1, "EXACT")])
+def test_shifted_poisson_manufactured_cosines(orc, P, method):
+    """Uniform Neumann mesh: cos(pi q (j + 1/2)/N) is an eigenvector of the cell-centred
+    d2/dy2 with eigenvalue -(4/h^2) sin^2(pi q/(2N)); with the shift sigma the solution is
+    d / (eigenvalue - sigma) for every line, whatever its shift."""
+    ny, h = 64, 1.0 / 64
+    ay = np.full(ny, 1 / h ** 2)
+    cy = np.full(ny, 1 / h ** 2)
+    ay[0] = 0.0
+    cy[-1] = 0.0
+    rng = np.random.default_rng(11)
+    lamz = rng.uniform(0.5, 3e4, 3)
+    lamx = rng.uniform(0.5, 3e4, 5)
+    j = np.arange(ny)
+    ph = np.empty((3, ny, 5), complex)
+    want = np.empty_like(ph)
+    for k in range(3):
+        for i in range(5):
+            q, q2 = rng.integers(0, ny, 2)
+            e1 = -(4 / h ** 2) * np.sin(np.pi * q / (2 * ny)) ** 2
+            e2 = -(4 / h ** 2) * np.sin(np.pi * q2 / (2 * ny)) ** 2
+            d1, d2 = np.cos(np.pi * q * (j + 0.5) / ny), np.cos(np.pi * q2 * (j + 0.5) / ny)
+            sig = lamz[k] + lamx[i]
+            ph[k, :, i] = d1 + 1j * d2
+            want[k, :, i] = d1 / (e1 - sig) + 1j * d2 / (e2 - sig)
+    orc.poisson_shifted(ph, ay, cy, lamz, lamx, P, getattr(orc, method))
+    assert np.max(np.abs(ph - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_shifted_poisson_gauge_pinned_line(orc):
+    """The line with zero shift: x_0 = 0 and the other rows of A x = d hold; other lines
+    are untouched by the pin (same as the unshifted solve where lamx = 0)."""
+    import workloads as W
+    ny = 32
+    ay, cy = W.poisson_metric(ny)
+    lamz = W.modified_wavenumbers(12)           # lamz_0 = 0
+    lamx = np.zeros(4)
+    rng = np.random.default_rng(2)
+    ph = rng.standard_normal((7, ny, 4)) + 1j * rng.standard_normal((7, ny, 4))
+    ref = ph.copy()
+    orc.poisson(ref, ay, cy, lamz, P=4)
+    got = ph.copy()
+    orc.poisson_shifted(got, ay, cy, lamz, lamx, 4)
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    assert np.all(got[0, 0, :] == 0)
