@@ -167,6 +167,22 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
                                     const double *cy, const double *lam, int P,
                                     tri_prec prec, int fp64_kmax, tri_info *info);
 
+/* Wall-normal Poisson solves with a shift per x-station as well (Sec. 2.2:
+ * the pressure equation transformed in both homogeneous directions; PPT
+ * paragraph of Sec. 3.2), in place on phihat[Nk][Ny][Nx] complex128.  For
+ * mode k and station i the real matrix is
+ *     a_j = ay_j,  c_j = cy_j,  b_j = -(ay_j + cy_j) - (lamz_k + lamx_i),
+ * every line with its own matrix, factored on the fly (nothing is stored).
+ * A line with lamz_k + lamx_i == 0 is gauge pinned (row 0 replaced by
+ * x_0 = 0).  ay, cy: device arrays of Ny (ay_0 = cy_{Ny-1} = 0); lamz: Nk,
+ * lamx: Nx device arrays of shifts >= 0.  method TRI_PPT or TRI_PDD with P
+ * partitions; Ny/P <= 32 rows per partition (<= 16 if P = 16), else
+ * TRI_E_UNSUPPORTED.  FP64 only; asynchronous, allocates nothing; zero pivots
+ * set the status word read by tri_sync_status. */
+tri_status poisson_shifted_solve(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
+                                 const double *ay, const double *cy, const double *lamz,
+                                 const double *lamx, int P, int method);
+
 /* ---- the pressure step around the Poisson solves (Sec. 2.2) -------------
  *
  * The fractional step ends every sub-step with a projection: the divergence

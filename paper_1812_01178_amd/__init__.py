@@ -28,6 +28,7 @@ __all__ = [
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
+    "poisson_shifted_solve",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -48,6 +49,7 @@ EXPORTED = [
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
+    "poisson_shifted_solve",
 ]
 
 
@@ -120,6 +122,7 @@ def lib():
         "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
         "tri_plan_destroy": (_I, [_V]),
         "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
+        "poisson_shifted_solve": (_I, [_V, _V, _I64, _I64, _I64, _V, _V, _V, _V, _I, _I]),
         "spanwise_rfft": (_I, [_V, _V, _V, _I64, _I64]),
         "spanwise_irfft": (_I, [_V, _V, _V, _I64, _I64]),
         "projection_divergence_rfft": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, _I64, _I64, _I64]),
@@ -241,6 +244,13 @@ def poisson_wavenumber_solve(ctx, phihat, ay, cy, lam, P: int = 4, prec=TRI_F64,
                                         ctypes.byref(inf) if inf else None)
     _check(st, "poisson_wavenumber_solve", ctx)
     return _info_dict(inf)
+
+
+def poisson_shifted_solve(ctx, phihat, ay, cy, lamz, lamx, P: int = 8, method=TRI_PPT) -> None:
+    """In-place wall-normal solves of phihat[Nk][Ny][Nx] complex128 with the shift lamz_k + lamx_i."""
+    Nk, Ny, Nx = phihat.shape
+    _check(lib().poisson_shifted_solve(ctx, _ptr(phihat), Nx, Ny, Nk, _ptr(ay), _ptr(cy), _ptr(lamz), _ptr(lamx),
+                                       int(P), int(method)), "poisson_shifted_solve", ctx)
 
 
 def spanwise_rfft(ctx, x, xhat) -> None:

@@ -819,6 +819,49 @@ tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t N
     return run_problem(ctx, pb, prec, info);
 }
 
+tri_status poisson_shifted_solve(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk, const double *ay,
+                                 const double *cy, const double *lamz, const double *lamx, int P, int method)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (Nx < 0 || Ny < 1 || Nk < 0) return fail(ctx, TRI_E_ARG, "bad Poisson extents");
+    if (method != TRI_PDD && method != TRI_PPT) return fail(ctx, TRI_E_ARG, "bad method %d", method);
+    tri_status st = check_partition(ctx, Ny, P, 0);
+    if (st) return st;
+    if (Nx == 0 || Nk == 0) return TRI_OK;
+    if (!phihat || !ay || !cy || !lamz || !lamx) return fail(ctx, TRI_E_ARG, "null Poisson pointer");
+    const int m = (int)(Ny / P);
+    if (m > kGeneralMaxM)
+        return fail(ctx, TRI_E_UNSUPPORTED, "shifted Poisson systems with m = %d > %d rows per partition", m,
+                    kGeneralMaxM);
+    if (m > 16 && P > 8) return fail(ctx, TRI_E_UNSUPPORTED, "shifted Poisson systems with m = %d > 16 need P <= 8", m);
+    if ((2 * Nx + 63) / 64 * Nk > 0x7fffffffLL) return fail(ctx, TRI_E_UNSUPPORTED, "too many lines");
+    GeneralArgs g{};
+    g.d = phihat;
+    g.n = Ny;
+    g.m = m;
+    g.P = P;
+    g.periodic = 0;
+    g.cplx = 1;
+    g.s_j = 2 * Nx;
+    g.nb0 = 2 * Nx;
+    g.nb1 = Nk;
+    g.s_b0 = 1;
+    g.s_b1 = 2 * Nx * Ny;
+    g.ngroups0 = (2 * Nx + 63) / 64;
+    g.a = ay;
+    g.b = nullptr;
+    g.c = cy;
+    g.cs_j = 1;
+    g.cs_b0 = 0;
+    g.cs_b1 = 0;
+    g.status = ctx->status_dev;
+    g.lamz = lamz;
+    g.lamx = lamx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_general(g, method, ctx->stream));
+    return TRI_OK;
+}
+
 // ---- pressure step ---------------------------------------------------------
 
 static bool ranges_overlap(const void *p, int64_t pbytes, const void *q, int64_t qbytes)

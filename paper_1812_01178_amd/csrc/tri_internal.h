@@ -138,6 +138,11 @@ struct GeneralArgs {
     const double *a, *b, *c;
     int64_t cs_j, cs_b0, cs_b1;
     int *status;
+    // Shifted Poisson systems (set together, with cs_b0 = cs_b1 = 0 and b
+    // unused): a = ay, c = cy shared by every line, b = -(ay + cy) - sigma with
+    // sigma = lamz[b1] + lamx[b0 >> cplx] per line; a line with sigma == 0 is
+    // gauge pinned (row 0 replaced by x_0 = 0).
+    const double *lamz = nullptr, *lamx = nullptr;
 };
 
 // Host launchers (tri_kernels.hip).  All return hipError_t of the launch.

@@ -1046,9 +1046,11 @@ hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStr
 // (wavefront = partition, lane = line); every lane factors its own block,
 // carrying the right-hand side and the a-corner spike through one forward
 // elimination (the paper batches Eq. (6) with Eq. (5) the same way), and
-// keeps x~, the forward-reduced spike and the pivots in VGPRs.
+// keeps x~, the forward-reduced spike and the pivots in VGPRs.  SHIFT: the
+// shifted Poisson systems of GeneralArgs (coefficients formed on the fly from
+// the shared ay, cy and the line's shift, never stored).
 // ===========================================================================
-template <int CMAX, int METHOD>
+template <int CMAX, int METHOD, bool SHIFT>
 __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const GeneralArgs A)
 {
     extern __shared__ double sh[];              // [6][P][64]
@@ -1068,6 +1070,15 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
     const double *__restrict__ cbp = A.b + cb;
     const double *__restrict__ cc = A.c + cb;
 
+    // row t of the block: (a_t, b_t, c_t)
+    const double sigma = SHIFT ? A.lamz[b1] + A.lamx[b0 >> A.cplx] : 0.0;
+    const bool pin = SHIFT && sigma == 0.0 && r == 0;     // global row 0 becomes x_0 = 0
+    auto row_c = [&](int t) { return (pin && t == 0) ? 0.0 : cc[t * csj]; };
+    auto row_b = [&](int t) {
+        if (!SHIFT) return cbp[t * csj];
+        return (pin && t == 0) ? 1.0 : -(ca[t * csj] + cc[t * csj]) - sigma;
+    };
+
     double x[CMAX], gv[CMAX], cp[CMAX];
 #pragma unroll
     for (int t = 0; t < CMAX; ++t) { x[t] = 0.0; gv[t] = 0.0; cp[t] = 0.0; }
@@ -1076,16 +1087,17 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
         for (int t = 0; t < CMAX; ++t)
             if (t < m) x[t] = p[t * sj];
     }
+    if (pin) x[0] = 0.0;
     const double a_first = (r >= 1 || periodic) ? ca[0] : 0.0;
-    const double c_last = (r <= P - 2 || periodic) ? cc[(int64_t)(m - 1) * csj] : 0.0;
+    const double c_last = (r <= P - 2 || periodic) ? row_c(m - 1) : 0.0;
     double cpp = 0.0, gx = 0.0, gvp = 0.0, beta_last = 0.0;
     bool bad = false;
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
         if (t < m) {
             const double aa = (t == 0) ? 0.0 : ca[t * csj];
-            const double ccv = (t == m - 1) ? 0.0 : cc[t * csj];
-            const double den = cbp[t * csj] - aa * cpp;
+            const double ccv = (t == m - 1) ? 0.0 : row_c(t);
+            const double den = row_b(t) - aa * cpp;
             bad |= !(den != 0.0);
             const double beta = 1.0 / den;
             gx = (x[t] - aa * gx) * beta;
@@ -1192,7 +1204,10 @@ static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
     const size_t lds = sizeof(double) * 6 * a.P * 64;
-    hipLaunchKernelGGL((k_general<CMAX, METHOD>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    if (a.lamz)
+        hipLaunchKernelGGL((k_general<CMAX, METHOD, true>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_general<CMAX, METHOD, false>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
     return hipGetLastError();
 }
 

@@ -211,3 +211,40 @@ def test_every_workgroup_width(T, ctx, width, monkeypatch):
     assert line_relerr(host(phi), phi1, axis=0) <= TOL
     assert line_relerr(host(dw), w1, axis=0) <= TOL
     assert line_relerr(host(dv), v1, axis=0) <= TOL
+
+
+def lam_x(nx):
+    """Modified wavenumbers of the cell-centred Neumann second difference in x (cosine modes)."""
+    return (4.0 * nx * nx) * np.sin(np.pi * np.arange(nx) / (2 * nx)) ** 2
+
+
+@pytest.mark.parametrize("nk,ny,nx,P,method", [(7, 64, 37, 4, "PPT"), (13, 256, 33, 8, "PPT"), (7, 64, 20, 8, "PDD"),
+                                               (5, 64, 70, 16, "PPT"), (4, 32, 5, 1, "PPT")])
+def test_shifted_poisson_matches_oracle(T, ctx, orc, nk, ny, nx, P, method):
+    """One matrix per (k, i) line, formed on the fly; the (0, 0) line is gauge pinned."""
+    ay, cy = W.poisson_metric(ny)
+    lamz = W.modified_wavenumbers(2 * (nk - 1))
+    lamx = lam_x(nx)
+    rng = np.random.default_rng(nk * ny + nx)
+    ph = rng.standard_normal((nk, ny, nx)) + 1j * rng.standard_normal((nk, ny, nx))
+    d = dev(ph, torch.complex128)
+    T.poisson_shifted_solve(ctx, d, dev(ay), dev(cy), dev(lamz), dev(lamx), P=P, method=getattr(T, "TRI_" + method))
+    T.tri_sync_status(ctx)
+    ref = ph.copy()
+    orc.poisson_shifted(ref, ay, cy, lamz, lamx, P, getattr(orc, method))
+    got = host(d)
+    assert line_relerr(got, ref, axis=1) <= TOL
+    assert np.all(got[0, 0, 0] == 0)
+
+
+def test_shifted_poisson_refusals(T, ctx):
+    L = T.lib()
+    ph = torch.zeros((3, 256, 4), dtype=torch.complex128, device="cuda")
+    z = torch.zeros(256, dtype=torch.float64, device="cuda")
+    args = lambda ny, P, meth: (ctx, ph.data_ptr(), 4, ny, 3, z.data_ptr(), z.data_ptr(), z.data_ptr(), z.data_ptr(),
+                                P, meth)
+    assert L.poisson_shifted_solve(*args(256, 4, T.TRI_PPT)) == T.TRI_E_UNSUPPORTED   # 64 rows per partition
+    assert L.poisson_shifted_solve(*args(256, 6, T.TRI_PPT)) == T.TRI_E_SHAPE         # 256 % 6
+    assert L.poisson_shifted_solve(*args(256, 8, 7)) == T.TRI_E_ARG                    # method
+    T.tri_sync_status(ctx)
+    assert torch.all(ph == 0)
