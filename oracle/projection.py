@@ -1,4 +1,4 @@
-"""Projection step on a staggered (y, z) grid, FP64, numpy + the oracle's solves.
+"""Projection step on a staggered (y, z) or (x, y, z) grid, FP64, numpy/scipy + the oracle's solves.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
@@ -66,6 +66,62 @@ def correct(phihat: np.ndarray, v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz
     v_new[:, 1:Ny, :] -= (phi[:, 1:, :] - phi[:, :-1, :]) / yc_gap[None, :, None]
     w_new = w - (phi - np.roll(phi, 1, axis=0)) / dz
     return v_new, w_new, phi
+
+
+# ---- the 3-D step: walls at both x-ends as well, cosine transform in x ------
+
+def divergence3d(u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float, dy: np.ndarray,
+                 dz: float) -> np.ndarray:
+    """u[Nz][Ny][Nx+1] (x-faces), v, w as in divergence -> D[Nz][Ny][Nx]."""
+    return (u[:, :, 1:] - u[:, :, :-1]) / dx + divergence(v, w, dy, dz)
+
+
+def streamwise_dct(x: np.ndarray) -> np.ndarray:
+    """Cosine transform along the last axis (x), real and imaginary parts alike:
+    X_k = sum_n x_n cos(pi k (2n+1)/(2N))."""
+    import scipy.fft as sf
+    x = np.asarray(x)
+    out = sf.dct(x.real, type=2, axis=-1) / 2
+    if np.iscomplexobj(x):
+        out = out + 1j * (sf.dct(x.imag, type=2, axis=-1) / 2)
+    return np.ascontiguousarray(out)
+
+
+def streamwise_idct(X: np.ndarray) -> np.ndarray:
+    """Exact inverse of streamwise_dct."""
+    import scipy.fft as sf
+    X = np.asarray(X)
+    out = sf.idct(2 * X.real, type=2, axis=-1)
+    if np.iscomplexobj(X):
+        out = out + 1j * sf.idct(2 * X.imag, type=2, axis=-1)
+    return np.ascontiguousarray(out)
+
+
+def metric_x(nx: int, dx: float) -> np.ndarray:
+    """lam_x(i) = (4/dx^2) sin^2(pi i/(2 Nx)): eigenvalues (negated) of the cell-centred
+    Neumann second difference in x, whose eigenvectors are the cosine modes."""
+    return (4.0 / dx ** 2) * np.sin(np.pi * np.arange(nx) / (2 * nx)) ** 2
+
+
+def correct3d(phihat: np.ndarray, u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float,
+              dy: np.ndarray, dz: float):
+    """correct(), and u on the interior x-faces by the x-gradient of phi."""
+    v_new, w_new, phi = correct(phihat, v, w, dy, dz)
+    u_new = u.copy()
+    u_new[:, :, 1:-1] -= (phi[:, :, 1:] - phi[:, :, :-1]) / dx
+    return u_new, v_new, w_new, phi
+
+
+def project3d(u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float, dy: np.ndarray, dz: float,
+              P: int = 8, method: int = PPT):
+    """Return (u_new, v_new, w_new, phi) with div(u_new, v_new, w_new) = 0 to round-off."""
+    from . import poisson_shifted
+    Nz, Ny, Nx = w.shape
+    ay, cy, lamz = metric(dy, Nz, dz)
+    lamx = metric_x(Nx, dx)
+    Dhat = streamwise_dct(spanwise_rfft(divergence3d(u, v, w, dx, dy, dz)))
+    poisson_shifted(Dhat, ay, cy, lamz, lamx, P, method)
+    return correct3d(streamwise_idct(Dhat), u, v, w, dx, dy, dz)
 
 
 def project(v: np.ndarray, w: np.ndarray, dy: np.ndarray, dz: float, P: int = 4,

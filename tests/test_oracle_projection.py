@@ -143,3 +143,52 @@ def test_shifted_poisson_gauge_pinned_line(orc):
     orc.poisson_shifted(got, ay, cy, lamz, lamx, 4)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     assert np.all(got[0, 0, :] == 0)
+
+
+# ---- the 3-D step: cosine transform in x -------------------------------------
+
+@pytest.mark.parametrize("nx", [2, 6, 10, 24])
+def test_streamwise_dct_is_the_cosine_sum(nx):
+    import math
+    from oracle import projection
+    rng = np.random.default_rng(nx)
+    x = rng.standard_normal((3, nx)) + 1j * rng.standard_normal((3, nx))
+    X = projection.streamwise_dct(x)
+    for r in range(3):
+        for k in range(nx):
+            want = sum(x[r, n] * math.cos(math.pi * k * (2 * n + 1) / (2 * nx)) for n in range(nx))
+            assert abs(X[r, k] - want) < 1e-13 * nx
+    assert np.max(np.abs(projection.streamwise_idct(X) - x)) < 1e-14
+
+
+@pytest.mark.parametrize("nx,q", [(2048, 0), (2048, 5), (96, 95)])
+def test_streamwise_dct_of_a_cosine_mode(nx, q):
+    """cos(pi q (n + 1/2)/N) transforms to N/2 at k = q (N at q = 0) and 0 elsewhere."""
+    from oracle import projection
+    n = np.arange(nx)
+    X = projection.streamwise_dct(np.cos(np.pi * q * (n + 0.5) / nx))
+    want = np.zeros(nx)
+    want[q] = nx if q == 0 else nx / 2
+    assert np.max(np.abs(X - want)) < 1e-12 * nx
+
+
+@pytest.mark.parametrize("P,method", [(8, "PPT"), (4, "PPT"), (1, "EXACT")])
+def test_projection3d_divergence_free(orc, P, method):
+    """x, y and z corrections together: the 3-D divergence vanishes to round-off;
+    wall faces (x-ends, y-walls) are untouched."""
+    from oracle import projection
+    nx, ny, nz = 12, 32, 10
+    rng = np.random.default_rng(31)
+    dy = np.diff(W.tanh_faces(ny))
+    dx, dz = 1.0 / nx, 1.0 / nz
+    u = rng.standard_normal((nz, ny, nx + 1))
+    u[:, :, 0] = u[:, :, nx] = 0.0
+    v = rng.standard_normal((nz, ny + 1, nx))
+    v[:, 0, :] = v[:, ny, :] = 0.0
+    w = rng.standard_normal((nz, ny, nx))
+    div0 = np.max(np.abs(projection.divergence3d(u, v, w, dx, dy, dz)))
+    u1, v1, w1, phi = projection.project3d(u, v, w, dx, dy, dz, P=P, method=getattr(orc, method))
+    assert div0 > 10
+    assert np.max(np.abs(projection.divergence3d(u1, v1, w1, dx, dy, dz))) <= 1e-13 * div0
+    assert np.all(u1[:, :, 0] == 0) and np.all(u1[:, :, nx] == 0)
+    assert np.all(v1[:, 0, :] == 0) and np.all(v1[:, ny, :] == 0)
