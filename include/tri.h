@@ -242,6 +242,45 @@ tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, 
                            const double *ay, const double *cy, const double *lam, double *phihat,
                            double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P);
 
+/* ---- the 3-D pressure step: cosine transform in x as well (Sec. 2.2) -------
+ *
+ * With walls at both x-ends (u = 0 on the faces i = 0 and i = Nx, Neumann
+ * for phi), the pressure equation is diagonalised in x by the cosine
+ * transform and in z by the Fourier transform; what remains are the shifted
+ * wall-normal systems of poisson_shifted_solve with
+ * lamx_i = (4/dx^2) sin^2(pi i/(2 Nx)).  u[Nz][Ny][Nx+1] lives on the
+ * x-faces; everything else as for the spanwise-only step above. */
+
+/* In place on `rows` rows of Nx complex128 values (contiguous rows, 16-byte
+ * aligned): X_k = sum_n x_n cos(pi k (2n+1)/(2 Nx)), k < Nx, real and
+ * imaginary parts alike.  Nx even, 2^a 3^b 5^c <= 4096 (TRI_E_SHAPE for odd
+ * or Nx < 2, TRI_E_UNSUPPORTED otherwise). */
+tri_status streamwise_dct(tri_ctx ctx, double *xhat, int64_t Nx, int64_t rows);
+/* Its exact inverse: x_n = (X_0 + 2 sum_{k>0} X_k cos(pi k (2n+1)/(2 Nx)))/Nx. */
+tri_status streamwise_idct(tri_ctx ctx, double *xhat, int64_t Nx, int64_t rows);
+
+/* dhat = spanwise_rfft(D), D = (u_{i+1} - u_i)/dx + (v_{j+1} - v_j)/dy_j
+ * + (w_{k+1} - w_k)/dz, fused into the transform. */
+tri_status projection3d_divergence_rfft(tri_ctx ctx, const double *u, const double *v,
+                                        const double *w, double dx, const double *dy, double dz,
+                                        double *dhat, int64_t Nx, int64_t Ny, int64_t Nz);
+
+/* projection_correct, then u_i -= (phi_i - phi_{i-1})/dx on the interior
+ * x-faces i = 1..Nx-1 (the end faces are left as they are). */
+tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, double *u,
+                                double *v, double *w, double dx, const double *dy, double dz,
+                                int64_t Nx, int64_t Ny, int64_t Nz);
+
+/* The whole 3-D projection: projection3d_divergence_rfft into phihat,
+ * streamwise_dct, poisson_shifted_solve (PPT, P partitions; ay, cy, lamz,
+ * lamx the metric of this grid for the result to be divergence free),
+ * streamwise_idct, projection3d_correct into phi.  Every argument is checked
+ * before the first launch; allocates nothing. */
+tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, double dx,
+                             const double *dy, double dz, const double *ay, const double *cy,
+                             const double *lamz, const double *lamx, double *phihat, double *phi,
+                             int64_t Nx, int64_t Ny, int64_t Nz, int P);
+
 /* ---- plans: factor once, execute many times, capture as a HIP graph ------ */
 
 typedef enum { TRI_ITEM_ADI_X = 0, TRI_ITEM_ADI_Y = 1, TRI_ITEM_ADI_Z = 2,

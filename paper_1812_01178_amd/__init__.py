@@ -28,7 +28,8 @@ __all__ = [
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
-    "poisson_shifted_solve",
+    "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
+    "projection3d_correct", "projection3d_step",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -49,7 +50,8 @@ EXPORTED = [
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
-    "poisson_shifted_solve",
+    "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
+    "projection3d_correct", "projection3d_step",
 ]
 
 
@@ -123,6 +125,14 @@ def lib():
         "tri_plan_destroy": (_I, [_V]),
         "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
         "poisson_shifted_solve": (_I, [_V, _V, _I64, _I64, _I64, _V, _V, _V, _V, _I, _I]),
+        "streamwise_dct": (_I, [_V, _V, _I64, _I64]),
+        "streamwise_idct": (_I, [_V, _V, _I64, _I64]),
+        "projection3d_divergence_rfft": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, ctypes.c_double, _V,
+                                              _I64, _I64, _I64]),
+        "projection3d_correct": (_I, [_V, _V, _V, _V, _V, _V, ctypes.c_double, _V, ctypes.c_double,
+                                      _I64, _I64, _I64]),
+        "projection3d_step": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, ctypes.c_double, _V, _V, _V, _V, _V, _V,
+                                   _I64, _I64, _I64, _I]),
         "spanwise_rfft": (_I, [_V, _V, _V, _I64, _I64]),
         "spanwise_irfft": (_I, [_V, _V, _V, _I64, _I64]),
         "projection_divergence_rfft": (_I, [_V, _V, _V, _V, ctypes.c_double, _V, _I64, _I64, _I64]),
@@ -251,6 +261,41 @@ def poisson_shifted_solve(ctx, phihat, ay, cy, lamz, lamx, P: int = 8, method=TR
     Nk, Ny, Nx = phihat.shape
     _check(lib().poisson_shifted_solve(ctx, _ptr(phihat), Nx, Ny, Nk, _ptr(ay), _ptr(cy), _ptr(lamz), _ptr(lamx),
                                        int(P), int(method)), "poisson_shifted_solve", ctx)
+
+
+def streamwise_dct(ctx, xhat) -> None:
+    """In-place cosine transform along the last axis of a complex128 tensor."""
+    Nx = xhat.shape[-1]
+    _check(lib().streamwise_dct(ctx, _ptr(xhat), Nx, xhat.numel() // Nx), "streamwise_dct", ctx)
+
+
+def streamwise_idct(ctx, xhat) -> None:
+    """In-place inverse of streamwise_dct."""
+    Nx = xhat.shape[-1]
+    _check(lib().streamwise_idct(ctx, _ptr(xhat), Nx, xhat.numel() // Nx), "streamwise_idct", ctx)
+
+
+def projection3d_divergence_rfft(ctx, u, v, w, dx: float, dy, dz: float, dhat) -> None:
+    """dhat = spanwise FFT of div(u, v, w); u[Nz][Ny][Nx+1], v[Nz][Ny+1][Nx], w[Nz][Ny][Nx]."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection3d_divergence_rfft(ctx, _ptr(u), _ptr(v), _ptr(w), float(dx), _ptr(dy), float(dz),
+                                              _ptr(dhat), Nx, Ny, Nz), "projection3d_divergence_rfft", ctx)
+
+
+def projection3d_correct(ctx, phihat, phi, u, v, w, dx: float, dy, dz: float) -> None:
+    """phi = inverse spanwise FFT of phihat; u, v, w corrected in place by grad phi."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection3d_correct(ctx, _ptr(phihat), _ptr(phi), _ptr(u), _ptr(v), _ptr(w), float(dx), _ptr(dy),
+                                      float(dz), Nx, Ny, Nz), "projection3d_correct", ctx)
+
+
+def projection3d_step(ctx, u, v, w, dx: float, dy, dz: float, ay, cy, lamz, lamx, phihat, phi, P: int = 8) -> None:
+    """Divergence + spanwise FFT, streamwise cosine transform, shifted Poisson solves (PPT),
+    inverse transforms, gradient correction of u, v, w."""
+    Nz, Ny, Nx = w.shape
+    _check(lib().projection3d_step(ctx, _ptr(u), _ptr(v), _ptr(w), float(dx), _ptr(dy), float(dz), _ptr(ay),
+                                   _ptr(cy), _ptr(lamz), _ptr(lamx), _ptr(phihat), _ptr(phi), Nx, Ny, Nz, int(P)),
+           "projection3d_step", ctx)
 
 
 def spanwise_rfft(ctx, x, xhat) -> None:

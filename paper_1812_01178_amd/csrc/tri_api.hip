@@ -881,6 +881,24 @@ static tri_status fft_check(tri_ctx ctx, int64_t lines, int64_t Nz, FftShape &S,
 }
 
 static bool misaligned(const void *p) { return ((uintptr_t)p & 7) != 0; }
+
+// The arrays a whole projection writes (phihat, phi, [u,] v, w) must be
+// pairwise disjoint and disjoint from dy; checked before its first launch.
+static tri_status projection_arrays_disjoint(tri_ctx ctx, const char *who, const double *phihat, const double *phi,
+                                             const double *u, const double *v, const double *w, const double *dy,
+                                             int64_t Nx, int64_t Ny, int64_t Nz)
+{
+    const int64_t lines = Nx * Ny;
+    const void *p[6] = {phihat, phi, v, w, u, dy};
+    const int64_t nb[6] = {16 * (Nz / 2 + 1) * lines, 8 * Nz * lines, 8 * Nz * (lines + Nx), 8 * Nz * lines,
+                           u ? 8 * Nz * (lines + Ny) : 0, 8 * Ny};
+    for (int i = 0; i < 6; ++i)
+        for (int j = i + 1; j < 5; ++j)
+            if (ranges_overlap(p[i], nb[i], p[j], nb[j])) return fail(ctx, TRI_E_ARG, "%s: arrays overlap", who);
+    for (int i = 0; i < 5; ++i)
+        if (ranges_overlap(p[i], nb[i], dy, nb[5])) return fail(ctx, TRI_E_ARG, "%s: dy overlaps an output", who);
+    return TRI_OK;
+}
 static bool misaligned16(const void *p) { return ((uintptr_t)p & 15) != 0; }   // complex128 spectra
 
 tri_status spanwise_rfft(tri_ctx ctx, const double *x, double *xhat, int64_t lines, int64_t Nz)
@@ -988,6 +1006,118 @@ tri_status projection_correct(tri_ctx ctx, const double *phihat, double *phi, do
     return TRI_OK;
 }
 
+static tri_status dct_call(tri_ctx ctx, double *xhat, int64_t Nx, int64_t rows, bool inverse, const char *who)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (rows < 0) return fail(ctx, TRI_E_ARG, "%s: rows = %lld < 0", who, (long long)rows);
+    if (Nx < 2 || (Nx & 1)) return fail(ctx, TRI_E_SHAPE, "%s: Nx = %lld must be even and >= 2", who, (long long)Nx);
+    DctArgs A;
+    if (!dct_shape(Nx, A.S))
+        return fail(ctx, TRI_E_UNSUPPORTED, "%s: Nx = %lld is not 2^a 3^b 5^c <= %d", who, (long long)Nx, kDctMaxN);
+    if (rows == 0) return TRI_OK;
+    if (!xhat || misaligned16(xhat)) return fail(ctx, TRI_E_ARG, "%s: null or misaligned array", who);
+    A.x = xhat;
+    A.rows = rows;
+    A.row_stride = Nx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_dct(A, inverse, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status streamwise_dct(tri_ctx ctx, double *xhat, int64_t Nx, int64_t rows)
+{
+    return dct_call(ctx, xhat, Nx, rows, false, "streamwise_dct");
+}
+
+tri_status streamwise_idct(tri_ctx ctx, double *xhat, int64_t Nx, int64_t rows)
+{
+    return dct_call(ctx, xhat, Nx, rows, true, "streamwise_idct");
+}
+
+tri_status projection3d_divergence_rfft(tri_ctx ctx, const double *u, const double *v, const double *w, double dx,
+                                        const double *dy, double dz, double *dhat, int64_t Nx, int64_t Ny,
+                                        int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftArgs A;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection3d_divergence_rfft");
+    if (st) return st;
+    if (!(dx > 0.0)) return fail(ctx, TRI_E_ARG, "projection3d_divergence_rfft: dx must be > 0");
+    if (!u || !v || !w || !dhat || misaligned(u) || misaligned(v) || misaligned(w) || misaligned16(dhat))
+        return fail(ctx, TRI_E_ARG, "projection3d_divergence_rfft: null or misaligned array");
+    const int64_t lines = Nx * Ny;
+    const int64_t hb = 16 * (Nz / 2 + 1) * lines;
+    if (ranges_overlap(dhat, hb, u, 8 * Nz * (lines + Ny)) || ranges_overlap(dhat, hb, v, 8 * Nz * (lines + Nx)) ||
+        ranges_overlap(dhat, hb, w, 8 * Nz * lines) || ranges_overlap(dhat, hb, dy, 8 * Ny))
+        return fail(ctx, TRI_E_ARG, "projection3d_divergence_rfft: dhat overlaps an input");
+    A.lines = lines;
+    A.Nx = Nx;
+    A.u = u;
+    A.dx = dx;
+    A.v = v;
+    A.w = w;
+    A.dy = dy;
+    A.dz = dz;
+    A.xhat = dhat;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftDivergence3, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, double *u, double *v, double *w,
+                                double dx, const double *dy, double dz, int64_t Nx, int64_t Ny, int64_t Nz)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (!(dx > 0.0)) return fail(ctx, TRI_E_ARG, "projection3d_correct: dx must be > 0");
+    if (!u || misaligned(u)) return fail(ctx, TRI_E_ARG, "projection3d_correct: null or misaligned u");
+    if (Nx >= 1 && Ny >= 1 && Nz >= 1) {
+        const int64_t lines = Nx * Ny;
+        const int64_t ub = 8 * Nz * (lines + Ny);
+        const void *p[4] = {phihat, phi, v, w};
+        const int64_t nb[4] = {16 * (Nz / 2 + 1) * lines, 8 * Nz * lines, 8 * Nz * (lines + Nx), 8 * Nz * lines};
+        for (int i = 0; i < 4; ++i)
+            if (ranges_overlap(u, ub, p[i], nb[i])) return fail(ctx, TRI_E_ARG, "projection3d_correct: arrays overlap");
+    }
+    tri_status st = projection_correct(ctx, phihat, phi, v, w, dy, dz, Nx, Ny, Nz);
+    if (st) return st;
+    HIP_TRY(ctx, launch_grad_x(u, phi, dx, Nx, Ny * Nz, ctx->stream));
+    return TRI_OK;
+}
+
+tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, double dx, const double *dy, double dz,
+                             const double *ay, const double *cy, const double *lamz, const double *lamx,
+                             double *phihat, double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P)
+{
+    if (!ctx) return TRI_E_ARG;
+    FftShape S, Sx;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, S, "projection3d_step");
+    if (st) return st;
+    if (Nx < 2 || (Nx & 1) || !dct_shape(Nx, Sx))
+        return fail(ctx, TRI_E_UNSUPPORTED, "projection3d_step: Nx = %lld is not even 2^a 3^b 5^c <= %d",
+                    (long long)Nx, kDctMaxN);
+    const int m = (int)(Ny / std::max(P, 1));
+    if (P < 1 || Ny % P || m > kGeneralMaxM || (m > 16 && P > 8))
+        return fail(ctx, TRI_E_UNSUPPORTED, "projection3d_step: P = %d does not split Ny = %lld into <= 32 rows", P,
+                    (long long)Ny);
+    if (!ay || !cy || !lamz || !lamx || !phihat || !phi || !u || !v || !w)
+        return fail(ctx, TRI_E_ARG, "projection3d_step: null array");
+    if (misaligned16(phihat) || misaligned(phi) || misaligned(u) || misaligned(v) || misaligned(w))
+        return fail(ctx, TRI_E_ARG, "projection3d_step: misaligned array");
+    if (!(dx > 0.0)) return fail(ctx, TRI_E_ARG, "projection3d_step: dx must be > 0");
+    st = projection_arrays_disjoint(ctx, "projection3d_step", phihat, phi, u, v, w, dy, Nx, Ny, Nz);
+    if (st) return st;
+    st = projection3d_divergence_rfft(ctx, u, v, w, dx, dy, dz, phihat, Nx, Ny, Nz);
+    if (st) return st;
+    const int64_t nk = Nz / 2 + 1;
+    st = streamwise_dct(ctx, phihat, Nx, nk * Ny);
+    if (st) return st;
+    st = poisson_shifted_solve(ctx, phihat, Nx, Ny, nk, ay, cy, lamz, lamx, P, TRI_PPT);
+    if (st) return st;
+    st = streamwise_idct(ctx, phihat, Nx, nk * Ny);
+    if (st) return st;
+    return projection3d_correct(ctx, phihat, phi, u, v, w, dx, dy, dz, Nx, Ny, Nz);
+}
+
 tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, double dz, const double *ay,
                            const double *cy, const double *lam, double *phihat, double *phi, int64_t Nx,
                            int64_t Ny, int64_t Nz, int P)
@@ -1001,6 +1131,10 @@ tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, 
     st = poisson_problem(ctx, phihat, Nx, Ny, Nz / 2 + 1, ay, cy, lam, P, pb, 0);
     if (st) return st;
     if (!phi || !v || !w) return fail(ctx, TRI_E_ARG, "projection_step: null array");
+    if (misaligned16(phihat) || misaligned(phi) || misaligned(v) || misaligned(w))
+        return fail(ctx, TRI_E_ARG, "projection_step: misaligned array");
+    st = projection_arrays_disjoint(ctx, "projection_step", phihat, phi, nullptr, v, w, dy, Nx, Ny, Nz);
+    if (st) return st;
     st = projection_divergence_rfft(ctx, v, w, dy, dz, phihat, Nx, Ny, Nz);
     if (st) return st;
     st = run_problem(ctx, pb, TRI_F64, nullptr);

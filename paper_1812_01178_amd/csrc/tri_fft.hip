@@ -105,8 +105,19 @@ constexpr int kFftThreads = 256;
 // buf[M][L].  Butterfly j reads elements j + r M/R, twiddles element r by
 // W_{Ns R}^{(j mod Ns) r} = twM[(j mod Ns) r M/(Ns R)], and writes output r to
 // (j/Ns) Ns R + (j mod Ns) + r Ns.
-template <int R, int IT>
-__device__ inline void fft_pass(cplx *buf, const cplx *twM, int M, int Ns, int L, int ln, int tr, int T)
+// Twiddle W_M^q from a full table (M entries) or from two short ones
+// (W^q = W^{64 (q >> 6)} W^{q & 63}: 64 + M/64 entries, for long transforms).
+struct TwFull {
+    const cplx *t;
+    __device__ cplx operator()(int q) const { return t[q]; }
+};
+struct TwSplit {
+    const cplx *lo, *hi;
+    __device__ cplx operator()(int q) const { return cmul(hi[q >> 6], lo[q & 63]); }
+};
+
+template <int R, int IT, class TW>
+__device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, int ln, int tr, int T)
 {
     const int nb = M / R;
     const int tws = M / (Ns * R);
@@ -126,7 +137,7 @@ __device__ inline void fft_pass(cplx *buf, const cplx *twM, int M, int Ns, int L
         if (j < nb) {
             const int jn = j % Ns;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twM[jn * r * tws]);
+            for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twM(jn * r * tws));
             dft<R>(v[it]);
             const int d = (j / Ns) * Ns * R + jn;
 #pragma unroll
@@ -136,8 +147,8 @@ __device__ inline void fft_pass(cplx *buf, const cplx *twM, int M, int Ns, int L
     __syncthreads();
 }
 
-template <int L, int MMAX>
-__device__ inline void fft_lines(cplx *buf, const cplx *twM, const FftShape &S, int ln, int tr)
+template <int L, int MMAX, class TW>
+__device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, int ln, int tr)
 {
     constexpr int T = kFftThreads / L;
     int Ns = 1;
@@ -177,12 +188,13 @@ struct FftTile {
     static constexpr int NB = 12;
 };
 
-// Forward: x rows (or the divergence of (v, w), DIV) -> spectrum rows.
-template <int L, int MMAX, bool DIV>
+// Forward: x rows (DIV = 0), or the divergence of (v, w) (DIV = 1) or of
+// (u, v, w) (DIV = 2) -> spectrum rows.
+template <int L, int MMAX, int DIV>
 __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
 {
     using TL = FftTile<L, MMAX>;
-    constexpr int T = TL::T, NPT = TL::NPT, NB = TL::NB;
+    constexpr int T = TL::T, NPT = TL::NPT, NB = DIV == 2 ? 8 : TL::NB;
     extern __shared__ double lds_fft[];
     const int M = A.S.M;
     cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [M][L]
@@ -200,14 +212,20 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
         // Ny+1 faces per plane, w is periodic in k.  Every face value is read
         // by two cells (plain loads, so that the second read finds it cached).
         const int64_t sv = A.lines + A.Nx;          // (Ny+1) Nx
-        const double dyj = act ? A.dy[g / A.Nx] : 1.0;
+        const int64_t jg = act ? g / A.Nx : 0;
+        const double dyj = act ? A.dy[jg] : 1.0;
+        // u[Nz][Ny][Nx+1] on the x-faces (3-D projection only): face i of cell
+        // (j, i) at j (Nx+1) + i in its plane
+        constexpr bool has_u = DIV == 2;
+        const int64_t su = A.lines + (A.lines / A.Nx), ug = g + jg;
 #pragma unroll
         for (int b0 = 0; b0 < NPT; b0 += NB) {
-            double v0[NB], v1[NB], w0[NB], w1[NB];
+            double v0[NB], v1[NB], w0[NB], w1[NB], u0[has_u ? NB : 1], u1[has_u ? NB : 1];
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int k = tr + (b0 + u) * T;
                 v0[u] = v1[u] = w0[u] = w1[u] = 0.0;
+                if (has_u) u0[u] = u1[u] = 0.0;
                 if (b0 + u < NPT && act && k < Nz) {
                     const int k1 = k + 1 == Nz ? 0 : k + 1;
                     const double *vk = A.v + k * sv + g;
@@ -215,13 +233,24 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
                     v1[u] = vk[A.Nx];
                     w0[u] = A.w[k * A.lines + g];
                     w1[u] = A.w[k1 * A.lines + g];
+                    if (has_u) {
+                        const double *uk = A.u + k * su + ug;
+                        u0[u] = uk[0];
+                        u1[u] = uk[1];
+                    }
                 }
             }
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int k = tr + (b0 + u) * T;
-                if (b0 + u < NPT && k < Nz)
-                    bd[((k >> 1) * L + ln) * 2 + (k & 1)] = act ? (v1[u] - v0[u]) / dyj + (w1[u] - w0[u]) / A.dz : 0.0;
+                if (b0 + u < NPT && k < Nz) {
+                    double x = 0.0;
+                    if (act) {
+                        x = (v1[u] - v0[u]) / dyj + (w1[u] - w0[u]) / A.dz;
+                        if (has_u) x = (u1[u] - u0[u]) / A.dx + x;
+                    }
+                    bd[((k >> 1) * L + ln) * 2 + (k & 1)] = x;
+                }
             }
         }
     } else {
@@ -242,7 +271,7 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX>(buf, twM, A.S, ln, tr);
+    fft_lines<L, MMAX>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     v2d *out = reinterpret_cast<v2d *>(A.xhat);
@@ -325,7 +354,7 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX>(buf, twM, A.S, ln, tr);
+    fft_lines<L, MMAX>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     const double inv_m = 1.0 / M;
@@ -365,6 +394,120 @@ __global__ void __launch_bounds__(256) k_grad_y(double *v, const double *phi, co
     double *vp = v + ((int64_t)k * (Ny + 1) + j) * Nx + i;
     const double grad = (p[0] - p[-Nx]) / h;
     __builtin_nontemporal_store(__builtin_nontemporal_load(vp) - grad, vp);
+}
+
+// Streamwise gradient correction on the interior x-faces:
+// u[k][j][i] -= (phi[k][j][i] - phi[k][j][i-1]) / dx, i = 1..Nx-1.
+__global__ void __launch_bounds__(256) k_grad_x(double *u, const double *phi, double dx, int Nx, int nbx)
+{
+    const int64_t row = blockIdx.x / nbx;                       // k Ny + j
+    const int i = 1 + (int)(blockIdx.x - row * nbx) * 256 + (int)threadIdx.x;
+    if (i >= Nx) return;
+    const double *p = phi + row * Nx + i;
+    double *up = u + row * (Nx + 1) + i;
+    const double grad = (p[0] - p[-1]) / dx;
+    __builtin_nontemporal_store(__builtin_nontemporal_load(up) - grad, up);
+}
+
+// ---------------------------------------------------------------------------
+// Streamwise cosine transform of complex rows (each row: N values, contiguous):
+// X_k = sum_n x_n cos(pi k (2n+1) / (2N)), and its inverse.  Through one
+// complex N-point FFT per row: v_n = x_{2n}, v_{N-1-n} = x_{2n+1}, V = DFT(v);
+// with A_k = (V_k + conj V_{N-k})/2 and B_k = (V_k - conj V_{N-k})/(2i) (the
+// spectra of the real and imaginary parts) and W = exp(-i pi k/(2N)):
+// X_k = Re(W A_k) + i Re(W B_k), X_{N-k} = -Im(W A_k) - i Im(W B_k).  The
+// inverse forms V_k = conj(W) ((P_k + Q_{N-k}) + i (Q_k - P_{N-k})) from
+// P = Re X, Q = Im X (P_N = Q_N = 0), transforms back and unscrambles.
+// Rows are transformed in place (a workgroup reads all of its rows before
+// it writes them).
+template <int L, int NMAX, bool INV>
+__global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
+{
+    constexpr int T = kFftThreads / L;
+    constexpr int NPT = NMAX / T;
+    extern __shared__ double lds_fft[];
+    const int N = A.S.M;
+    cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [N][L]
+    cplx *lo = buf + (size_t)N * L;                  // W_N^t, t < 64
+    cplx *hi = lo + 64;                              // W_N^{64 s}
+    const int ln = threadIdx.x % L, tr = threadIdx.x / L;
+    const int64_t row = (int64_t)blockIdx.x * L + ln;
+    const bool act = row < A.rows;
+    v2d *x = reinterpret_cast<v2d *>(A.x) + (act ? row : 0) * A.row_stride;
+    for (int t = threadIdx.x; t < 64 + (N + 63) / 64; t += kFftThreads) {
+        double sn, cs;
+        sincospi(2.0 * (t < 64 ? t : 64 * (t - 64)) / N, &sn, &cs);
+        lo[t] = {cs, -sn};   // hi follows lo contiguously
+    }
+    if (!INV) {
+        v2d xv[NPT];
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int n = tr + u * T;
+            xv[u] = (act && n < N) ? __builtin_nontemporal_load(x + n) : v2d{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int n = tr + u * T;
+            if (n < N) buf[((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln] = {xv[u].x, xv[u].y};
+        }
+    } else {
+        constexpr int KP = (NMAX / 2 + 1 + T - 1) / T;
+        v2d xa[KP], xb[KP];
+#pragma unroll
+        for (int u = 0; u < KP; ++u) {
+            const int k = tr + u * T;
+            xa[u] = xb[u] = v2d{0.0, 0.0};
+            if (act && k <= N / 2) {
+                xa[u] = __builtin_nontemporal_load(x + k);
+                if (k > 0) xb[u] = __builtin_nontemporal_load(x + (N - k));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < KP; ++u) {
+            const int k = tr + u * T;
+            if (k > N / 2) continue;
+            double sn, cs;
+            sincospi((double)k / (2 * N), &sn, &cs);
+            const cplx wc = {cs, sn};                                   // conj(W) = exp(+i pi k/(2N))
+            const double P = xa[u].x, Q = xa[u].y, Pm = xb[u].x, Qm = xb[u].y;
+            const cplx vk = cmul(wc, {P + Qm, Q - Pm});
+            buf[k * L + ln] = cconj(vk);                               // conjugated: inverse by forward passes
+            if (k > 0 && N - k != k) {
+                // V_{N-k} = conj(W^{N-k})... = i conj(wc) ((P_{N-k} + Q_k) + i (Q_{N-k} - P_k))
+                const cplx t = cmul(cconj(wc), {Pm + Q, Qm - P});
+                buf[(N - k) * L + ln] = cconj(cplx{-t.im, t.re});
+            }
+        }
+    }
+    __syncthreads();
+
+    fft_lines<L, NMAX>(buf, TwSplit{lo, hi}, A.S, ln, tr);
+
+    if (!act) return;
+    if (!INV) {
+        for (int k = tr; k <= N / 2; k += T) {
+            const cplx vk = buf[k * L + ln];
+            const cplx vm = buf[(k == 0 ? 0 : N - k) * L + ln];
+            const cplx a = {0.5 * (vk.re + vm.re), 0.5 * (vk.im - vm.im)};
+            const cplx b = {0.5 * (vk.im + vm.im), -0.5 * (vk.re - vm.re)};
+            double sn, cs;
+            sincospi((double)k / (2 * N), &sn, &cs);
+            const cplx w = {cs, -sn};
+            const cplx wa = cmul(w, a), wb = cmul(w, b);
+            __builtin_nontemporal_store(v2d{wa.re, wb.re}, x + k);
+            if (k > 0 && N - k != k) __builtin_nontemporal_store(v2d{-wa.im, -wb.im}, x + (N - k));
+        }
+    } else {
+        const double inv_n = 1.0 / N;
+#pragma unroll
+        for (int u = 0; u < NPT; ++u) {
+            const int n = tr + u * T;
+            if (n >= N) continue;
+            const cplx z = buf[((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln];
+            __builtin_nontemporal_store(v2d{z.re * inv_n, -z.im * inv_n}, x + n);
+        }
+    }
 }
 
 template <int L, int MMAX>
@@ -411,8 +554,9 @@ static hipError_t launch_fft_t(const FftArgs &A, int kind, hipStream_t s)
     const size_t lds = fft_lds_bytes_t<L, MMAX>(A.S.M);
     const dim3 grid((unsigned)blocks), block(kFftThreads);
     switch (kind) {
-    case kFftForward: hipLaunchKernelGGL((k_rfft_z<L, MMAX, false>), grid, block, lds, s, A); break;
-    case kFftDivergence: hipLaunchKernelGGL((k_rfft_z<L, MMAX, true>), grid, block, lds, s, A); break;
+    case kFftForward: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 0>), grid, block, lds, s, A); break;
+    case kFftDivergence: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 1>), grid, block, lds, s, A); break;
+    case kFftDivergence3: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 2>), grid, block, lds, s, A); break;
     case kFftInverse: hipLaunchKernelGGL((k_irfft_z<L, MMAX, false>), grid, block, lds, s, A); break;
     default: hipLaunchKernelGGL((k_irfft_z<L, MMAX, true>), grid, block, lds, s, A); break;
     }
@@ -427,6 +571,53 @@ hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s)
     if (L == 32) return launch_fft_t<32, 144>(A, kind, s);
     if (L == 16) return A.S.M <= 144 ? launch_fft_t<16, 144>(A, kind, s) : launch_fft_t<16, 288>(A, kind, s);
     return A.S.M <= 144 ? launch_fft_t<8, 144>(A, kind, s) : launch_fft_t<8, kFftMaxM>(A, kind, s);
+}
+
+bool dct_shape(int64_t N, FftShape &S)
+{
+    if (N < 2 || (N & 1) || N > kDctMaxN) return false;
+    S = FftShape{};
+    S.M = (int)N;
+    int m = S.M;
+    const int order[4] = {4, 2, 3, 5};
+    for (int f : order)
+        while (m % f == 0) {
+            if (S.npass == kFftMaxPasses) return false;
+            S.radix[S.npass++] = f;
+            m /= f;
+        }
+    return m == 1;
+}
+
+template <int L, int NMAX>
+static hipError_t launch_dct_t(const DctArgs &A, bool inverse, hipStream_t s)
+{
+    const int64_t blocks = (A.rows + L - 1) / L;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = sizeof(cplx) * ((size_t)A.S.M * L + 64 + (A.S.M + 63) / 64);
+    if (inverse)
+        hipLaunchKernelGGL((k_dct_x<L, NMAX, true>), dim3((unsigned)blocks), dim3(kFftThreads), lds, s, A);
+    else
+        hipLaunchKernelGGL((k_dct_x<L, NMAX, false>), dim3((unsigned)blocks), dim3(kFftThreads), lds, s, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s)
+{
+    if (A.rows <= 0) return hipSuccess;
+    if (A.S.M <= 512) return launch_dct_t<8, 512>(A, inverse, s);
+    if (A.S.M <= 2048) return launch_dct_t<2, 2048>(A, inverse, s);
+    return launch_dct_t<1, kDctMaxN>(A, inverse, s);
+}
+
+hipError_t launch_grad_x(double *u, const double *phi, double dx, int64_t Nx, int64_t rows, hipStream_t s)
+{
+    if (Nx < 2 || rows <= 0) return hipSuccess;
+    const int64_t nbx = (Nx - 1 + 255) / 256;
+    const int64_t blocks = nbx * rows;
+    if (blocks > 0x7fffffffLL || Nx > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad_x, dim3((unsigned)blocks), dim3(256), 0, s, u, phi, dx, (int)Nx, (int)nbx);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,

@@ -185,12 +185,26 @@ struct FftArgs {
     const double *w = nullptr;          // divergence: w[Nz][Ny][Nx] (z-faces)
     const double *dy = nullptr;         // cell widths [Ny]
     double dz = 0.0;
+    const double *u = nullptr;          // 3-D divergence: u[Nz][Ny][Nx+1] (x-faces)
+    double dx = 0.0;
     double *xhat = nullptr;             // forward output [M+1][lines] complex
     const double *xhat_in = nullptr;    // inverse input [M+1][lines] complex
     double *x_out = nullptr;            // inverse output rows [Nz][lines]
     double *w_io = nullptr;             // inverse with correction: w, in place
 };
-enum { kFftForward = 0, kFftDivergence = 1, kFftInverse = 2, kFftInverseCorrect = 3 };
+enum { kFftForward = 0, kFftDivergence = 1, kFftInverse = 2, kFftInverseCorrect = 3, kFftDivergence3 = 4 };
+// Streamwise cosine transform of complex rows (N = 2^a 3^b 5^c, even,
+// <= kDctMaxN); S.M holds N.
+constexpr int kDctMaxN = 4096;
+struct DctArgs {
+    FftShape S;
+    double *x = nullptr;                // rows of N complex128, transformed in place
+    int64_t rows = 0;
+    int64_t row_stride = 0;             // complex elements between rows
+};
+bool dct_shape(int64_t N, FftShape &S);
+hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s);
+hipError_t launch_grad_x(double *u, const double *phi, double dx, int64_t Nx, int64_t rows, hipStream_t s);
 bool fft_shape(int64_t Nz, FftShape &S);
 hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s);
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,

@@ -248,3 +248,123 @@ def test_shifted_poisson_refusals(T, ctx):
     assert L.poisson_shifted_solve(*args(256, 8, 7)) == T.TRI_E_ARG                    # method
     T.tri_sync_status(ctx)
     assert torch.all(ph == 0)
+
+
+# ---- the 3-D step: cosine transform in x as well ----------------------------
+
+@pytest.mark.parametrize("nx,rows", [(2, 5), (6, 9), (10, 3), (24, 100), (96, 33), (200, 7), (512, 17), (640, 5),
+                                     (2048, 13), (4096, 3)])
+def test_streamwise_dct_matches_oracle(T, ctx, nx, rows):
+    from oracle import projection
+    rng = np.random.default_rng(nx + rows)
+    x = rng.standard_normal((rows, nx)) + 1j * rng.standard_normal((rows, nx))
+    d = dev(x, torch.complex128)
+    T.streamwise_dct(ctx, d)
+    T.tri_sync_status(ctx)
+    ref = projection.streamwise_dct(x)
+    assert line_relerr(host(d), ref, axis=1) <= TOL
+    T.streamwise_idct(ctx, d)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(d), x, axis=1) <= 1e-14
+    X = rng.standard_normal((rows, nx)) + 1j * rng.standard_normal((rows, nx))
+    d = dev(X, torch.complex128)
+    T.streamwise_idct(ctx, d)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(d), projection.streamwise_idct(X), axis=1) <= TOL
+
+
+def grid3(nx, ny, nz, seed):
+    dy, dz, v, w = grid(nx, ny, nz, seed)
+    rng = np.random.default_rng(seed + 100)
+    u = rng.standard_normal((nz, ny, nx + 1))
+    u[:, :, 0] = 0.0
+    u[:, :, nx] = 0.0
+    return 1.0 / nx, dy, dz, u, v, w
+
+
+@pytest.mark.parametrize("nx,ny,nz", [(6, 32, 24), (34, 17, 96), (64, 16, 288)])
+def test_divergence3d_and_correct3d_match_oracle(T, ctx, nx, ny, nz):
+    from oracle import projection
+    dx, dy, dz, u, v, w = grid3(nx, ny, nz, 7)
+    dh = cdev((nz // 2 + 1, ny, nx))
+    T.projection3d_divergence_rfft(ctx, dev(u), dev(v), dev(w), dx, dev(dy), dz, dh)
+    T.tri_sync_status(ctx)
+    ref = projection.spanwise_rfft(projection.divergence3d(u, v, w, dx, dy, dz))
+    assert line_relerr(host(dh), ref, axis=0) <= TOL
+    rng = np.random.default_rng(8)
+    ph = rng.standard_normal((nz // 2 + 1, ny, nx)) + 1j * rng.standard_normal((nz // 2 + 1, ny, nx))
+    du, dv, dw = dev(u), dev(v), dev(w)
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.projection3d_correct(ctx, dev(ph, torch.complex128), phi, du, dv, dw, dx, dev(dy), dz)
+    T.tri_sync_status(ctx)
+    u1, v1, w1, phi1 = projection.correct3d(ph, u, v, w, dx, dy, dz)
+    assert line_relerr(host(phi), phi1, axis=0) <= TOL
+    gu = host(du)
+    assert line_relerr(gu, u1, axis=2) <= TOL
+    assert np.all(gu[:, :, 0] == 0) and np.all(gu[:, :, nx] == 0)
+    assert line_relerr(host(dv), v1, axis=0) <= TOL
+    assert line_relerr(host(dw), w1, axis=0) <= TOL
+
+
+@pytest.mark.parametrize("nx,ny,nz,P", [(6, 32, 24, 4), (30, 64, 96, 8), (16, 64, 288, 8)])
+def test_projection3d_step_matches_oracle_and_is_divergence_free(T, ctx, orc, nx, ny, nz, P):
+    from oracle import projection
+    dx, dy, dz, u, v, w = grid3(nx, ny, nz, 9)
+    ay, cy, lamz = projection.metric(dy, nz, dz)
+    lamx = projection.metric_x(nx, dx)
+    du, dv, dw = dev(u), dev(v), dev(w)
+    ph = cdev((nz // 2 + 1, ny, nx))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.projection3d_step(ctx, du, dv, dw, dx, dev(dy), dz, dev(ay), dev(cy), dev(lamz), dev(lamx), ph, phi, P=P)
+    T.tri_sync_status(ctx)
+    u1, v1, w1, phi1 = projection.project3d(u, v, w, dx, dy, dz, P=P, method=orc.PPT)
+    gu, gv, gw = host(du), host(dv), host(dw)
+    assert line_relerr(host(phi), phi1, axis=0) <= TOL
+    assert line_relerr(gu, u1, axis=2) <= TOL
+    assert line_relerr(gv, v1, axis=0) <= TOL
+    assert line_relerr(gw, w1, axis=0) <= TOL
+    div0 = np.max(np.abs(projection.divergence3d(u, v, w, dx, dy, dz)))
+    assert np.max(np.abs(projection.divergence3d(gu, gv, gw, dx, dy, dz))) <= 1e-13 * div0
+
+
+def test_dct_refusals_touch_nothing(T, ctx):
+    L = T.lib()
+    x = torch.zeros(2 * 64, dtype=torch.float64, device="cuda")
+    assert L.streamwise_dct(ctx, x.data_ptr(), 13, 2) == T.TRI_E_SHAPE          # odd
+    assert L.streamwise_dct(ctx, x.data_ptr(), 14, 2) == T.TRI_E_UNSUPPORTED    # 7 = prime > 5
+    assert L.streamwise_idct(ctx, x.data_ptr(), 8192, 0) == T.TRI_E_UNSUPPORTED  # > 4096
+    assert L.streamwise_dct(ctx, x.data_ptr() + 8, 4, 2) == T.TRI_E_ARG          # not 16-byte aligned
+    assert L.streamwise_dct(ctx, x.data_ptr(), 4, -1) == T.TRI_E_ARG
+    T.tri_sync_status(ctx)
+    assert torch.all(x == 0)
+
+
+def test_projection3d_at_benchmark_grid(T, ctx):
+    """2048 x 256 x 288 with u on the x-faces: divergence free to round-off after the
+    full 3-D step (divergence of the GPU result formed with plain torch ops)."""
+    from oracle import projection
+    nx, ny, nz = 2048, 256, 288
+    dy = np.diff(W.tanh_faces(ny))
+    dx, dz = 1.0 / nx, 1.0 / nz
+    ay, cy, lamz = projection.metric(dy, nz, dz)
+    lamx = projection.metric_x(nx, dx)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    u = torch.randn((nz, ny, nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u[:, :, 0] = 0.0
+    u[:, :, nx] = 0.0
+    v = torch.randn((nz, ny + 1, nx), dtype=torch.float64, device="cuda", generator=g)
+    v[:, 0, :] = 0.0
+    v[:, ny, :] = 0.0
+    w = torch.randn((nz, ny, nx), dtype=torch.float64, device="cuda", generator=g)
+    ddy = dev(dy)
+
+    def div(uu, vv, ww):
+        return ((uu[:, :, 1:] - uu[:, :, :-1]) / dx + ((vv[:, 1:, :] - vv[:, :-1, :]) / ddy[None, :, None]
+                + (torch.roll(ww, -1, 0) - ww) / dz))
+
+    div0 = div(u, v, w).abs().max().item()
+    ph = cdev((nz // 2 + 1, ny, nx))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    T.projection3d_step(ctx, u, v, w, dx, ddy, dz, dev(ay), dev(cy), dev(lamz), dev(lamx), ph, phi, P=8)
+    T.tri_sync_status(ctx)
+    assert div(u, v, w).abs().max().item() <= 1e-13 * div0
