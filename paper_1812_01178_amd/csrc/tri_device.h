@@ -94,6 +94,45 @@ __device__ inline bool gtsv_pivot(int K, double *dl, double *dd, double *du, dou
     return true;
 }
 
+// The same elimination on arrays with element k at x[k * st] (a lane's
+// column of LDS arrays): dl, dd, du, du2 (fill, scratch), rhs -> solution.
+__device__ inline bool gtsv_pivot_strided(int K, double *dl, double *dd, double *du, double *du2, double *rhs,
+                                          int st)
+{
+    for (int k = 0; k < K - 1; ++k) {
+        const double dlk = dl[k * st], ddk = dd[k * st], duk = du[k * st];
+        if (fabs(ddk) >= fabs(dlk)) {
+            if (ddk == 0.0) return false;
+            const double l = dlk / ddk;
+            dd[(k + 1) * st] -= l * duk;
+            rhs[(k + 1) * st] -= l * rhs[k * st];
+            du2[k * st] = 0.0;
+        } else {
+            const double l = ddk / dlk;
+            const double old_ddk1 = dd[(k + 1) * st];
+            dd[k * st] = dlk;
+            dd[(k + 1) * st] = duk - l * old_ddk1;
+            du[k * st] = old_ddk1;
+            if (k < K - 2) {
+                const double f = du[(k + 1) * st];
+                du2[k * st] = f;
+                du[(k + 1) * st] = -l * f;
+            } else {
+                du2[k * st] = 0.0;
+            }
+            const double rk = rhs[k * st];
+            rhs[k * st] = rhs[(k + 1) * st];
+            rhs[(k + 1) * st] = rk - l * rhs[k * st];
+        }
+    }
+    if (dd[(K - 1) * st] == 0.0) return false;
+    rhs[(K - 1) * st] /= dd[(K - 1) * st];
+    if (K >= 2) rhs[(K - 2) * st] = (rhs[(K - 2) * st] - du[(K - 2) * st] * rhs[(K - 1) * st]) / dd[(K - 2) * st];
+    for (int k = K - 3; k >= 0; --k)
+        rhs[k * st] = (rhs[k * st] - du[k * st] * rhs[(k + 1) * st] - du2[k * st] * rhs[(k + 2) * st]) / dd[k * st];
+    return true;
+}
+
 // Dense Gaussian elimination with partial pivoting, K <= kGenKDense.
 __device__ inline bool dense_gepp(int K, double *M, double *rhs)
 {

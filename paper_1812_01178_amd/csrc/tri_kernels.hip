@@ -1143,24 +1143,32 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
         // Zbar (Eq. (10)) of this lane's line: row 2i-1 = [v_m^(L), w_m^(L), 1],
         // row 2i = [1, v_1^(R), w_1^(R)] around the diagonal; cyclic if periodic.
         const int NI = periodic ? P : P - 1, K = 2 * NI;
-        double rhs[kGenKMax];
         bool ok = true;
         if (!periodic) {
-            double dl[kGenKMax], dd[kGenKMax], du[kGenKMax];
-            for (int i = 1; i <= NI; ++i) {
-                const int Li = i - 1, Ri = i;
-                const int u1 = 2 * i - 2, u2 = 2 * i - 1;
-                if (u1 > 0) dl[u1 - 1] = S(3, Li);   // v_m^(L) (zero for L = 0)
-                dd[u1] = S(5, Li);                    // w_m^(L)
-                du[u1] = 1.0;
-                dl[u1] = 1.0;
-                dd[u2] = S(2, Ri);                    // v_1^(R)
-                if (u2 < K - 1) du[u2] = S(4, Ri);    // w_1^(R)
-                rhs[u1] = S(1, Li);
-                rhs[u2] = S(0, Ri);
+            // the band of every lane's Zbar in LDS (after the tips), solved by
+            // wavefront 0 alone; the other partitions read their y after the barrier
+            double *Z = sh + (size_t)6 * P * 64;
+            auto B = [&](int q, int k) -> double & { return Z[((size_t)q * K + k) * 64 + lane]; };
+            if (r == 0 && K > 0) {
+                for (int i = 1; i <= NI; ++i) {
+                    const int Li = i - 1, Ri = i;
+                    const int u1 = 2 * i - 2, u2 = 2 * i - 1;
+                    if (u1 > 0) B(0, u1 - 1) = S(3, Li);   // dl: v_m^(L) (zero for L = 0)
+                    B(1, u1) = S(5, Li);                    // dd: w_m^(L)
+                    B(2, u1) = 1.0;                         // du
+                    B(0, u1) = 1.0;                         // dl
+                    B(1, u2) = S(2, Ri);                    // dd: v_1^(R)
+                    if (u2 < K - 1) B(2, u2) = S(4, Ri);    // du: w_1^(R)
+                    B(4, u1) = S(1, Li);                    // rhs
+                    B(4, u2) = S(0, Ri);
+                }
+                ok = gtsv_pivot_strided(K, &B(0, 0), &B(1, 0), &B(2, 0), &B(3, 0), &B(4, 0), 64);
             }
-            if (K > 0) ok = gtsv_pivot(K, dl, dd, du, rhs);
+            __syncthreads();
+            if (has_l) yl = B(4, 2 * r - 1);   // r >= 1 here (not periodic)
+            if (has_r) yr = B(4, 2 * r);
         } else {
+            double rhs[kGenKDense];
             double Zm[kGenKDense * kGenKDense];
             for (int t = 0; t < K * kGenKDense; ++t) Zm[t] = 0.0;
             for (int i = 1; i <= NI; ++i) {
@@ -1177,13 +1185,13 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
                 rhs[u2] = S(0, Ri);
             }
             ok = dense_gepp(K, Zm, rhs);
+            if (has_l) {
+                const int il = (r >= 1) ? r : P;
+                yl = rhs[2 * il - 1];
+            }
+            if (has_r) yr = rhs[2 * r];
         }
         if (!ok && active) atomicOr(A.status, kStatusZeroPivot);
-        if (has_l) {
-            const int il = (r >= 1) ? r : P;
-            yl = rhs[2 * il - 1];
-        }
-        if (has_r) yr = rhs[2 * r];
     }
 
     // x = x~ - (y_left v + y_right w), with v + w reduced by the same pivots
@@ -1199,11 +1207,17 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
     }
 }
 
+size_t general_lds_bytes(int P, int periodic)
+{
+    const int K = periodic ? 0 : 2 * (P - 1);   // LDS band of the non-periodic reduced systems
+    return sizeof(double) * ((size_t)6 * P + 5 * K) * 64;
+}
+
 template <int CMAX, int METHOD>
 static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
-    const size_t lds = sizeof(double) * 6 * a.P * 64;
+    const size_t lds = general_lds_bytes(a.P, METHOD == TRI_PPT ? a.periodic : 1);
     if (a.lamz)
         hipLaunchKernelGGL((k_general<CMAX, METHOD, true>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
     else
