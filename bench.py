@@ -199,6 +199,7 @@ def main():
     pressure = None
     if not args.no_pressure:
         pressure = pressure_section(T, ctx, stream, args, nx, ny, nz, copy["GB_s"])
+        pressure["three_d"] = pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy["GB_s"])
 
     # ---------------- independent systems with their own coefficients -----
     independent = None
@@ -568,6 +569,96 @@ def pressure_section(T, ctx, stream, args, nx, ny, nz, copy_gbs):
     log(f"pressure step: {ms_step:.3f} ms, {out['GB_s']:.0f} GB/s over the step, "
         f"{cells / (ms_step * 1e-3) / 1e9:.1f} G cells/s")
     del v, w, ph, phi
+    torch.cuda.empty_cache()
+    return out
+
+
+def pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy_gbs):
+    """The 3-D projection (walls at both x-ends as well): divergence of
+    (u, v, w) fused into the spanwise FFT, streamwise cosine transform, the
+    shifted wall-normal solves (one matrix per (k, i), PPT, P = 8: at most
+    32 rows per partition on the fly), inverse cosine transform, inverse FFT
+    with the w correction, v and u corrections.  u[Nz][Ny][Nx+1] (x-end
+    faces zero), v, w as in the spanwise-only step, N(0,1) from torch's device
+    generator (seed 1).  Checked before timing: divergence free to round-off."""
+    import torch
+    import workloads as W
+    nk = nz // 2 + 1
+    P = 8
+    dy = np.diff(W.tanh_faces(ny))
+    dx, dz = 1.0 / nx, 1.0 / nz
+    ay, cy = W.poisson_metric(ny)
+    lamz = W.modified_wavenumbers(nz)
+    lamx = (4.0 / dx ** 2) * np.sin(np.pi * np.arange(nx) / (2 * nx)) ** 2
+    dev = lambda x: torch.as_tensor(np.ascontiguousarray(x)).cuda()
+    ddy, day, dcy, dlz, dlx = dev(dy), dev(ay), dev(cy), dev(lamz), dev(lamx)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    u = torch.randn((nz, ny, nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u[:, :, 0] = 0.0
+    u[:, :, nx] = 0.0
+    v = torch.randn((nz, ny + 1, nx), dtype=torch.float64, device="cuda", generator=g)
+    v[:, 0, :] = 0.0
+    v[:, ny, :] = 0.0
+    w = torch.randn((nz, ny, nx), dtype=torch.float64, device="cuda", generator=g)
+    ph = torch.empty((nk, ny, nx), dtype=torch.complex128, device="cuda")
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+
+    def div(uu, vv, ww):
+        return ((uu[:, :, 1:] - uu[:, :, :-1]) / dx + ((vv[:, 1:, :] - vv[:, :-1, :]) / ddy[None, :, None]
+                + (torch.roll(ww, -1, 0) - ww) / dz))
+
+    parts = ["divergence_rfft", "dct", "poisson_shifted", "idct", "correct"]
+    fns = (lambda: T.projection3d_divergence_rfft(ctx, u, v, w, dx, ddy, dz, ph),
+           lambda: T.streamwise_dct(ctx, ph),
+           lambda: T.poisson_shifted_solve(ctx, ph, day, dcy, dlz, dlx, P=P, method=T.TRI_PPT),
+           lambda: T.streamwise_idct(ctx, ph),
+           lambda: T.projection3d_correct(ctx, ph, phi, u, v, w, dx, ddy, dz))
+
+    def step(events=None):
+        for i, fn in enumerate(fns):
+            if events is not None:
+                events[i].record(stream)
+            fn()
+        if events is not None:
+            events[len(fns)].record(stream)
+
+    div0 = div(u, v, w).abs().max().item()
+    step()
+    T.tri_sync_status(ctx)
+    div1 = div(u, v, w).abs().max().item()
+    log(f"pressure 3-D: max |div| {div0:.3e} -> {div1:.3e} ({div1 / div0:.1e})")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(fns) + 1)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for s_ in range(args.steps):
+        step(ev[s_])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    T.tri_sync_status(ctx)
+    cells = nx * ny * nz
+    spec = 16 * nk * ny * nx
+    alg = {"divergence_rfft": 8 * nz * ny * (nx + 1) + 8 * nz * (ny + 1) * nx + 8 * cells + spec,
+           "dct": 2 * spec, "poisson_shifted": 2 * spec, "idct": 2 * spec,
+           "correct": spec + 8 * cells + 16 * cells + 8 * cells + 16 * nz * (ny - 1) * nx
+                      + 8 * cells + 16 * nz * ny * (nx - 1)}
+    kernels = {}
+    for i, n in enumerate(parts):
+        ms = float(np.mean([ev[s_][i].elapsed_time(ev[s_][i + 1]) for s_ in range(args.steps)]))
+        gbs = alg[n] / (ms * 1e-3) / 1e9
+        kernels[n] = {"ms": round(ms, 4), "alg_bytes": alg[n], "GB_s": round(gbs, 1),
+                      "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "copy_frac": round(gbs / copy_gbs, 4)}
+        log(f"pressure 3-D {n}: {ms:.4f} ms  {gbs:.0f} GB/s  ({100 * gbs / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    ms_step = wall * 1e3 / args.steps
+    total = sum(alg.values())
+    out = {"grid": [nx, ny, nz], "P": P, "ms_per_step": round(ms_step, 4), "alg_bytes": total,
+           "GB_s": round(total / (ms_step * 1e-3) / 1e9, 1),
+           "hbm_frac": round(total / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "cells_per_s": cells / (ms_step * 1e-3), "kernels": kernels,
+           "divergence_before": div0, "divergence_after": div1, "divergence_ratio": div1 / div0}
+    log(f"pressure 3-D step: {ms_step:.3f} ms, {out['GB_s']:.0f} GB/s over the step")
+    del u, v, w, ph, phi
     torch.cuda.empty_cache()
     return out
 

@@ -99,6 +99,27 @@ __device__ inline void dft<5>(cplx *v)
     v[3] = csub(p2, q2);
 }
 
+template <>
+__device__ inline void dft<8>(cplx *v)
+{
+    // two radix-4 transforms of the even and odd elements, joined by W_8^k
+    constexpr double h = 0.70710678118654752440;   // 1/sqrt(2)
+    cplx e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+    dft<4>(e);
+    dft<4>(o);
+    const cplx o1 = {h * (o[1].re + o[1].im), h * (o[1].im - o[1].re)};     // W_8 o1
+    const cplx o2 = cmul_mi(o[2]);                                          // W_8^2 o2
+    const cplx o3 = {h * (o[3].im - o[3].re), -h * (o[3].im + o[3].re)};    // W_8^3 o3
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
 constexpr int kFftThreads = 256;
 
 // One Stockham pass of radix R over the M-point transforms of the L lines in
@@ -107,11 +128,14 @@ constexpr int kFftThreads = 256;
 // (j/Ns) Ns R + (j mod Ns) + r Ns.
 // Twiddle W_M^q from a full table (M entries) or from two short ones
 // (W^q = W^{64 (q >> 6)} W^{q & 63}: 64 + M/64 entries, for long transforms).
+// With TwSplit a butterfly looks up W^a once and forms W^{ra} as powers.
 struct TwFull {
+    static constexpr bool kPowers = false;
     const cplx *t;
     __device__ cplx operator()(int q) const { return t[q]; }
 };
 struct TwSplit {
+    static constexpr bool kPowers = true;
     const cplx *lo, *hi;
     __device__ cplx operator()(int q) const { return cmul(hi[q >> 6], lo[q & 63]); }
 };
@@ -136,8 +160,18 @@ __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, 
         const int j = tr + it * T;
         if (j < nb) {
             const int jn = j % Ns;
+            if (TW::kPowers) {
+                const cplx w1 = twM(jn * tws);
+                cplx wr = w1;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twM(jn * r * tws));
+                for (int r = 1; r < R; ++r) {
+                    v[it][r] = cmul(v[it][r], wr);
+                    wr = cmul(wr, w1);
+                }
+            } else {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[it][r] = cmul(v[it][r], twM(jn * r * tws));
+            }
             dft<R>(v[it]);
             const int d = (j / Ns) * Ns * R + jn;
 #pragma unroll
@@ -154,6 +188,7 @@ __device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, in
     int Ns = 1;
     for (int s = 0; s < S.npass; ++s) {
         switch (S.radix[s]) {
+        case 8: fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 4: fft_pass<4, (MMAX / 4 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 2: fft_pass<2, (MMAX / 2 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 3: fft_pass<3, (MMAX / 3 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
@@ -579,7 +614,7 @@ bool dct_shape(int64_t N, FftShape &S)
     S = FftShape{};
     S.M = (int)N;
     int m = S.M;
-    const int order[4] = {4, 2, 3, 5};
+    const int order[5] = {8, 4, 2, 3, 5};   // fewest passes over LDS
     for (int f : order)
         while (m % f == 0) {
             if (S.npass == kFftMaxPasses) return false;
@@ -605,7 +640,12 @@ static hipError_t launch_dct_t(const DctArgs &A, bool inverse, hipStream_t s)
 hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s)
 {
     if (A.rows <= 0) return hipSuccess;
-    if (A.S.M <= 512) return launch_dct_t<8, 512>(A, inverse, s);
+    const char *e = getenv("TRI_DCT_ROWS");
+    const int want = e ? atoi(e) : 0;
+    if (A.S.M <= 512 && (want == 0 || want == 8)) return launch_dct_t<8, 512>(A, inverse, s);
+    // two rows per workgroup (measured on MI355X at N = 2048: 0.66 ms against
+    // 0.78 ms with one row); TRI_DCT_ROWS=1 selects one row
+    if (A.S.M <= 2048 && want == 1) return launch_dct_t<1, 2048>(A, inverse, s);
     if (A.S.M <= 2048) return launch_dct_t<2, 2048>(A, inverse, s);
     return launch_dct_t<1, kDctMaxN>(A, inverse, s);
 }

@@ -368,3 +368,20 @@ def test_projection3d_at_benchmark_grid(T, ctx):
     T.projection3d_step(ctx, u, v, w, dx, ddy, dz, dev(ay), dev(cy), dev(lamz), dev(lamx), ph, phi, P=8)
     T.tri_sync_status(ctx)
     assert div(u, v, w).abs().max().item() <= 1e-13 * div0
+
+
+@pytest.mark.parametrize("rows_per_group", ["1", "2", "8"])
+def test_streamwise_dct_every_row_width(T, ctx, rows_per_group, monkeypatch):
+    """The cosine transform at each rows-per-workgroup width (TRI_DCT_ROWS)."""
+    from oracle import projection
+    monkeypatch.setenv("TRI_DCT_ROWS", rows_per_group)
+    rng = np.random.default_rng(17)
+    for nx in (480, 2048):
+        x = rng.standard_normal((7, nx)) + 1j * rng.standard_normal((7, nx))
+        d = dev(x, torch.complex128)
+        T.streamwise_dct(ctx, d)
+        T.tri_sync_status(ctx)
+        assert line_relerr(host(d), projection.streamwise_dct(x), axis=1) <= TOL
+        T.streamwise_idct(ctx, d)
+        T.tri_sync_status(ctx)
+        assert line_relerr(host(d), x, axis=1) <= 1e-14
