@@ -641,8 +641,9 @@ def pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy_gbs):
     spec = 16 * nk * ny * nx
     alg = {"divergence_rfft": 8 * nz * ny * (nx + 1) + 8 * nz * (ny + 1) * nx + 8 * cells + spec,
            "dct": 2 * spec, "poisson_shifted": 2 * spec, "idct": 2 * spec,
+           # spectrum in, phi out, w read + write, phi read once for the u and v corrections
            "correct": spec + 8 * cells + 16 * cells + 8 * cells + 16 * nz * (ny - 1) * nx
-                      + 8 * cells + 16 * nz * ny * (nx - 1)}
+                      + 16 * nz * ny * (nx - 1)}
     kernels = {}
     for i, n in enumerate(parts):
         ms = float(np.mean([ev[s_][i].elapsed_time(ev[s_][i + 1]) for s_ in range(args.steps)]))

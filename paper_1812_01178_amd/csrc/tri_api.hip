@@ -1070,17 +1070,22 @@ tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, 
     if (!ctx) return TRI_E_ARG;
     if (!(dx > 0.0)) return fail(ctx, TRI_E_ARG, "projection3d_correct: dx must be > 0");
     if (!u || misaligned(u)) return fail(ctx, TRI_E_ARG, "projection3d_correct: null or misaligned u");
-    if (Nx >= 1 && Ny >= 1 && Nz >= 1) {
-        const int64_t lines = Nx * Ny;
-        const int64_t ub = 8 * Nz * (lines + Ny);
-        const void *p[4] = {phihat, phi, v, w};
-        const int64_t nb[4] = {16 * (Nz / 2 + 1) * lines, 8 * Nz * lines, 8 * Nz * (lines + Nx), 8 * Nz * lines};
-        for (int i = 0; i < 4; ++i)
-            if (ranges_overlap(u, ub, p[i], nb[i])) return fail(ctx, TRI_E_ARG, "projection3d_correct: arrays overlap");
-    }
-    tri_status st = projection_correct(ctx, phihat, phi, v, w, dy, dz, Nx, Ny, Nz);
+    FftArgs A;
+    tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, A.S, "projection3d_correct");
     if (st) return st;
-    HIP_TRY(ctx, launch_grad_x(u, phi, dx, Nx, Ny * Nz, ctx->stream));
+    if (!phihat || !phi || !v || !w || misaligned16(phihat) || misaligned(phi) || misaligned(v) || misaligned(w))
+        return fail(ctx, TRI_E_ARG, "projection3d_correct: null or misaligned array");
+    st = projection_arrays_disjoint(ctx, "projection3d_correct", phihat, phi, u, v, w, dy, Nx, Ny, Nz);
+    if (st) return st;
+    A.lines = Nx * Ny;
+    A.Nx = Nx;
+    A.dz = dz;
+    A.xhat_in = phihat;
+    A.x_out = phi;
+    A.w_io = w;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_fft(A, kFftInverseCorrect, ctx->stream));
+    HIP_TRY(ctx, launch_grad_xy(u, v, phi, dy, dx, Nx, Ny, Nz, ctx->stream));
     return TRI_OK;
 }
 

@@ -431,17 +431,29 @@ __global__ void __launch_bounds__(256) k_grad_y(double *v, const double *phi, co
     __builtin_nontemporal_store(__builtin_nontemporal_load(vp) - grad, vp);
 }
 
-// Streamwise gradient correction on the interior x-faces:
-// u[k][j][i] -= (phi[k][j][i] - phi[k][j][i-1]) / dx, i = 1..Nx-1.
-__global__ void __launch_bounds__(256) k_grad_x(double *u, const double *phi, double dx, int Nx, int nbx)
+// Both wall-parallel corrections of the 3-D step from one read of phi: at
+// cell (k, j, i), v[k][j][i] -= (phi_j - phi_{j-1})/h_j for j >= 1 and
+// u[k][j][i] -= (phi_i - phi_{i-1})/dx for i >= 1 (the neighbours' phi are
+// read again from cache); the wall faces j = 0, Ny and i = 0, Nx are left.
+__global__ void __launch_bounds__(256) k_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx,
+                                                  int Nx, int Ny, int nbx)
 {
     const int64_t row = blockIdx.x / nbx;                       // k Ny + j
-    const int i = 1 + (int)(blockIdx.x - row * nbx) * 256 + (int)threadIdx.x;
+    const int i = (int)(blockIdx.x - row * nbx) * 256 + (int)threadIdx.x;
     if (i >= Nx) return;
+    const int64_t k = row / Ny;
+    const int j = (int)(row - k * Ny);
     const double *p = phi + row * Nx + i;
-    double *up = u + row * (Nx + 1) + i;
-    const double grad = (p[0] - p[-1]) / dx;
-    __builtin_nontemporal_store(__builtin_nontemporal_load(up) - grad, up);
+    const double pc = p[0];
+    if (j >= 1) {
+        const double h = 0.5 * (dy[j - 1] + dy[j]);
+        double *vp = v + (k * (Ny + 1) + j) * Nx + i;
+        __builtin_nontemporal_store(__builtin_nontemporal_load(vp) - (pc - p[-Nx]) / h, vp);
+    }
+    if (i >= 1) {
+        double *up = u + row * (Nx + 1) + i;
+        __builtin_nontemporal_store(__builtin_nontemporal_load(up) - (pc - p[-1]) / dx, up);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -650,13 +662,15 @@ hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s)
     return launch_dct_t<1, kDctMaxN>(A, inverse, s);
 }
 
-hipError_t launch_grad_x(double *u, const double *phi, double dx, int64_t Nx, int64_t rows, hipStream_t s)
+hipError_t launch_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
+                          int64_t Ny, int64_t Nz, hipStream_t s)
 {
-    if (Nx < 2 || rows <= 0) return hipSuccess;
-    const int64_t nbx = (Nx - 1 + 255) / 256;
-    const int64_t blocks = nbx * rows;
-    if (blocks > 0x7fffffffLL || Nx > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_grad_x, dim3((unsigned)blocks), dim3(256), 0, s, u, phi, dx, (int)Nx, (int)nbx);
+    if (Nx < 1 || Ny < 1 || Nz < 1) return hipSuccess;
+    const int64_t nbx = (Nx + 255) / 256;
+    const int64_t blocks = nbx * Ny * Nz;
+    if (blocks > 0x7fffffffLL || Nx > 0x7fffffffLL || Ny > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_grad_xy, dim3((unsigned)blocks), dim3(256), 0, s, u, v, phi, dy, dx, (int)Nx, (int)Ny,
+                       (int)nbx);
     return hipGetLastError();
 }
 

@@ -204,7 +204,8 @@ struct DctArgs {
 };
 bool dct_shape(int64_t N, FftShape &S);
 hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s);
-hipError_t launch_grad_x(double *u, const double *phi, double dx, int64_t Nx, int64_t rows, hipStream_t s);
+hipError_t launch_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
+                          int64_t Ny, int64_t Nz, hipStream_t s);
 bool fft_shape(int64_t Nz, FftShape &S);
 hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s);
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,
