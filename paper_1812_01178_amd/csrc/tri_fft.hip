@@ -181,14 +181,18 @@ __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, 
     __syncthreads();
 }
 
-template <int L, int MMAX, class TW>
+// R8: radix-8 passes are compiled in (only where the plan uses them: their
+// registers would otherwise lower the occupancy of every transform kernel).
+template <int L, int MMAX, bool R8, class TW>
 __device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, int ln, int tr)
 {
     constexpr int T = kFftThreads / L;
     int Ns = 1;
     for (int s = 0; s < S.npass; ++s) {
         switch (S.radix[s]) {
-        case 8: fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 8:
+            if constexpr (R8) fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            break;
         case 4: fft_pass<4, (MMAX / 4 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 2: fft_pass<2, (MMAX / 2 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 3: fft_pass<3, (MMAX / 3 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
@@ -306,7 +310,7 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX>(buf, TwFull{twM}, A.S, ln, tr);
+    fft_lines<L, MMAX, false>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     v2d *out = reinterpret_cast<v2d *>(A.xhat);
@@ -389,7 +393,7 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX>(buf, TwFull{twM}, A.S, ln, tr);
+    fft_lines<L, MMAX, false>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     const double inv_m = 1.0 / M;
@@ -529,7 +533,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, NMAX>(buf, TwSplit{lo, hi}, A.S, ln, tr);
+    fft_lines<L, NMAX, true>(buf, TwSplit{lo, hi}, A.S, ln, tr);
 
     if (!act) return;
     if (!INV) {
