@@ -125,6 +125,22 @@ def exact(a, b, c, d, periodic: bool = False) -> np.ndarray:
     return cyclic(a, b, c, d) if periodic else thomas(a, b, c, d)
 
 
+def dense_solve(a, b, c, d, periodic: bool = False) -> np.ndarray:
+    """x = A^{-1} d for any nonsingular tridiagonal (cyclic if periodic) row set: the
+    plain definition, by Gaussian elimination with partial pivoting on the assembled
+    dense matrix (LAPACK through numpy).  The reference for general, non-dominant
+    systems, where eliminations without pivoting break down."""
+    a, b, c, d = map(_f64, (a, b, c, d))
+    n = b.size
+    A = np.diag(b)
+    if n > 1:
+        A += np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        if periodic:
+            A[0, n - 1] += a[0]
+            A[n - 1, 0] += c[n - 1]
+    return np.linalg.solve(A, d)
+
+
 def exact_ld(a, b, c, d, periodic: bool = False) -> np.ndarray:
     """x = A^{-1} d by Thomas (or the cyclic Sherman-Morrison solve) in long double."""
     a, b, c, d = map(_f64, (a, b, c, d))

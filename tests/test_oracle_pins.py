@@ -497,3 +497,16 @@ def test_error_paths(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.thomas(a, b0, c, np.ones(10))
     assert e.value.code == 3
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_dense_solve_non_dominant_exact_rational(orc, periodic):
+    """The reference for non-dominant systems equals exact rational elimination on a
+    system with zero diagonal entries (where elimination without pivoting divides by 0)."""
+    rng = np.random.default_rng(8)
+    n = 12
+    a, b, c = W.random_tridiag_nondominant(n, rng, periodic=periodic)
+    assert b[0] == 0.0 and b[7] == 0.0
+    d = rng.uniform(-1, 1, n)
+    xr = _exact_fraction_solve(dense(a, b, c, periodic), d)
+    assert relerr(orc.dense_solve(a, b, c, d, periodic), xr) < 1e-13

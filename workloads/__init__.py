@@ -142,6 +142,22 @@ def cfg_poisson_rhs(nx: int, ny: int, nz: int, seed: int = 0) -> np.ndarray:
     return spanwise_rfft(cfg_field(nx, ny, nz, seed))
 
 
+def random_tridiag_nondominant(n: int, rng: np.random.Generator, periodic: bool = False):
+    """Random non-symmetric rows far from diagonal dominance: |a|, |c| ~ U(0.5, 1) with
+    random signs, b ~ U(-0.3, 0.3) and b = 0 on every 7th row (so an elimination without
+    pivoting meets zero pivots); a[0], c[n-1] are zero unless periodic."""
+    sa = np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
+    sc = np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
+    a = sa * rng.uniform(0.5, 1.0, n)
+    c = sc * rng.uniform(0.5, 1.0, n)
+    b = rng.uniform(-0.3, 0.3, n)
+    b[::7] = 0.0
+    if not periodic:
+        a[0] = 0.0
+        c[-1] = 0.0
+    return a, b, c
+
+
 def random_tridiag(n: int, rng: np.random.Generator, margin: float = 1.0,
                    periodic: bool = False):
     """Random non-symmetric strictly dominant row set: |b| = |a| + |c| + margin*U(0.5,1.5).
