@@ -1050,8 +1050,8 @@ hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStr
 // shifted Poisson systems of GeneralArgs (coefficients formed on the fly from
 // the shared ay, cy and the line's shift, never stored).
 // ===========================================================================
-template <int CMAX, int METHOD, bool SHIFT>
-__global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const GeneralArgs A)
+template <int CMAX, int METHOD, bool SHIFT, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 {
     extern __shared__ double sh[];              // [6][P][64]
     const int lane = threadIdx.x & 63;
@@ -1090,37 +1090,133 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
     if (pin) x[0] = 0.0;
     const double a_first = (r >= 1 || periodic) ? ca[0] : 0.0;
     const double c_last = (r <= P - 2 || periodic) ? row_c(m - 1) : 0.0;
-    double cpp = 0.0, gx = 0.0, gvp = 0.0, beta_last = 0.0;
-    bool bad = false;
+
+    // Block elimination with diagonal pivoting (the local solver the PPT
+    // paragraph of Sec. 3.2 names): at row t the pivot is the 1x1 entry d_t, or
+    // the 2x2 block of rows t, t+1 when |d_t| sigma < kappa |a_{t+1} c_t|
+    // (Bunch-Kaufman test as used for tridiagonal systems, sigma the largest
+    // neighbouring entry, kappa = (sqrt 5 - 1)/2).  Every row ends as
+    // x_t = p_t - q_t x_{t+link}: link 1, or 2 for the first row of a 2x2
+    // block (bit t of `two`).  p for the right-hand side (x) and for the
+    // a-corner spike (gv), q in cp.  Diagonally dominant rows always take the
+    // 1x1 pivot (plain Thomas); the shifted Poisson rows are, so SHIFT
+    // compiles the test out, and so does PDD (meant for dominant rows: on
+    // others its truncation is inaccurate whatever the pivots).
+    constexpr bool PIVOT = !SHIFT && METHOD == TRI_PPT;
+    constexpr double kKappa = 0.61803398874989484820;
+    uint64_t two = 0;
+    double pq = 0.0, px = 0.0, pv = 0.0;       // q, p of the row before (link 1 to this row)
+    double wl1 = 0.0, wl2 = 0.0;               // p of the c-corner spike at rows m-1, m-2
+    bool bad = false, pend = false;
+    double xl = 0.0, vm = 0.0, wm = 0.0, xf = 0.0, v0 = 0.0, w0 = 0.0;
+    if constexpr (!PIVOT) {
+        // 1x1 pivots only (plain Thomas), w from the product of the multipliers
+        double cpp = 0.0, gx = 0.0, gvp = 0.0, beta_last = 0.0;
 #pragma unroll
-    for (int t = 0; t < CMAX; ++t)
-        if (t < m) {
-            const double aa = (t == 0) ? 0.0 : ca[t * csj];
-            const double ccv = (t == m - 1) ? 0.0 : row_c(t);
-            const double den = row_b(t) - aa * cpp;
-            bad |= !(den != 0.0);
-            const double beta = 1.0 / den;
-            gx = (x[t] - aa * gx) * beta;
-            x[t] = gx;
-            gvp = (t == 0) ? a_first * beta : -(aa * beta) * gvp;
-            gv[t] = gvp;
-            cpp = ccv * beta;
-            cp[t] = cpp;
-            beta_last = beta;
+        for (int t = 0; t < CMAX; ++t)
+            if (t < m) {
+                const double aa = (t == 0) ? 0.0 : ca[t * csj];
+                const double ccv = (t == m - 1) ? 0.0 : row_c(t);
+                const double den = row_b(t) - aa * cpp;
+                bad |= !(den != 0.0);
+                const double beta = 1.0 / den;
+                gx = (x[t] - aa * gx) * beta;
+                x[t] = gx;
+                gvp = (t == 0) ? a_first * beta : -(aa * beta) * gvp;
+                gv[t] = gvp;
+                cpp = ccv * beta;
+                cp[t] = cpp;
+                beta_last = beta;
+            }
+        if (bad && active) atomicOr(A.status, kStatusZeroPivot);
+        xl = gx, vm = gvp;
+        double xn = 0.0, vn = 0.0, cprod = 1.0;
+#pragma unroll
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < m) {
+                xn = x[t] - cp[t] * xn;
+                x[t] = xn;
+                vn = gv[t] - cp[t] * vn;
+                if (t < m - 1) cprod *= -cp[t];
+            }
+        xf = x[0], v0 = vn;
+        wm = beta_last * c_last, w0 = wm * cprod;
+        wl1 = wm;
+    } else {
+#pragma unroll
+    for (int t = 0; t < CMAX; ++t) {
+        if (t >= m) continue;
+        if (pend) {                            // second row of a 2x2 block, done with its first
+            pend = false;
+            continue;
         }
+        const double at = (t == 0) ? 0.0 : ca[t * csj];
+        const double ct = (t == m - 1) ? 0.0 : row_c(t);
+        const double d = row_b(t) - at * pq;
+        const double rx = x[t] - at * px;
+        const double rv = ((t == 0) ? a_first : 0.0) - at * pv;
+        bool use2 = false;
+        double a1 = 0.0, b1 = 0.0, c1 = 0.0;
+        if (PIVOT && t + 1 < CMAX && t + 1 < m) {
+            a1 = ca[(t + 1) * csj];
+            b1 = row_b(t + 1);
+            c1 = (t + 1 == m - 1) ? 0.0 : row_c(t + 1);
+            const double a2 = (t + 2 < m) ? ca[(t + 2) * csj] : 0.0;
+            const double sg = fmax(fmax(fmax(fabs(ct), fabs(a1)), fmax(fabs(b1), fabs(c1))), fabs(a2));
+            use2 = fabs(d) * sg < kKappa * fabs(a1 * ct);
+        }
+        if (!use2) {
+            bad |= !(d != 0.0);
+            const double beta = 1.0 / d;
+            x[t] = rx * beta;
+            gv[t] = rv * beta;
+            cp[t] = ct * beta;
+            pq = cp[t];
+            px = x[t];
+            pv = gv[t];
+            if (t == m - 1) wl1 = c_last * beta;
+        } else if (t + 1 < CMAX) {
+            const double det = d * b1 - ct * a1;
+            bad |= !(det != 0.0);
+            const double idet = 1.0 / det;
+            const double r1 = x[t + 1];        // row t+1's own right-hand side (the spike's is 0)
+            x[t] = (b1 * rx - ct * r1) * idet;
+            gv[t] = (b1 * rv) * idet;
+            cp[t] = -(ct * c1) * idet;         // x_t couples to x_{t+2}
+            x[t + 1] = (d * r1 - a1 * rx) * idet;
+            gv[t + 1] = -(a1 * rv) * idet;
+            cp[t + 1] = (d * c1) * idet;
+            two |= 1ull << t;
+            pq = cp[t + 1];
+            px = x[t + 1];
+            pv = gv[t + 1];
+            if (t + 1 == m - 1) {
+                wl2 = -(ct * c_last) * idet;
+                wl1 = (d * c_last) * idet;
+            }
+            pend = true;
+        }
+    }
     if (bad && active) atomicOr(A.status, kStatusZeroPivot);
-    const double xl = gx, vm = gvp;
-    double xn = 0.0, vn = 0.0, cprod = 1.0;
+    // back substitution of x~, v (a-corner spike) and w (c-corner spike),
+    // keeping the values of the two rows below
+    double x1 = 0.0, x2 = 0.0, v1 = 0.0, v2 = 0.0, w1 = 0.0, w2 = 0.0;
 #pragma unroll
     for (int t = CMAX - 1; t >= 0; --t)
         if (t < m) {
-            xn = x[t] - cp[t] * xn;
-            x[t] = xn;
-            vn = gv[t] - cp[t] * vn;
-            if (t < m - 1) cprod *= -cp[t];
+            const bool l2 = (two >> t) & 1;
+            const double xt = x[t] - cp[t] * (l2 ? x2 : x1);
+            const double vt = gv[t] - cp[t] * (l2 ? v2 : v1);
+            const double pw = (t == m - 1) ? wl1 : ((t == m - 2) ? wl2 : 0.0);
+            const double wt = pw - cp[t] * (l2 ? w2 : w1);
+            x[t] = xt;
+            x2 = x1, x1 = xt;
+            v2 = v1, v1 = vt;
+            w2 = w1, w1 = wt;
+            if (t == m - 1) xl = xt, vm = vt, wm = wt;
         }
-    const double xf = x[0], v0 = vn;
-    const double wm = beta_last * c_last, w0 = wm * cprod;
+    xf = x1, v0 = v1, w0 = w1;
+    }
 
     auto S = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * 64 + lane]; };
     S(0, r) = xf; S(1, r) = xl; S(2, r) = v0; S(3, r) = vm; S(4, r) = w0; S(5, r) = wm;
@@ -1195,13 +1291,24 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_general(const Genera
     }
 
     // x = x~ - (y_left v + y_right w), with v + w reduced by the same pivots
-    if (active) {
+    if (active && !PIVOT) {
         double dn = 0.0;
 #pragma unroll
         for (int t = CMAX - 1; t >= 0; --t)
             if (t < m) {
                 const double gd = yl * gv[t] + ((t == m - 1) ? yr * wm : 0.0);
                 dn = gd - cp[t] * dn;
+                p[t * sj] = x[t] - dn;
+            }
+    } else if (active) {
+        double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+        for (int t = CMAX - 1; t >= 0; --t)
+            if (t < m) {
+                const bool l2 = (two >> t) & 1;
+                const double pw = (t == m - 1) ? wl1 : ((t == m - 2) ? wl2 : 0.0);
+                const double dn = (yl * gv[t] + yr * pw) - cp[t] * (l2 ? d2 : d1);
+                d2 = d1, d1 = dn;
                 p[t * sj] = x[t] - dn;
             }
     }
@@ -1218,10 +1325,23 @@ static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
     const size_t lds = general_lds_bytes(a.P, METHOD == TRI_PPT ? a.periodic : 1);
+    // P > 8 partitions need 1024-lane workgroups (at most 128 VGPRs a lane);
+    // fewer run with the 512-lane bound and twice the registers
+    // (more than 16 rows per partition come with at most 8 partitions)
+    if constexpr (CMAX <= 16) {
+        if (a.P > 8) {
+            if (a.lamz)
+                hipLaunchKernelGGL((k_general<CMAX, METHOD, true, 1024>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+            else
+                hipLaunchKernelGGL((k_general<CMAX, METHOD, false, 1024>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+            return hipGetLastError();
+        }
+    }
+    if (a.P > 8) return hipErrorInvalidValue;
     if (a.lamz)
-        hipLaunchKernelGGL((k_general<CMAX, METHOD, true>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+        hipLaunchKernelGGL((k_general<CMAX, METHOD, true, 512>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
     else
-        hipLaunchKernelGGL((k_general<CMAX, METHOD, false>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+        hipLaunchKernelGGL((k_general<CMAX, METHOD, false, 512>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
     return hipGetLastError();
 }
 

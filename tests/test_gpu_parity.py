@@ -556,3 +556,56 @@ def test_autotuned_plan_matches_oracle(T, ctx, orc, monkeypatch):
         assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) <= TOL
     finally:
         T.tri_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("n,P,periodic", [(48, 4, False), (48, 2, False), (64, 2, False), (48, 8, False),
+                                          (24, 4, True), (36, 3, True)])
+def test_general_non_dominant_diagonal_pivoting(T, ctx, orc, n, P, periodic):
+    """Rows far from diagonal dominance (zero diagonal entries every 7th row): the
+    per-line PPT solve picks 2x2 pivots where a 1x1 pivot would be zero or small, and
+    reaches A^{-1} d.  Each line's error is held to max(1e-12, 64 eps kappa), kappa the
+    largest condition number of the line and of its partition blocks."""
+    nlines = 150
+    rng = np.random.default_rng(900 + n + P)
+    A = np.empty((nlines, n)); B = np.empty((nlines, n)); C = np.empty((nlines, n))
+    for s in range(nlines):
+        A[s], B[s], C[s] = W.random_tridiag_nondominant(n, rng, periodic=periodic)
+    D = rng.uniform(-1, 1, (n, nlines))
+    At, Bt, Ct = (np.ascontiguousarray(X.T) for X in (A, B, C))
+    dd = dev(D)
+    T.tri_ppt_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0),
+                    coef_strides=(nlines, 1, 0), P=P, periodic=periodic)
+    T.tri_sync_status(ctx)                      # no zero pivot reported
+    got = host(dd)
+    m = n // P
+    for s in range(nlines):
+        ref = orc.dense_solve(A[s], B[s], C[s], D[:, s], periodic)
+        full = np.diag(B[s]) + np.diag(A[s, 1:], -1) + np.diag(C[s, :-1], 1)
+        if periodic:
+            full[0, -1] += A[s, 0]
+            full[-1, 0] += C[s, -1]
+        kappa = np.linalg.cond(full)
+        for r in range(P):
+            blk = full[r * m:(r + 1) * m, r * m:(r + 1) * m]
+            kappa = max(kappa, np.linalg.cond(blk))
+        err = np.max(np.abs(got[:, s] - ref)) / np.max(np.abs(ref))
+        assert err <= max(TOL, 64 * 2.2e-16 * kappa), (s, err, kappa)
+
+
+def test_general_pivoting_keeps_dominant_rows_on_1x1_pivots(T, ctx, orc):
+    """On diagonally dominant rows the pivot test never takes a 2x2 block: the result
+    matches the oracle's PPT (Thomas blocks) as before."""
+    n, P, nlines = 64, 4, 130
+    rng = np.random.default_rng(41)
+    A = np.empty((nlines, n)); B = np.empty((nlines, n)); C = np.empty((nlines, n))
+    for s in range(nlines):
+        A[s], B[s], C[s] = W.random_tridiag(n, rng, margin=0.05)
+    D = rng.uniform(-1, 1, (n, nlines))
+    At, Bt, Ct = (np.ascontiguousarray(X.T) for X in (A, B, C))
+    ref = D.copy().ravel()
+    orc.solve_batch(orc.PPT, ref, n, nlines, 1, s_j=nlines, s_b0=1, s_b1=0, a=At.ravel(), b=Bt.ravel(),
+                    c=Ct.ravel(), cs_j=nlines, cs_b0=1, cs_b1=0, P=P)
+    dd = dev(D)
+    T.tri_ppt_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0), coef_strides=(nlines, 1, 0), P=P)
+    T.tri_sync_status(ctx)
+    assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
