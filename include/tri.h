@@ -138,7 +138,12 @@ tri_status tri_pdd_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lin
 /* PPT over a batch of lines (Sec. 3.2, Eqs. (9)-(11)): the same local
  * solves, the tridiagonal (cyclic when periodic) system Zbar y = E^T x~ solved
  * with partial pivoting in FP64, and x = x~ - Ybar y.  Exact for any P.
- * Arguments as tri_pdd_solve. */
+ * With coefficients per line (any cs_b0/cs_b1 != 0) and TRI_F64, the
+ * partition blocks are factored with diagonal pivoting (1x1 or 2x2 pivots,
+ * the local solver the PPT paragraph names), so general tridiagonal systems
+ * that are not diagonally dominant solve as long as every block is
+ * nonsingular; diagonally dominant rows always take 1x1 pivots.  Shared
+ * matrices and PDD use 1x1 pivots.  Arguments as tri_pdd_solve. */
 tri_status tri_ppt_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines,
                          tri_field field, void *d_inout, int P, int periodic,
                          tri_prec prec, tri_info *info);
