@@ -385,3 +385,56 @@ def test_streamwise_dct_every_row_width(T, ctx, rows_per_group, monkeypatch):
         T.streamwise_idct(ctx, d)
         T.tri_sync_status(ctx)
         assert line_relerr(host(d), x, axis=1) <= 1e-14
+
+
+def test_pressure_steps_replay_from_hip_graphs(T, ctx, orc):
+    """Both projections allocate nothing and never synchronise, so they record into a
+    HIP graph: the 3-D step as one call, the spanwise-only step with its Poisson solve as
+    a plan.  Each graph is replayed three times, with eager restores and synchronisations
+    between the replays, and every replay is checked against the eager result."""
+    from oracle import projection
+    nx, ny, nz = 30, 64, 96
+    dx, dy, dz, u0, v0, w0 = grid3(nx, ny, nz, 21)
+    ay, cy, lamz = projection.metric(dy, nz, dz)
+    lamx = projection.metric_x(nx, dx)
+    dd = [dev(t) for t in (dy, ay, cy, lamz, lamx)]
+    u, v, w = dev(u0), dev(v0), dev(w0)
+    ph = cdev((nz // 2 + 1, ny, nx))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    # eager references
+    T.projection3d_step(ctx, u, v, w, dx, dd[0], dz, dd[1], dd[2], dd[3], dd[4], ph, phi, P=8)
+    T.tri_sync_status(ctx)
+    ref3 = [t.clone() for t in (u, v, w, phi)]
+    v.copy_(dev(v0)); w.copy_(dev(w0))
+    plan = T.tri_plan_create(ctx, [dict(kind=T.TRI_ITEM_POISSON, field=ph, Nx=nx, Ny=ny, Nz=nz // 2 + 1, a=dd[1],
+                                        c=dd[2], lam=dd[3], P=4, method=T.TRI_PPT)])
+    try:
+        def step2():
+            T.projection_divergence_rfft(ctx, v, w, dd[0], dz, ph)
+            T.tri_plan_execute(plan)
+            T.projection_correct(ctx, ph, phi, v, w, dd[0], dz)
+        step2()
+        T.tri_sync_status(ctx)
+        ref2 = [t.clone() for t in (v, w, phi)]
+        graphs = []
+        side = torch.cuda.Stream()
+        for body in (lambda: T.projection3d_step(ctx, u, v, w, dx, dd[0], dz, dd[1], dd[2], dd[3], dd[4], ph, phi,
+                                                 P=8), step2):
+            g = torch.cuda.CUDAGraph()
+            T.tri_set_stream(ctx, side.cuda_stream)
+            with torch.cuda.graph(g, stream=side):
+                body()
+            T.tri_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+            graphs.append(g)
+        for rep in range(3):
+            for g, ref, tensors in ((graphs[0], ref3, (u, v, w, phi)), (graphs[1], ref2, (v, w, phi))):
+                u.copy_(dev(u0)); v.copy_(dev(v0)); w.copy_(dev(w0)); phi.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                for got, want in zip(tensors, ref):
+                    assert torch.equal(got, want), rep
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+        T.tri_plan_destroy(plan)
