@@ -1240,7 +1240,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
         // row 2i = [1, v_1^(R), w_1^(R)] around the diagonal; cyclic if periodic.
         const int NI = periodic ? P : P - 1, K = 2 * NI;
         bool ok = true;
-        if (!periodic) {
+        if (SHIFT || !periodic) {             // (shifted systems are never periodic)
             // the band of every lane's Zbar in LDS (after the tips), solved by
             // wavefront 0 alone; the other partitions read their y after the barrier
             double *Z = sh + (size_t)6 * P * 64;
