@@ -1,6 +1,7 @@
 // tri_fft.hip -- the pressure step around the Poisson wavenumber solves
 // (Sec. 2.2): spanwise real FFT of the divergence of the intermediate
-// velocity, inverse FFT of the pseudo-pressure, gradient correction.
+// velocity, inverse FFT of the pseudo-pressure, gradient correction; for the
+// 3-D step also the streamwise cosine transform (at the end of the file).
 //
 // Layout: fields [Nz][Ny][Nx] FP64, x fastest.  A spanwise line is one
 // (j, i) station; the Ny*Nx stations of a z-plane are contiguous, so the
@@ -16,7 +17,8 @@
 // complex FFT as conj(DFT_M(conj Z))/M; the imaginary parts of X_0 and X_M
 // are ignored (they are zero for the spectrum of a real line).
 //
-// The complex FFT is a self-sorting mixed-radix (4, 2, 3, 5) Stockham
+// The complex FFT is a self-sorting mixed-radix (4, 2, 3, 5; 8 as well for
+// the cosine transform) Stockham
 // transform held in LDS: a workgroup takes L neighbouring lines (L doubles
 // per plane row, coalesced), T = 256/L threads per line; in every pass a
 // thread reads its butterflies' inputs into registers, the workgroup
@@ -122,10 +124,6 @@ __device__ inline void dft<8>(cplx *v)
 
 constexpr int kFftThreads = 256;
 
-// One Stockham pass of radix R over the M-point transforms of the L lines in
-// buf[M][L].  Butterfly j reads elements j + r M/R, twiddles element r by
-// W_{Ns R}^{(j mod Ns) r} = twM[(j mod Ns) r M/(Ns R)], and writes output r to
-// (j/Ns) Ns R + (j mod Ns) + r Ns.
 // Twiddle W_M^q from a full table (M entries) or from two short ones
 // (W^q = W^{64 (q >> 6)} W^{q & 63}: 64 + M/64 entries, for long transforms).
 // With TwSplit a butterfly looks up W^a once and forms W^{ra} as powers.
@@ -140,6 +138,10 @@ struct TwSplit {
     __device__ cplx operator()(int q) const { return cmul(hi[q >> 6], lo[q & 63]); }
 };
 
+// One Stockham pass of radix R over the M-point transforms of the L lines in
+// buf[M][L].  Butterfly j reads elements j + r M/R, twiddles element r by
+// W_{Ns R}^{(j mod Ns) r} = twM((j mod Ns) r M/(Ns R)), and writes output r to
+// (j/Ns) Ns R + (j mod Ns) + r Ns.
 template <int R, int IT, class TW>
 __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, int ln, int tr, int T)
 {
