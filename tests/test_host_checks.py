@@ -1,0 +1,97 @@
+"""Host-side checks that need no GPU: the bench's self-checks (backward errors)
+detect wrong solutions, the bench refuses more than one GPU, and the product
+code never reaches the oracle (only the tests, smoke() and the bench's CPU
+baseline may)."""
+import ast
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    sys.path.insert(0, ROOT)
+    import bench
+    return bench
+
+
+def _dense(a, b, c, periodic):
+    n = b.size
+    A = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+    if periodic:
+        A[0, -1] += a[0]
+        A[-1, 0] += c[-1]
+    return A
+
+
+def test_line_residual_accepts_solutions_and_rejects_perturbed_ones():
+    bench = _bench()
+    rng = np.random.default_rng(3)
+    for periodic in (False, True):
+        a, b, c = W.random_tridiag(40, rng, periodic=periodic)
+        d = rng.standard_normal((6, 40))
+        x = np.linalg.solve(_dense(a, b, c, periodic), d.T).T
+        assert bench.line_residual(a, b, c, x, d, periodic) < 1e-15
+        x[3, 17] *= 1 + 1e-9
+        assert bench.line_residual(a, b, c, x, d, periodic) > 1e-11
+
+
+def test_apply_tri_composes_along_axes():
+    """A_z A_y A_x applied along three axes equals the Kronecker-structured product."""
+    bench = _bench()
+    rng = np.random.default_rng(4)
+    u = rng.standard_normal((5, 4, 6))
+    cx, cy, cz = W.momentum_uniform(6), W.momentum_stretched(4), W.momentum_periodic(5)
+    y = u
+    for (a, b, c), axis, per in ((cz, 0, True), (cy, 1, False), (cx, 2, False)):
+        y, _ = bench.apply_tri(a, b, c, y, axis, per)
+    want = np.einsum("ai,bj,ck,ijk->abc", _dense(*cz, True), _dense(*cy, False), _dense(*cx, False), u)
+    assert np.max(np.abs(y - want)) < 1e-12 * np.max(np.abs(want))
+
+
+def test_poisson_rows_pin_the_zero_mode():
+    bench = _bench()
+    ay, cy = W.poisson_metric(16)
+    lam = W.modified_wavenumbers(8)
+    a, b, c, pin = bench.poisson_rows(ay, cy, lam)
+    assert pin[0] and not pin[1:].any()
+    assert b[0, 0] == 1.0 and c[0, 0] == 0.0 and a[0, 0] == 0.0
+    assert np.array_equal(b[1], -(ay + cy) - lam[1])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def _imports(path):
+    tree = ast.parse(open(path).read())
+    names = set()
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Import):
+            names.update(a.name.split(".")[0] for a in node.names)
+        elif isinstance(node, ast.ImportFrom) and node.module:
+            names.add(node.module.split(".")[0])
+    return names
+
+
+def test_product_code_does_not_use_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1812_01178_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith(".py"):
+                assert "oracle" not in _imports(os.path.join(dirpath, f)), f
+    for f in os.listdir(os.path.join(ROOT, "workloads")):
+        if f.endswith(".py"):
+            assert "oracle" not in _imports(os.path.join(ROOT, "workloads", f)), f
+    # bench.py: only inside the CPU-baseline block of main()
+    src = open(os.path.join(ROOT, "bench.py")).read().splitlines()
+    uses = [i for i, ln in enumerate(src) if "import oracle" in ln or "from oracle" in ln]
+    assert len(uses) == 1 and "cpu_baseline" in src[uses[0] + 1]
