@@ -438,3 +438,32 @@ def test_pressure_steps_replay_from_hip_graphs(T, ctx, orc):
     finally:
         T.tri_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
         T.tri_plan_destroy(plan)
+
+
+def test_projection_steps_refuse_before_any_launch(T, ctx):
+    """Overlapping outputs, a misaligned spectrum or an unsupported shape are refused
+    before the first kernel: the velocity is left exactly as it was."""
+    from oracle import projection
+    nx, ny, nz = 12, 32, 24
+    dx, dy, dz, u0, v0, w0 = grid3(nx, ny, nz, 13)
+    ay, cy, lamz = projection.metric(dy, nz, dz)
+    lamx = projection.metric_x(nx, dx)
+    dd = [dev(t) for t in (dy, ay, cy, lamz, lamx)]
+    u, v, w = dev(u0), dev(v0), dev(w0)
+    ph = cdev((nz // 2 + 1, ny, nx))
+    phi = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+    L = T.lib()
+    ptr = lambda t: t.data_ptr()
+
+    def step3(phihat_p, phi_p, P=8, Nx=nx):
+        return L.projection3d_step(ctx, ptr(u), ptr(v), ptr(w), dx, ptr(dd[0]), dz, ptr(dd[1]), ptr(dd[2]),
+                                   ptr(dd[3]), ptr(dd[4]), phihat_p, phi_p, Nx, ny, nz, P)
+    assert step3(ptr(ph), ptr(ph)) == T.TRI_E_ARG                 # phi inside phihat
+    assert step3(ptr(ph) + 8, ptr(phi)) == T.TRI_E_ARG             # spectrum not 16-byte aligned
+    assert step3(ptr(ph), ptr(u)) == T.TRI_E_ARG                   # phi over u
+    assert step3(ptr(ph), ptr(phi), P=3) == T.TRI_E_UNSUPPORTED    # 32 rows do not split in 3
+    assert step3(ptr(ph), ptr(phi), Nx=14) == T.TRI_E_UNSUPPORTED  # 7 is not a supported factor
+    assert L.projection_step(ctx, ptr(v), ptr(w), ptr(dd[0]), dz, ptr(dd[1]), ptr(dd[2]), ptr(dd[3]), ptr(ph),
+                             ptr(ph), nx, ny, nz, 4) == T.TRI_E_ARG
+    T.tri_sync_status(ctx)
+    assert torch.equal(u, dev(u0)) and torch.equal(v, dev(v0)) and torch.equal(w, dev(w0))
