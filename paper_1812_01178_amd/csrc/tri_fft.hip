@@ -483,15 +483,23 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
     cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [N][L]
     cplx *lo = buf + (size_t)N * L;                  // W_N^t, t < 64
     cplx *hi = lo + 64;                              // W_N^{64 s}
+    const int nhi = (N + 63) / 64;
+    cplx *q4 = hi + nhi;                             // W_{4N}^r, r < 4
     const int ln = threadIdx.x % L, tr = threadIdx.x / L;
     const int64_t row = (int64_t)blockIdx.x * L + ln;
     const bool act = row < A.rows;
     v2d *x = reinterpret_cast<v2d *>(A.x) + (act ? row : 0) * A.row_stride;
-    for (int t = threadIdx.x; t < 64 + (N + 63) / 64; t += kFftThreads) {
+    for (int t = threadIdx.x; t < 64 + nhi + 4; t += kFftThreads) {
         double sn, cs;
-        sincospi(2.0 * (t < 64 ? t : 64 * (t - 64)) / N, &sn, &cs);
-        lo[t] = {cs, -sn};   // hi follows lo contiguously
+        if (t < 64 + nhi)
+            sincospi(2.0 * (t < 64 ? t : 64 * (t - 64)) / N, &sn, &cs);
+        else
+            sincospi((double)(t - 64 - nhi) / (2 * N), &sn, &cs);
+        lo[t] = {cs, -sn};   // hi and q4 follow lo contiguously
     }
+    // exp(-i pi k/(2N)) = W_{4N}^k = W_N^{k/4} W_{4N}^{k mod 4}
+    const TwSplit twn{lo, hi};
+    auto w4 = [&](int k) { return cmul(twn(k >> 2), q4[k & 3]); };
     if (!INV) {
         v2d xv[NPT];
 #pragma unroll
@@ -520,9 +528,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
         for (int u = 0; u < KP; ++u) {
             const int k = tr + u * T;
             if (k > N / 2) continue;
-            double sn, cs;
-            sincospi((double)k / (2 * N), &sn, &cs);
-            const cplx wc = {cs, sn};                                   // conj(W) = exp(+i pi k/(2N))
+            const cplx wc = cconj(w4(k));                               // conj(W) = exp(+i pi k/(2N))
             const double P = xa[u].x, Q = xa[u].y, Pm = xb[u].x, Qm = xb[u].y;
             const cplx vk = cmul(wc, {P + Qm, Q - Pm});
             buf[k * L + ln] = cconj(vk);                               // conjugated: inverse by forward passes
@@ -544,9 +550,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
             const cplx vm = buf[(k == 0 ? 0 : N - k) * L + ln];
             const cplx a = {0.5 * (vk.re + vm.re), 0.5 * (vk.im - vm.im)};
             const cplx b = {0.5 * (vk.im + vm.im), -0.5 * (vk.re - vm.re)};
-            double sn, cs;
-            sincospi((double)k / (2 * N), &sn, &cs);
-            const cplx w = {cs, -sn};
+            const cplx w = w4(k);
             const cplx wa = cmul(w, a), wb = cmul(w, b);
             __builtin_nontemporal_store(v2d{wa.re, wb.re}, x + k);
             if (k > 0 && N - k != k) __builtin_nontemporal_store(v2d{-wa.im, -wb.im}, x + (N - k));
@@ -647,7 +651,7 @@ static hipError_t launch_dct_t(const DctArgs &A, bool inverse, hipStream_t s)
 {
     const int64_t blocks = (A.rows + L - 1) / L;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t lds = sizeof(cplx) * ((size_t)A.S.M * L + 64 + (A.S.M + 63) / 64);
+    const size_t lds = sizeof(cplx) * ((size_t)A.S.M * L + 64 + (A.S.M + 63) / 64 + 4);
     if (inverse)
         hipLaunchKernelGGL((k_dct_x<L, NMAX, true>), dim3((unsigned)blocks), dim3(kFftThreads), lds, s, A);
     else
