@@ -497,6 +497,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
             sincospi((double)(t - 64 - nhi) / (2 * N), &sn, &cs);
         lo[t] = {cs, -sn};   // hi and q4 follow lo contiguously
     }
+    __syncthreads();         // the tables are read before the transform (inverse)
     // exp(-i pi k/(2N)) = W_{4N}^k = W_N^{k/4} W_{4N}^{k mod 4}
     const TwSplit twn{lo, hi};
     auto w4 = [&](int k) { return cmul(twn(k >> 2), q4[k & 3]); };
