@@ -122,6 +122,63 @@ __device__ inline void dft<8>(cplx *v)
     v[7] = csub(e[3], o3);
 }
 
+// Radix 16 = 4 x 4 and radix 9 = 3 x 3 in registers: X[k1 + R1 k2] =
+// DFT_R2 over b of W_R^{b k1} DFT_R1(v_b, v_{b+R2}, ...)[k1].
+template <>
+__device__ inline void dft<16>(cplx *v)
+{
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;   // cos, sin(pi/8)
+    constexpr double h = 0.70710678118654752440;
+    const cplx tw[3][3] = {{{c1, -s1}, {h, -h}, {s1, -c1}},      // W_16^{b k1}, b = 1..3, k1 = 1..3
+                           {{h, -h}, {0.0, -1.0}, {-h, -h}},
+                           {{s1, -c1}, {-h, -h}, {-c1, s1}}};
+    cplx y[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) y[b][a] = v[b + 4 * a];
+        dft<4>(y[b]);
+    }
+#pragma unroll
+    for (int b = 1; b < 4; ++b)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) y[b][k1] = cmul(y[b][k1], tw[b - 1][k1 - 1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx z[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        dft<4>(z);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = z[k2];
+    }
+}
+
+template <>
+__device__ inline void dft<9>(cplx *v)
+{
+    constexpr double c1 = 0.76604444311897803520, s1 = 0.64278760968653932632;   // cos, sin(2 pi/9)
+    constexpr double c2 = 0.17364817766693034885, s2 = 0.98480775301220805936;   // 4 pi/9
+    constexpr double c4 = -0.93969262078590838405, s4 = 0.34202014332566873304;  // 8 pi/9
+    const cplx tw[2][2] = {{{c1, -s1}, {c2, -s2}}, {{c2, -s2}, {c4, -s4}}};      // W_9^{b k1}
+    cplx y[3][3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) y[b][a] = v[b + 3 * a];
+        dft<3>(y[b]);
+    }
+#pragma unroll
+    for (int b = 1; b < 3; ++b)
+#pragma unroll
+        for (int k1 = 1; k1 < 3; ++k1) y[b][k1] = cmul(y[b][k1], tw[b - 1][k1 - 1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        cplx z[3] = {y[0][k1], y[1][k1], y[2][k1]};
+        dft<3>(z);
+#pragma unroll
+        for (int k2 = 0; k2 < 3; ++k2) v[k1 + 3 * k2] = z[k2];
+    }
+}
+
 constexpr int kFftThreads = 256;
 
 // Twiddle W_M^q from a full table (M entries) or from two short ones
@@ -183,17 +240,26 @@ __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, 
     __syncthreads();
 }
 
-// R8: radix-8 passes are compiled in (only where the plan uses them: their
-// registers would otherwise lower the occupancy of every transform kernel).
-template <int L, int MMAX, bool R8, class TW>
+constexpr int kRadix8 = 1, kRadix16 = 2;
+
+// RSET: which long radices are compiled in (kRadix8, kRadix16 for 16 and 9),
+// only where the plan uses them: their registers would otherwise lower the
+// occupancy of every transform kernel.
+template <int L, int MMAX, int RSET, class TW>
 __device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, int ln, int tr)
 {
     constexpr int T = kFftThreads / L;
     int Ns = 1;
     for (int s = 0; s < S.npass; ++s) {
         switch (S.radix[s]) {
+        case 16:
+            if constexpr ((RSET & kRadix16) != 0) fft_pass<16, (MMAX / 16 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            break;
+        case 9:
+            if constexpr ((RSET & kRadix16) != 0) fft_pass<9, (MMAX / 9 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            break;
         case 8:
-            if constexpr (R8) fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            if constexpr ((RSET & kRadix8) != 0) fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
             break;
         case 4: fft_pass<4, (MMAX / 4 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         case 2: fft_pass<2, (MMAX / 2 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
@@ -231,7 +297,7 @@ struct FftTile {
 
 // Forward: x rows (DIV = 0), or the divergence of (v, w) (DIV = 1) or of
 // (u, v, w) (DIV = 2) -> spectrum rows.
-template <int L, int MMAX, int DIV>
+template <int L, int MMAX, int DIV, int RSET>
 __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
 {
     using TL = FftTile<L, MMAX>;
@@ -312,7 +378,7 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX, false>(buf, TwFull{twM}, A.S, ln, tr);
+    fft_lines<L, MMAX, RSET>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     v2d *out = reinterpret_cast<v2d *>(A.xhat);
@@ -333,7 +399,7 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
 // gradient of x (the pseudo-pressure): w_k -= (x_k - x_{k-1})/dz, periodic.
 // The w rows are loaded before the transform, so that they arrive while it
 // runs.
-template <int L, int MMAX, bool CORR>
+template <int L, int MMAX, bool CORR, int RSET>
 __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
 {
     using TL = FftTile<L, MMAX>;
@@ -395,7 +461,7 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, MMAX, false>(buf, TwFull{twM}, A.S, ln, tr);
+    fft_lines<L, MMAX, RSET>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
     const double inv_m = 1.0 / M;
@@ -542,7 +608,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
     }
     __syncthreads();
 
-    fft_lines<L, NMAX, true>(buf, TwSplit{lo, hi}, A.S, ln, tr);
+    fft_lines<L, NMAX, kRadix8 | kRadix16>(buf, TwSplit{lo, hi}, A.S, ln, tr);
 
     if (!act) return;
     if (!INV) {
@@ -576,20 +642,27 @@ size_t fft_lds_bytes_t(int M)
 
 }  // namespace
 
-bool fft_shape(int64_t Nz, FftShape &S)
+// Passes of an M-point transform: the radices of `order`, each taken as
+// often as it divides what is left (false if M has other prime factors).
+static bool make_plan(int M, const int *order, int norder, FftShape &S)
 {
-    if (Nz < 2 || (Nz & 1) || Nz / 2 > kFftMaxM) return false;
     S = FftShape{};
-    S.M = (int)(Nz / 2);
-    int m = S.M;
-    const int order[4] = {4, 2, 3, 5};
-    for (int f : order)
-        while (m % f == 0) {
+    S.M = M;
+    int m = M;
+    for (int i = 0; i < norder; ++i)
+        while (m % order[i] == 0) {
             if (S.npass == kFftMaxPasses) return false;
-            S.radix[S.npass++] = f;
-            m /= f;
+            S.radix[S.npass++] = order[i];
+            m /= order[i];
         }
     return m == 1;
+}
+
+bool fft_shape(int64_t Nz, FftShape &S)
+{
+    static const int order[4] = {4, 2, 3, 5};
+    if (Nz < 2 || (Nz & 1) || Nz / 2 > kFftMaxM) return false;
+    return make_plan((int)(Nz / 2), order, 4, S);
 }
 
 // Lines per workgroup (measured on MI355X at Nz = 288): 16 for the
@@ -605,6 +678,8 @@ static int fft_lines_per_group(int M, int kind)
     return kind == kFftInverseCorrect ? fit : std::min(fit, 16);
 }
 
+// The spanwise transforms use radices 4, 2, 3, 5 (the plan of fft_shape):
+// two passes of 16 and 9 at M = 144 measured no faster than four of 4, 4, 3, 3.
 template <int L, int MMAX>
 static hipError_t launch_fft_t(const FftArgs &A, int kind, hipStream_t s)
 {
@@ -612,11 +687,11 @@ static hipError_t launch_fft_t(const FftArgs &A, int kind, hipStream_t s)
     const size_t lds = fft_lds_bytes_t<L, MMAX>(A.S.M);
     const dim3 grid((unsigned)blocks), block(kFftThreads);
     switch (kind) {
-    case kFftForward: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 0>), grid, block, lds, s, A); break;
-    case kFftDivergence: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 1>), grid, block, lds, s, A); break;
-    case kFftDivergence3: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 2>), grid, block, lds, s, A); break;
-    case kFftInverse: hipLaunchKernelGGL((k_irfft_z<L, MMAX, false>), grid, block, lds, s, A); break;
-    default: hipLaunchKernelGGL((k_irfft_z<L, MMAX, true>), grid, block, lds, s, A); break;
+    case kFftForward: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 0, 0>), grid, block, lds, s, A); break;
+    case kFftDivergence: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 1, 0>), grid, block, lds, s, A); break;
+    case kFftDivergence3: hipLaunchKernelGGL((k_rfft_z<L, MMAX, 2, 0>), grid, block, lds, s, A); break;
+    case kFftInverse: hipLaunchKernelGGL((k_irfft_z<L, MMAX, false, 0>), grid, block, lds, s, A); break;
+    default: hipLaunchKernelGGL((k_irfft_z<L, MMAX, true, 0>), grid, block, lds, s, A); break;
     }
     return hipGetLastError();
 }
@@ -633,18 +708,9 @@ hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s)
 
 bool dct_shape(int64_t N, FftShape &S)
 {
+    static const int order[7] = {16, 8, 4, 2, 9, 3, 5};    // 2048 = 16 * 16 * 8: three passes
     if (N < 2 || (N & 1) || N > kDctMaxN) return false;
-    S = FftShape{};
-    S.M = (int)N;
-    int m = S.M;
-    const int order[5] = {8, 4, 2, 3, 5};   // fewest passes over LDS
-    for (int f : order)
-        while (m % f == 0) {
-            if (S.npass == kFftMaxPasses) return false;
-            S.radix[S.npass++] = f;
-            m /= f;
-        }
-    return m == 1;
+    return make_plan((int)N, order, 7, S);
 }
 
 template <int L, int NMAX>
@@ -666,8 +732,9 @@ hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s)
     const char *e = getenv("TRI_DCT_ROWS");
     const int want = e ? atoi(e) : 0;
     if (A.S.M <= 512 && (want == 0 || want == 8)) return launch_dct_t<8, 512>(A, inverse, s);
-    // two rows per workgroup (measured on MI355X at N = 2048: 0.66 ms against
-    // 0.78 ms with one row); TRI_DCT_ROWS=1 selects one row
+    // two rows per workgroup (measured on MI355X at N = 2048 and 145 x 256
+    // rows: 0.57-0.60 ms against 0.59-0.61 ms with one row); TRI_DCT_ROWS=1
+    // selects one row
     if (A.S.M <= 2048 && want == 1) return launch_dct_t<1, 2048>(A, inverse, s);
     if (A.S.M <= 2048) return launch_dct_t<2, 2048>(A, inverse, s);
     return launch_dct_t<1, kDctMaxN>(A, inverse, s);
