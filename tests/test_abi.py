@@ -56,3 +56,16 @@ def test_null_context_and_status_strings(T):
     assert T.tri_status_string(99) == "unknown status"
     assert L.tri_plan_item_partitions(None, 0) == -1
     assert L.tri_stream_copy(None, None, None, 0) == T.TRI_E_ARG
+    # the pressure-step entry points refuse a null context before anything else
+    assert L.spanwise_rfft(None, None, None, 4, 8) == T.TRI_E_ARG
+    assert L.spanwise_irfft(None, None, None, 4, 8) == T.TRI_E_ARG
+    assert L.streamwise_dct(None, None, 8, 1) == T.TRI_E_ARG
+    assert L.streamwise_idct(None, None, 8, 1) == T.TRI_E_ARG
+    assert L.projection_divergence_rfft(None, None, None, None, 1.0, None, 4, 4, 8) == T.TRI_E_ARG
+    assert L.projection_correct(None, None, None, None, None, None, 1.0, 4, 4, 8) == T.TRI_E_ARG
+    assert L.projection_step(None, None, None, None, 1.0, None, None, None, None, None, 4, 4, 8, 1) == T.TRI_E_ARG
+    assert L.projection3d_divergence_rfft(None, None, None, None, 1.0, None, 1.0, None, 4, 4, 8) == T.TRI_E_ARG
+    assert L.projection3d_correct(None, None, None, None, None, None, 1.0, None, 1.0, 4, 4, 8) == T.TRI_E_ARG
+    assert L.projection3d_step(None, None, None, None, 1.0, None, 1.0, None, None, None, None, None, None,
+                               4, 4, 8, 1) == T.TRI_E_ARG
+    assert L.poisson_shifted_solve(None, None, 4, 4, 4, None, None, None, None, 1, T.TRI_PPT) == T.TRI_E_ARG
