@@ -58,7 +58,7 @@ typedef enum {
     TRI_E_ARG = 1,           /* null pointer, bad enum, negative size            */
     TRI_E_SHAPE = 2,         /* n % P != 0, m < 2, P out of range, n < 3 periodic */
     TRI_E_ZERO_PIVOT = 3,    /* a partition block hit a zero pivot (device)      */
-    TRI_E_PDD_UNSAFE = 4,    /* reserved: strict PDD truncation check            */
+    TRI_E_PDD_UNSAFE = 4,    /* strict PDD: a dropped entry above the tolerance  */
     TRI_E_NOT_CONVERGED = 5, /* FP32 + FP64 refinement did not converge (device) */
     TRI_E_HIP = 6,           /* a HIP runtime call failed                        */
     TRI_E_NOMEM = 7,         /* device or host allocation failed                 */
@@ -112,8 +112,20 @@ tri_status tri_create(tri_ctx *out, int device, void *hip_stream);
 tri_status tri_destroy(tri_ctx ctx);
 /* Change the stream later calls queue on. */
 tri_status tri_set_stream(tri_ctx ctx, void *hip_stream);
+/* Strict PDD (Sec. 3.2 holds PDD accurate only where the entries it drops
+ * from Z are negligible): with tol > 0, every later PDD solve of this
+ * context -- one-shot calls, poisson_shifted_solve with TRI_PDD, and plans
+ * created afterwards -- whose dropped reduced-system entries (v at a
+ * partition's last row, w at its first) exceed tol sets the status word,
+ * and tri_sync_status returns TRI_E_PDD_UNSAFE (the solve itself still
+ * runs; nothing synchronises).  TRI_F32_REFINE solves are not checked:
+ * their refinement converges to A^-1 d, not to the truncated system.
+ * tol = 0 (the default) turns the check off; the largest dropped entry of
+ * a shared-matrix call is reported in tri_info.pdd_drop_max either way.
+ * TRI_E_ARG for a negative or NaN tol. */
+tri_status tri_set_pdd_tolerance(tri_ctx ctx, double tol);
 /* Wait for the stream, read and clear the sticky device status word:
- * TRI_OK, TRI_E_ZERO_PIVOT or TRI_E_NOT_CONVERGED. */
+ * TRI_OK, TRI_E_ZERO_PIVOT, TRI_E_NOT_CONVERGED or TRI_E_PDD_UNSAFE. */
 tri_status tri_sync_status(tri_ctx ctx);
 /* Static English text for a status code. */
 const char *tri_status_string(int status);

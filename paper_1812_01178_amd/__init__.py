@@ -19,7 +19,7 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime libtri binds to)
 
 __all__ = [
-    "TriError", "lib", "tri_create", "tri_destroy", "tri_set_stream", "tri_sync_status",
+    "TriError", "lib", "tri_create", "tri_destroy", "tri_set_stream", "tri_set_pdd_tolerance", "tri_sync_status",
     "tri_status_string", "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep",
     "poisson_wavenumber_solve", "tri_plan_create", "tri_plan_execute", "tri_plan_capture",
     "tri_plan_graph_launch", "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy",
@@ -45,7 +45,7 @@ TRI_MAX_PARTITIONS = 16
 
 # every symbol include/tri.h declares
 EXPORTED = [
-    "tri_create", "tri_destroy", "tri_set_stream", "tri_sync_status", "tri_status_string",
+    "tri_create", "tri_destroy", "tri_set_stream", "tri_set_pdd_tolerance", "tri_sync_status", "tri_status_string",
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
@@ -105,6 +105,7 @@ def lib():
         "tri_create": (_I, [ctypes.POINTER(_V), _I, _V]),
         "tri_destroy": (_I, [_V]),
         "tri_set_stream": (_I, [_V, _V]),
+        "tri_set_pdd_tolerance": (_I, [_V, ctypes.c_double]),
         "tri_sync_status": (_I, [_V]),
         "tri_status_string": (ctypes.c_char_p, [_I]),
         "tri_last_error": (ctypes.c_char_p, [_V]),
@@ -195,6 +196,12 @@ def tri_destroy(ctx) -> None:
 
 def tri_set_stream(ctx, stream: int | None) -> None:
     _check(lib().tri_set_stream(ctx, stream), "tri_set_stream", ctx)
+
+
+def tri_set_pdd_tolerance(ctx, tol: float) -> None:
+    """Strict PDD: later PDD solves whose dropped entries exceed tol (> 0) make
+    tri_sync_status raise TRI_E_PDD_UNSAFE; 0 turns the check off."""
+    _check(lib().tri_set_pdd_tolerance(ctx, float(tol)), "tri_set_pdd_tolerance", ctx)
 
 
 def tri_sync_status(ctx) -> int:

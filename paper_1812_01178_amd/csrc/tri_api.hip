@@ -27,6 +27,7 @@ struct tri_ctx_s {
     unsigned long long *resid_dev = nullptr;
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    double pdd_tol = 0.0;                 // strict PDD: > 0 reports dropped entries above it
     std::string last_error;
 };
 
@@ -567,6 +568,7 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
         g.cs_b0 = pb.cs_b0;
         g.cs_b1 = pb.cs_b1;
         g.status = ctx->status_dev;
+        g.pdd_tol = ctx->pdd_tol;
         if (prec == TRI_F32_REFINE) {
             if (m > kGeneralRefineMaxM || pb.P > 8)
                 return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE with per-line coefficients needs m <= %d, P <= 8",
@@ -583,6 +585,7 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
     tri_status st = ensure_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
     if (st) return st;
     Tables T = carve_tables(ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+    T.pdd_tol = prec == TRI_F32_REFINE ? 0.0 : ctx->pdd_tol;   // refinement reaches A^-1 d
     std::vector<Launch> ls;
     st = build_launches(ctx, pb, T, prec, ls);
     if (st) return st;
@@ -756,6 +759,14 @@ tri_status tri_stream_copy(tri_ctx ctx, double *dst, const double *src, int64_t 
     return TRI_OK;
 }
 
+tri_status tri_set_pdd_tolerance(tri_ctx ctx, double tol)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (!(tol >= 0.0)) return fail(ctx, TRI_E_ARG, "tri_set_pdd_tolerance: tolerance %g must be >= 0", tol);
+    ctx->pdd_tol = tol;
+    return TRI_OK;
+}
+
 tri_status tri_set_stream(tri_ctx ctx, void *hip_stream)
 {
     if (!ctx) return TRI_E_ARG;
@@ -773,6 +784,8 @@ tri_status tri_sync_status(tri_ctx ctx)
     HIP_TRY(ctx, hipMemset(ctx->status_dev, 0, sizeof(int)));
     if (h & kStatusZeroPivot) return fail(ctx, TRI_E_ZERO_PIVOT, "zero pivot reported by a kernel");
     if (h & kStatusNotConverged) return fail(ctx, TRI_E_NOT_CONVERGED, "refinement did not converge");
+    if (h & kStatusPddUnsafe)
+        return fail(ctx, TRI_E_PDD_UNSAFE, "a PDD dropped entry exceeds the tolerance %.3g", ctx->pdd_tol);
     return TRI_OK;
 }
 
@@ -855,6 +868,7 @@ tri_status poisson_shifted_solve(tri_ctx ctx, double *phihat, int64_t Nx, int64_
     g.cs_b0 = 0;
     g.cs_b1 = 0;
     g.status = ctx->status_dev;
+    g.pdd_tol = ctx->pdd_tol;
     g.lamz = lamz;
     g.lamx = lamx;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -1578,6 +1592,7 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
             return fail(ctx, TRI_E_NOMEM, "plan tables of %zu bytes", bytes);
         }
         pi.T = carve_tables(pi.mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+        pi.T.pdd_tol = prec == TRI_F32_REFINE ? 0.0 : ctx->pdd_tol;   // refinement reaches A^-1 d
         st = item_launches(ctx, pb, pi.T, prec, pi.launches);
         if (st) {
             tri_plan_destroy(plan);

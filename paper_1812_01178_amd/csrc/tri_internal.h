@@ -57,6 +57,7 @@ struct Tables {
     int P = 0;
     int periodic = 0;
     int method = 0;
+    double pdd_tol = 0.0;    // > 0: PDD tables with a dropped entry above it set kStatusPddUnsafe
 };
 
 inline size_t tables_bytes_F(int64_t G, int64_t n) { return sizeof(double) * (size_t)(G * kNumFactors * n); }
@@ -143,6 +144,7 @@ struct GeneralArgs {
     // sigma = lamz[b1] + lamx[b0 >> cplx] per line; a line with sigma == 0 is
     // gauge pinned (row 0 replaced by x_0 = 0).
     const double *lamz = nullptr, *lamx = nullptr;
+    double pdd_tol = 0.0;    // > 0: PDD lines with a dropped entry above it set kStatusPddUnsafe
 };
 
 // Host launchers (tri_kernels.hip).  All return hipError_t of the launch.
@@ -243,5 +245,6 @@ constexpr int kGeneralPPTMaxP = 8;
 // Status word bits (device).
 constexpr int kStatusZeroPivot = 1;
 constexpr int kStatusNotConverged = 2;
+constexpr int kStatusPddUnsafe = 4;       // a PDD dropped entry above the context's tolerance
 
 }  // namespace tri

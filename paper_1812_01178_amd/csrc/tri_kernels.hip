@@ -148,6 +148,7 @@ __global__ __launch_bounds__(64) void k_factor(MatSrc S, Tables T, int *status)
             if (R <= P - 2 || periodic) dmax = fmax(dmax, fabs(wfirst(R)));
         }
         T.drop[g] = dmax;
+        if (T.method == TRI_PDD && T.pdd_tol > 0.0 && dmax > T.pdd_tol) atomicOr(status, kStatusPddUnsafe);
     }
 
     if (T.method == TRI_PDD) {
@@ -1224,6 +1225,12 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 
     double yl = 0.0, yr = 0.0;
     const bool has_l = (r > 0) || periodic, has_r = (r < P - 1) || periodic;
+    if (METHOD == TRI_PDD && A.pdd_tol > 0.0 && active) {
+        // the entries PDD drops that this partition holds: v at its last row
+        // (left side of the next interface), w at its first row (right side)
+        const double d = fmax(has_l && has_r ? fabs(vm) : 0.0, has_l && has_r ? fabs(w0) : 0.0);
+        if (d > A.pdd_tol) atomicOr(A.status, kStatusPddUnsafe);
+    }
     if (METHOD == TRI_PDD) {
         if (has_l) {
             const int L = (r > 0) ? r - 1 : P - 1;

@@ -7,6 +7,8 @@ bitwise equality for the exactly representable indexing probes.
 Sizes span several workgroups and end in ragged tails; full BASELINE shapes
 are covered by sampled lines in test_gpu_fullsize.py.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -332,6 +334,89 @@ def test_pdd_drop_reported(T, ctx):
     assert info["pdd_drop_max"] < 1e-14
     info = T.adi_sweep(ctx, 1, du, dev(a), dev(b), dev(c), 16, method=0, info=True)
     assert info["pdd_drop_max"] > 1e-8
+
+
+def _pdd_dropped_max(A, B, C, P, periodic):
+    """Largest entry PDD drops, from the exact partition spikes: per partition, the
+    left spike at its last row and the right spike at its first row, where both
+    interfaces exist."""
+    nlines, n = B.shape
+    m = n // P
+    worst = 0.0
+    for s in range(nlines):
+        for r in range(P):
+            if not periodic and (r == 0 or r == P - 1):
+                continue
+            lo = r * m
+            blk = np.diag(B[s, lo:lo + m]) + np.diag(A[s, lo + 1:lo + m], -1) + np.diag(C[s, lo:lo + m - 1], 1)
+            e1 = np.zeros(m); e1[0] = A[s, lo]
+            em = np.zeros(m); em[-1] = C[s, lo + m - 1]
+            worst = max(worst, abs(np.linalg.solve(blk, e1)[-1]), abs(np.linalg.solve(blk, em)[0]))
+    return worst
+
+
+def test_strict_pdd_shared_matrix(T, ctx):
+    """tri_set_pdd_tolerance: with a tolerance set, a shared-matrix PDD solve whose
+    dropped entries exceed it makes tri_sync_status report TRI_E_PDD_UNSAFE; one
+    whose dropped entries stay below it does not; tolerance 0 turns the check off."""
+    Nz, Ny, Nx = 4, 256, 64
+    a, b, c = (dev(v) for v in W.momentum_stretched(Ny))
+    du = dev(W.cfg_field(Nx, Ny, Nz))
+    T.tri_sync_status(ctx)
+    try:
+        T.tri_set_pdd_tolerance(ctx, 1e-12)
+        T.adi_sweep(ctx, 1, du, a, b, c, 4, method=T.TRI_PDD)          # drops < 1e-14
+        T.tri_sync_status(ctx)
+        T.adi_sweep(ctx, 1, du, a, b, c, 16, method=T.TRI_PDD)         # drops > 1e-8
+        with pytest.raises(T.TriError) as e:
+            T.tri_sync_status(ctx)
+        assert e.value.status == T.TRI_E_PDD_UNSAFE
+        T.tri_sync_status(ctx)                                          # cleared once reported
+        T.adi_sweep(ctx, 1, du, a, b, c, 16, method=T.TRI_PPT)         # PPT drops nothing
+        T.tri_sync_status(ctx)
+        T.tri_set_pdd_tolerance(ctx, 0.0)
+        T.adi_sweep(ctx, 1, du, a, b, c, 16, method=T.TRI_PDD)
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_set_pdd_tolerance(ctx, 0.0)
+    L = T.lib()
+    assert L.tri_set_pdd_tolerance(ctx, ctypes.c_double(-1.0)) == T.TRI_E_ARG
+    assert L.tri_set_pdd_tolerance(ctx, ctypes.c_double(float("nan"))) == T.TRI_E_ARG
+
+
+@pytest.mark.parametrize("periodic", [False, True])
+def test_strict_pdd_per_line_coefficients(T, ctx, orc, periodic):
+    """The same check in the per-line kernel: strongly dominant lines in long
+    partitions stay below the tolerance (and match the oracle's PDD); weakly
+    dominant lines in short partitions exceed it."""
+    nlines, n, tol = 100, 128, 1e-12
+    rng = np.random.default_rng(77 + periodic)
+    cases = ((4, 3.0, False), (16, 0.02, True))        # (P, margin, expect the report)
+    try:
+        T.tri_set_pdd_tolerance(ctx, tol)
+        for P, margin, unsafe in cases:
+            A = np.empty((nlines, n)); B = np.empty((nlines, n)); C = np.empty((nlines, n))
+            for s in range(nlines):
+                A[s], B[s], C[s] = W.random_tridiag(n, rng, periodic=periodic, margin=margin)
+            assert (_pdd_dropped_max(A, B, C, P, periodic) > tol) == unsafe   # the fixture's side
+            D = rng.uniform(-1, 1, (n, nlines))
+            At, Bt, Ct = (np.ascontiguousarray(X.T) for X in (A, B, C))
+            dd = dev(D)
+            T.tri_pdd_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0),
+                            coef_strides=(nlines, 1, 0), P=P, periodic=periodic)
+            if unsafe:
+                with pytest.raises(T.TriError) as e:
+                    T.tri_sync_status(ctx)
+                assert e.value.status == T.TRI_E_PDD_UNSAFE
+            else:
+                T.tri_sync_status(ctx)
+                ref = D.copy().ravel()
+                orc.solve_batch(orc.PDD, ref, n, nlines, 1, s_j=nlines, s_b0=1, s_b1=0, a=At.ravel(),
+                                b=Bt.ravel(), c=Ct.ravel(), cs_j=nlines, cs_b0=1, cs_b1=0, P=P,
+                                periodic=periodic)
+                assert line_relerr(host(dd), ref.reshape(n, nlines), axis=0) <= TOL
+    finally:
+        T.tri_set_pdd_tolerance(ctx, 0.0)
 
 
 # ---------------------------------------------------------------------------

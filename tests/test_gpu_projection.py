@@ -237,6 +237,30 @@ def test_shifted_poisson_matches_oracle(T, ctx, orc, nk, ny, nx, P, method):
     assert np.all(got[0, 0, 0] == 0)
 
 
+
+def test_shifted_poisson_strict_pdd(T, ctx):
+    """With a PDD tolerance set, the shifted solves report TRI_E_PDD_UNSAFE when
+    PDD drops O(1) entries (the low modes at 8 rows per partition) and stay
+    silent under PPT, which drops nothing."""
+    nk, ny, nx, P = 7, 64, 20, 8
+    ay, cy = W.poisson_metric(ny)
+    args = (dev(ay), dev(cy), dev(W.modified_wavenumbers(2 * (nk - 1))), dev(lam_x(nx)))
+    rng = np.random.default_rng(5)
+    ph = rng.standard_normal((nk, ny, nx)) + 1j * rng.standard_normal((nk, ny, nx))
+    T.tri_sync_status(ctx)
+    try:
+        T.tri_set_pdd_tolerance(ctx, 1e-12)
+        T.poisson_shifted_solve(ctx, dev(ph, torch.complex128), *args, P=P, method=T.TRI_PPT)
+        T.tri_sync_status(ctx)
+        T.poisson_shifted_solve(ctx, dev(ph, torch.complex128), *args, P=P, method=T.TRI_PDD)
+        with pytest.raises(T.TriError) as e:
+            T.tri_sync_status(ctx)
+        assert e.value.status == T.TRI_E_PDD_UNSAFE
+    finally:
+        T.tri_set_pdd_tolerance(ctx, 0.0)
+    T.poisson_shifted_solve(ctx, dev(ph, torch.complex128), *args, P=P, method=T.TRI_PDD)
+    T.tri_sync_status(ctx)
+
 def test_shifted_poisson_refusals(T, ctx):
     L = T.lib()
     ph = torch.zeros((3, 256, 4), dtype=torch.complex128, device="cuda")
