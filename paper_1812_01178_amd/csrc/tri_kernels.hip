@@ -1242,6 +1242,77 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
             const double det = 1.0 - wm * S(2, R);
             yr = (S(0, R) - S(2, R) * xl) / det;
         }
+    } else if constexpr (SHIFT && MAXT == 512) {
+        // Shifted rows are diagonally dominant and never periodic, so the
+        // reduced system needs no pivoting: it is solved by block cyclic
+        // reduction over the P partitions, all wavefronts at once.  Partition
+        // r's unknowns X_r = (x at its first row, x at its last row) satisfy
+        //   X_r + L_r X_{r-1} + U_r X_{r+1} = (x~ first, x~ last),
+        // L_r = [[0, v_1], [0, v_m]] on the left neighbour's last row and
+        // U_r = [[w_1, 0], [w_m, 0]] on the right neighbour's first row (the
+        // same equations as the rows of Z in Eq. (7), grouped by partition).
+        // A step at distance h eliminates X_{r-h} and X_{r+h} with rows r-h and
+        // r+h and rescales the row to a unit diagonal block; after the steps
+        // h = 1, 2, 4, .. < P each row stands alone.  Dominance (|v| + |w| <= 1
+        // row by row) carries through the steps.  Rows cross between
+        // wavefronts through LDS (10 values a row, over the tips, which no
+        // one reads on this path).  The rows stay in LDS between steps, since
+        // the registers hold what the correction needs; a step reads this row
+        // and the neighbours' blocks as it uses them and writes the new row
+        // after a barrier.  (The 1024-lane instances, for P > 8, have no room
+        // for the step's temporaries and keep the band solve below.)
+        auto Q = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * 64 + lane]; };
+        bool ok = true;
+        Q(0, r) = 0.0; Q(1, r) = v0; Q(2, r) = 0.0; Q(3, r) = vm;      // L_r
+        Q(4, r) = w0; Q(5, r) = 0.0; Q(6, r) = wm; Q(7, r) = 0.0;      // U_r
+        Q(8, r) = xf; Q(9, r) = xl;                                    // right-hand side
+        for (int h = 1; h < P; h *= 2) {
+            __syncthreads();
+            double d00 = 1.0, d01 = 0.0, d10 = 0.0, d11 = 1.0;
+            double e0 = Q(8, r), e1 = Q(9, r);
+            double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;       // -L_r L_{r-h}
+            double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;       // -U_r U_{r+h}
+            if (r - h >= 0) {
+                const double l00 = Q(0, r), l01 = Q(1, r), l10 = Q(2, r), l11 = Q(3, r);
+                const int q = r - h;
+                const double t0 = Q(4, q), t1 = Q(5, q), t2 = Q(6, q), t3 = Q(7, q);
+                d00 -= l00 * t0 + l01 * t2; d01 -= l00 * t1 + l01 * t3;
+                d10 -= l10 * t0 + l11 * t2; d11 -= l10 * t1 + l11 * t3;
+                const double s0 = Q(8, q), s1 = Q(9, q);
+                e0 -= l00 * s0 + l01 * s1; e1 -= l10 * s0 + l11 * s1;
+                const double k0 = Q(0, q), k1 = Q(1, q), k2 = Q(2, q), k3 = Q(3, q);
+                n0 = -(l00 * k0 + l01 * k2); n1 = -(l00 * k1 + l01 * k3);
+                n2 = -(l10 * k0 + l11 * k2); n3 = -(l10 * k1 + l11 * k3);
+            }
+            if (r + h < P) {
+                const double u00 = Q(4, r), u01 = Q(5, r), u10 = Q(6, r), u11 = Q(7, r);
+                const int q = r + h;
+                const double t0 = Q(0, q), t1 = Q(1, q), t2 = Q(2, q), t3 = Q(3, q);
+                d00 -= u00 * t0 + u01 * t2; d01 -= u00 * t1 + u01 * t3;
+                d10 -= u10 * t0 + u11 * t2; d11 -= u10 * t1 + u11 * t3;
+                const double s0 = Q(8, q), s1 = Q(9, q);
+                e0 -= u00 * s0 + u01 * s1; e1 -= u10 * s0 + u11 * s1;
+                const double k0 = Q(4, q), k1 = Q(5, q), k2 = Q(6, q), k3 = Q(7, q);
+                m0 = -(u00 * k0 + u01 * k2); m1 = -(u00 * k1 + u01 * k3);
+                m2 = -(u10 * k0 + u11 * k2); m3 = -(u10 * k1 + u11 * k3);
+            }
+            const double det = d00 * d11 - d01 * d10;
+            if (det == 0.0) ok = false;
+            const double id = 1.0 / det;
+            const double i00 = d11 * id, i01 = -d01 * id, i10 = -d10 * id, i11 = d00 * id;
+            __syncthreads();                  // every partition has read step h's rows
+            Q(0, r) = i00 * n0 + i01 * n2; Q(1, r) = i00 * n1 + i01 * n3;
+            Q(2, r) = i10 * n0 + i11 * n2; Q(3, r) = i10 * n1 + i11 * n3;
+            Q(4, r) = i00 * m0 + i01 * m2; Q(5, r) = i00 * m1 + i01 * m3;
+            Q(6, r) = i10 * m0 + i11 * m2; Q(7, r) = i10 * m1 + i11 * m3;
+            Q(8, r) = i00 * e0 + i01 * e1; Q(9, r) = i10 * e0 + i11 * e1;
+        }
+        // X_r is now row r's right-hand side: y are the left neighbour's last
+        // row and the right neighbour's first row
+        __syncthreads();
+        if (has_l) yl = Q(9, r - 1);
+        if (has_r) yr = Q(8, r + 1);
+        if (!ok && active) atomicOr(A.status, kStatusZeroPivot);
     } else {
         // Zbar (Eq. (10)) of this lane's line: row 2i-1 = [v_m^(L), w_m^(L), 1],
         // row 2i = [1, v_1^(R), w_1^(R)] around the diagonal; cyclic if periodic.
@@ -1321,8 +1392,9 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
     }
 }
 
-size_t general_lds_bytes(int P, int periodic)
+size_t general_lds_bytes(int P, int periodic, bool shift)
 {
+    if (shift && P <= 8) return sizeof(double) * (size_t)10 * P * 64;   // block cyclic reduction rows
     const int K = periodic ? 0 : 2 * (P - 1);   // LDS band of the non-periodic reduced systems
     return sizeof(double) * ((size_t)6 * P + 5 * K) * 64;
 }
@@ -1331,7 +1403,7 @@ template <int CMAX, int METHOD>
 static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
-    const size_t lds = general_lds_bytes(a.P, METHOD == TRI_PPT ? a.periodic : 1);
+    const size_t lds = general_lds_bytes(a.P, METHOD == TRI_PPT ? a.periodic : 1, METHOD == TRI_PPT && a.lamz);
     // P > 8 partitions need 1024-lane workgroups (at most 128 VGPRs a lane);
     // fewer run with the 512-lane bound and twice the registers
     // (more than 16 rows per partition come with at most 8 partitions)
