@@ -1120,7 +1120,17 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
                 const double ccv = (t == m - 1) ? 0.0 : row_c(t);
                 const double den = row_b(t) - aa * cpp;
                 bad |= !(den != 0.0);
-                const double beta = 1.0 / den;
+                // the shifted rows' pivots are far from the range ends: the
+                // reciprocal estimate and two Newton steps (each r += r(1 - den r)
+                // doubles the correct bits) replace the longer IEEE division
+                double beta;
+                if constexpr (SHIFT) {
+                    beta = __builtin_amdgcn_rcp(den);
+                    beta = fma(beta, fma(-den, beta, 1.0), beta);
+                    beta = fma(beta, fma(-den, beta, 1.0), beta);
+                } else {
+                    beta = 1.0 / den;
+                }
                 gx = (x[t] - aa * gx) * beta;
                 x[t] = gx;
                 gvp = (t == 0) ? a_first * beta : -(aa * beta) * gvp;
