@@ -847,7 +847,7 @@ tri_status poisson_shifted_solve(tri_ctx ctx, double *phihat, int64_t Nx, int64_
         return fail(ctx, TRI_E_UNSUPPORTED, "shifted Poisson systems with m = %d > %d rows per partition", m,
                     kGeneralMaxM);
     if (m > 16 && P > 8) return fail(ctx, TRI_E_UNSUPPORTED, "shifted Poisson systems with m = %d > 16 need P <= 8", m);
-    if ((2 * Nx + 63) / 64 * Nk > 0x7fffffffLL) return fail(ctx, TRI_E_UNSUPPORTED, "too many lines");
+    if ((2 * Nx + 31) / 32 * Nk > 0x7fffffffLL) return fail(ctx, TRI_E_UNSUPPORTED, "too many lines");
     GeneralArgs g{};
     g.d = phihat;
     g.n = Ny;

@@ -1054,13 +1054,18 @@ hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStr
 template <int CMAX, int METHOD, bool SHIFT, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 {
-    extern __shared__ double sh[];              // [6][P][64]
-    const int lane = threadIdx.x & 63;
-    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // LW lines a workgroup: 64 (a wavefront per partition), or 32 for the
+    // shifted systems with P <= 8 (half a wavefront per partition), whose
+    // blocks fill 250 VGPRs: two such workgroups share a CU, so one loads
+    // while the other computes
+    constexpr int LW = (SHIFT && MAXT == 512) ? 32 : 64;
+    extern __shared__ double sh[];              // [6][P][LW]
+    const int lane = threadIdx.x & (LW - 1);
+    const int r = LW == 64 ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x / LW);
     const int64_t blk = blockIdx.x;
     const int64_t grp = blk % A.ngroups0;
     const int64_t b1 = blk / A.ngroups0;
-    const int64_t b0raw = grp * 64 + lane;
+    const int64_t b0raw = grp * LW + lane;
     const bool active = b0raw < A.nb0;
     const int64_t b0 = active ? b0raw : 0;
     const int m = A.m, P = A.P, periodic = A.periodic;
@@ -1229,7 +1234,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
     xf = x1, v0 = v1, w0 = w1;
     }
 
-    auto S = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * 64 + lane]; };
+    auto S = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * LW + lane]; };
     S(0, r) = xf; S(1, r) = xl; S(2, r) = v0; S(3, r) = vm; S(4, r) = w0; S(5, r) = wm;
     __syncthreads();
 
@@ -1271,7 +1276,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
         // and the neighbours' blocks as it uses them and writes the new row
         // after a barrier.  (The 1024-lane instances, for P > 8, have no room
         // for the step's temporaries and keep the band solve below.)
-        auto Q = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * 64 + lane]; };
+        auto Q = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * LW + lane]; };
         bool ok = true;
         Q(0, r) = 0.0; Q(1, r) = v0; Q(2, r) = 0.0; Q(3, r) = vm;      // L_r
         Q(4, r) = w0; Q(5, r) = 0.0; Q(6, r) = wm; Q(7, r) = 0.0;      // U_r
@@ -1331,8 +1336,8 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
         if (SHIFT || !periodic) {             // (shifted systems are never periodic)
             // the band of every lane's Zbar in LDS (after the tips), solved by
             // wavefront 0 alone; the other partitions read their y after the barrier
-            double *Z = sh + (size_t)6 * P * 64;
-            auto B = [&](int q, int k) -> double & { return Z[((size_t)q * K + k) * 64 + lane]; };
+            double *Z = sh + (size_t)6 * P * LW;
+            auto B = [&](int q, int k) -> double & { return Z[((size_t)q * K + k) * LW + lane]; };
             if (r == 0 && K > 0) {
                 for (int i = 1; i <= NI; ++i) {
                     const int Li = i - 1, Ri = i;
@@ -1346,7 +1351,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
                     B(4, u1) = S(1, Li);                    // rhs
                     B(4, u2) = S(0, Ri);
                 }
-                ok = gtsv_pivot_strided(K, &B(0, 0), &B(1, 0), &B(2, 0), &B(3, 0), &B(4, 0), 64);
+                ok = gtsv_pivot_strided(K, &B(0, 0), &B(1, 0), &B(2, 0), &B(3, 0), &B(4, 0), LW);
             }
             __syncthreads();
             if (has_l) yl = B(4, 2 * r - 1);   // r >= 1 here (not periodic)
@@ -1404,7 +1409,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 
 size_t general_lds_bytes(int P, int periodic, bool shift)
 {
-    if (shift && P <= 8) return sizeof(double) * (size_t)10 * P * 64;   // block cyclic reduction rows
+    if (shift && P <= 8) return sizeof(double) * (size_t)10 * P * 32;   // block cyclic reduction rows
     const int K = periodic ? 0 : 2 * (P - 1);   // LDS band of the non-periodic reduced systems
     return sizeof(double) * ((size_t)6 * P + 5 * K) * 64;
 }
@@ -1427,10 +1432,16 @@ static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
         }
     }
     if (a.P > 8) return hipErrorInvalidValue;
-    if (a.lamz)
-        hipLaunchKernelGGL((k_general<CMAX, METHOD, true, 512>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
-    else
+    if (a.lamz) {
+        // 32 lines a workgroup (the kernel's LW for these instances)
+        GeneralArgs h = a;
+        h.ngroups0 = (a.nb0 + 31) / 32;
+        const size_t lds32 = METHOD == TRI_PPT ? lds : sizeof(double) * (size_t)6 * a.P * 32;
+        hipLaunchKernelGGL((k_general<CMAX, METHOD, true, 512>), dim3((unsigned)(h.ngroups0 * h.nb1)), dim3(32 * a.P),
+                           lds32, s, h);
+    } else {
         hipLaunchKernelGGL((k_general<CMAX, METHOD, false, 512>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+    }
     return hipGetLastError();
 }
 
