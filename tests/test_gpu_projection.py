@@ -219,7 +219,11 @@ def lam_x(nx):
 
 
 @pytest.mark.parametrize("nk,ny,nx,P,method", [(7, 64, 37, 4, "PPT"), (13, 256, 33, 8, "PPT"), (7, 64, 20, 8, "PDD"),
-                                               (5, 64, 70, 16, "PPT"), (4, 32, 5, 1, "PPT")])
+                                               (5, 64, 70, 16, "PPT"), (4, 32, 5, 1, "PPT"),
+                                               # partition counts that are not powers of two (the
+                                               # reduction's step count and end guards), odd tails
+                                               (3, 96, 41, 3, "PPT"), (5, 60, 19, 5, "PPT"), (4, 96, 23, 6, "PDD"),
+                                               (6, 112, 17, 7, "PPT"), (3, 64, 9, 2, "PPT")])
 def test_shifted_poisson_matches_oracle(T, ctx, orc, nk, ny, nx, P, method):
     """One matrix per (k, i) line, formed on the fly; the (0, 0) line is gauge pinned."""
     ay, cy = W.poisson_metric(ny)
