@@ -1055,9 +1055,9 @@ template <int CMAX, int METHOD, bool SHIFT, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 {
     // LW lines a workgroup: 64 (a wavefront per partition), or 32 for the
-    // shifted systems with P <= 8 (half a wavefront per partition), whose
-    // blocks fill 250 VGPRs: two such workgroups share a CU, so one loads
-    // while the other computes
+    // shifted systems (half a wavefront per partition), whose blocks fill up
+    // to 252 VGPRs: two such workgroups share a CU, so one loads while the
+    // other computes
     constexpr int LW = (SHIFT && MAXT == 512) ? 32 : 64;
     extern __shared__ double sh[];              // [6][P][LW]
     const int lane = threadIdx.x & (LW - 1);
@@ -1274,8 +1274,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
         // one reads on this path).  The rows stay in LDS between steps, since
         // the registers hold what the correction needs; a step reads this row
         // and the neighbours' blocks as it uses them and writes the new row
-        // after a barrier.  (The 1024-lane instances, for P > 8, have no room
-        // for the step's temporaries and keep the band solve below.)
+        // after a barrier.
         auto Q = [&](int q, int part) -> double & { return sh[((int64_t)q * P + part) * LW + lane]; };
         bool ok = true;
         Q(0, r) = 0.0; Q(1, r) = v0; Q(2, r) = 0.0; Q(3, r) = vm;      // L_r
@@ -1409,7 +1408,7 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
 
 size_t general_lds_bytes(int P, int periodic, bool shift)
 {
-    if (shift && P <= 8) return sizeof(double) * (size_t)10 * P * 32;   // block cyclic reduction rows
+    if (shift) return sizeof(double) * (size_t)10 * P * 32;   // block cyclic reduction rows
     const int K = periodic ? 0 : 2 * (P - 1);   // LDS band of the non-periodic reduced systems
     return sizeof(double) * ((size_t)6 * P + 5 * K) * 64;
 }
@@ -1419,19 +1418,17 @@ static hipError_t launch_general_t(const GeneralArgs &a, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
     const size_t lds = general_lds_bytes(a.P, METHOD == TRI_PPT ? a.periodic : 1, METHOD == TRI_PPT && a.lamz);
-    // P > 8 partitions need 1024-lane workgroups (at most 128 VGPRs a lane);
-    // fewer run with the 512-lane bound and twice the registers
-    // (more than 16 rows per partition come with at most 8 partitions)
+    // 64 lines and P > 8 partitions need 1024-lane workgroups (at most 128
+    // VGPRs a lane); fewer run with the 512-lane bound and twice the registers
+    // (more than 16 rows per partition come with at most 8 partitions).  The
+    // shifted systems run 32 lines a workgroup, so up to 16 partitions fit 512.
     if constexpr (CMAX <= 16) {
-        if (a.P > 8) {
-            if (a.lamz)
-                hipLaunchKernelGGL((k_general<CMAX, METHOD, true, 1024>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
-            else
-                hipLaunchKernelGGL((k_general<CMAX, METHOD, false, 1024>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
+        if (a.P > 8 && !a.lamz) {
+            hipLaunchKernelGGL((k_general<CMAX, METHOD, false, 1024>), dim3((unsigned)blocks), dim3(64 * a.P), lds, s, a);
             return hipGetLastError();
         }
     }
-    if (a.P > 8) return hipErrorInvalidValue;
+    if (a.P > (a.lamz ? 16 : 8)) return hipErrorInvalidValue;
     if (a.lamz) {
         // 32 lines a workgroup (the kernel's LW for these instances)
         GeneralArgs h = a;
