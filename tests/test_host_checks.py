@@ -95,3 +95,34 @@ def test_product_code_does_not_use_the_oracle():
     src = open(os.path.join(ROOT, "bench.py")).read().splitlines()
     uses = [i for i, ln in enumerate(src) if "import oracle" in ln or "from oracle" in ln]
     assert len(uses) == 1 and "cpu_baseline" in src[uses[0] + 1]
+
+
+def test_spikes_of_dominant_blocks_sum_to_at_most_one():
+    """The shifted Poisson solves eliminate the reduced system without pivoting
+    because, for a row-dominant block, the left and right spikes satisfy
+    |v_j| + |w_j| <= 1 at every row (maximum principle: they are the block's
+    response to unit boundary values).  Checked on random dominant blocks and on
+    the weakly dominant Neumann-metric rows with zero shift, whose bound is tight."""
+    rng = np.random.default_rng(12)
+
+    def spikes(a, b, c):
+        m = b.size
+        B = np.diag(b) + np.diag(a[1:], -1) + np.diag(c[:-1], 1)
+        e0 = np.zeros(m); e0[0] = a[0]
+        em = np.zeros(m); em[-1] = c[-1]
+        return np.linalg.solve(B, e0), np.linalg.solve(B, em)
+
+    for _ in range(200):
+        m = int(rng.integers(2, 33))
+        a, b, c = W.random_tridiag(m, rng, periodic=True, margin=float(rng.uniform(0.0, 2.0)))
+        v, w = spikes(a, b, c)
+        assert np.max(np.abs(v) + np.abs(w)) <= 1.0 + 1e-12
+    ay, cy = W.poisson_metric(256)
+    for sigma in (0.0, 1e-3, 39.5):
+        for lo, m in ((32, 32), (96, 16), (224, 32)):
+            sl = slice(lo, lo + m)
+            v, w = spikes(ay[sl], -(ay[sl] + cy[sl]) - sigma, cy[sl])
+            s = np.abs(v) + np.abs(w)
+            assert np.max(s) <= 1.0 + 1e-12
+            if sigma == 0.0 and lo + m < 256:
+                assert np.max(s) > 1.0 - 1e-9       # tight: constants solve the homogeneous rows
