@@ -118,8 +118,11 @@ tri_status tri_set_stream(tri_ctx ctx, void *hip_stream);
  * created afterwards -- whose dropped reduced-system entries (v at a
  * partition's last row, w at its first) exceed tol sets the status word,
  * and tri_sync_status returns TRI_E_PDD_UNSAFE (the solve itself still
- * runs; nothing synchronises).  TRI_F32_REFINE solves are not checked:
- * their refinement converges to A^-1 d, not to the truncated system.
+ * runs; nothing synchronises).  A plan's items (all shared-matrix) are
+ * checked once, when tri_plan_create computes their tables; the next
+ * tri_sync_status reports it.
+ * TRI_F32_REFINE solves are not checked: their refinement converges to
+ * A^-1 d, not to the truncated system.
  * tol = 0 (the default) turns the check off; the largest dropped entry of
  * a shared-matrix call is reported in tri_info.pdd_drop_max either way.
  * TRI_E_ARG for a negative or NaN tol. */
