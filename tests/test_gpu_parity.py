@@ -384,6 +384,35 @@ def test_strict_pdd_shared_matrix(T, ctx):
     assert L.tri_set_pdd_tolerance(ctx, ctypes.c_double(float("nan"))) == T.TRI_E_ARG
 
 
+
+def test_strict_pdd_plan_reports_at_creation(T, ctx, monkeypatch):
+    """A plan created under a tolerance checks its PDD items when it computes
+    their tables: a y item at P = 16 (dropped entries > 1e-8) is reported by the
+    next tri_sync_status, the same item at P = 4 is not, and executing the plan
+    reports nothing further."""
+    monkeypatch.setenv("TRI_AUTOTUNE", "0")
+    Nz, Ny, Nx = 4, 256, 64
+    a, b, c = (dev(v) for v in W.momentum_stretched(Ny))
+    u = dev(W.cfg_field(Nx, Ny, Nz))
+    item = lambda P: [dict(kind=T.TRI_ITEM_ADI_Y, field=u, Nx=Nx, Ny=Ny, Nz=Nz, a=a, b=b, c=c, P=P,
+                           periodic=0, method=T.TRI_PDD)]
+    T.tri_sync_status(ctx)
+    try:
+        T.tri_set_pdd_tolerance(ctx, 1e-12)
+        safe = T.tri_plan_create(ctx, item(4))
+        T.tri_sync_status(ctx)
+        unsafe = T.tri_plan_create(ctx, item(16))
+        with pytest.raises(T.TriError) as e:
+            T.tri_sync_status(ctx)
+        assert e.value.status == T.TRI_E_PDD_UNSAFE
+        T.tri_plan_execute(unsafe)
+        T.tri_plan_execute(safe)
+        T.tri_sync_status(ctx)
+        T.tri_plan_destroy(unsafe)
+        T.tri_plan_destroy(safe)
+    finally:
+        T.tri_set_pdd_tolerance(ctx, 0.0)
+
 @pytest.mark.parametrize("periodic", [False, True])
 def test_strict_pdd_per_line_coefficients(T, ctx, orc, periodic):
     """The same check in the per-line kernel: strongly dominant lines in long
