@@ -84,7 +84,7 @@ ITEMS = [  # name, direction, P, periodic, method
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU y-slab design is described in DESIGN.md", file=sys.stderr)
         sys.exit(2)
 

@@ -62,7 +62,7 @@ typedef enum {
     TRI_E_NOT_CONVERGED = 5, /* FP32 + FP64 refinement did not converge (device) */
     TRI_E_HIP = 6,           /* a HIP runtime call failed                        */
     TRI_E_NOMEM = 7,         /* device or host allocation failed                 */
-    TRI_E_UNSUPPORTED = 8    /* valid request outside what this build handles    */
+    TRI_E_UNSUPPORTED = 8    /* valid request outside what the library handles  */
 } tri_status;
 
 typedef enum { TRI_F64 = 0, TRI_F32_REFINE = 1 } tri_prec;
