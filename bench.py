@@ -85,7 +85,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU y-slab design is described in DESIGN.md", file=sys.stderr)
+              "the solves would shard as wall-normal slabs with PDD/PPT exchanges between neighbours, "
+              "which one GPU cannot show", file=sys.stderr)
         sys.exit(2)
 
     import torch
