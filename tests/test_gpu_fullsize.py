@@ -7,6 +7,8 @@ one by one.  Each solve runs on the pristine input.
 * Poisson wavenumber solves 145 x 256 x 2048 complex (PPT, P=4), k = 0 pinned
 * independent systems 4096 x 64 (PDD, P=4, one r per line), all lines
 * FP32 + FP64 refinement of the x, y, z sweeps and Poisson solves, against the exact solution
+* shifted wall-normal solves of the 3-D pressure step, 145 x 256 x 2048 complex (PPT, P=8),
+  one matrix per (k, i), the (0, 0) line pinned
 """
 import numpy as np
 import pytest
@@ -116,6 +118,30 @@ def test_fullsize_poisson(T, ctx, orc, prec):
         ref = solve(rhs.real) + 1j * solve(rhs.imag)
         assert line_relerr(got[s], ref, axis=0) <= TOL, (s, k)
 
+
+
+def test_fullsize_poisson_shifted(T, ctx, orc):
+    phihat = W.cfg_poisson_rhs(NX, NY, NZ, seed=2)
+    ay, cy = W.poisson_metric(NY)
+    lamz = W.modified_wavenumbers(NZ)
+    lamx = (4.0 * NX ** 2) * np.sin(np.pi * np.arange(NX) / (2 * NX)) ** 2
+    phi = torch.as_tensor(phihat).cuda()
+    T.poisson_shifted_solve(ctx, phi, dev(ay), dev(cy), dev(lamz), dev(lamx), P=8, method=T.TRI_PPT)
+    T.tri_sync_status(ctx)
+    rng = np.random.default_rng(8)
+    ks = np.concatenate([[0, 0, 1, 2, NK - 1], rng.integers(0, NK, 43)])
+    iis = np.concatenate([[0, 1, 0, 5, NX - 1], rng.integers(0, NX, 43)])
+    got = phi[torch.as_tensor(ks), :, torch.as_tensor(iis)].cpu().numpy()
+    assert np.all(got[0][0] == 0)
+    for s, (k, i) in enumerate(zip(ks, iis)):
+        sigma = lamz[k] + lamx[i]
+        b = -(ay + cy) - sigma
+        c_ = cy.copy()
+        rhs = phihat[k, :, i].copy()
+        if sigma == 0.0:
+            b[0] = 1.0; c_[0] = 0.0; rhs[0] = 0.0
+        ref = orc.ppt(ay, b, c_, rhs.real, 8) + 1j * orc.ppt(ay, b, c_, rhs.imag, 8)
+        assert line_relerr(got[s], ref, axis=0) <= TOL, (s, k, i)
 
 def test_fullsize_independent_lines(T, ctx, orc):
     n, nlines, P = 64, 4096, 4
