@@ -13,6 +13,9 @@ wraps it for numpy arrays:
   reference for results that converge to the exact solution
 * ``pdd``  -- Sec. 3.2, PDD paragraph and Algorithm 1 (depends on P)
 * ``ppt``  -- Sec. 3.2, Eqs. (9)-(11) (exact; periodic wrap as interface P)
+* ``dpivot`` / ``ppt_dp`` / ``ppt_dp_batch`` -- the block solver with
+  diagonal pivoting that the PPT paragraph of Sec. 3.2 names, alone and as
+  PPT's local solver; both also return every row's pivot kind
 * ``reduced_system`` -- Z (Eq. (7)), Zbar (Eq. (10)), E^T x~ and spikes
 * ``solve_batch`` / ``adi_sweep`` / ``poisson`` -- batched strided drivers
 
@@ -86,6 +89,14 @@ def lib():
         L.orc_poisson.argtypes = [ctypes.c_int, _D, _I64, _I64, _I64, _D, _D, _D,
                                   ctypes.c_int, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
+        _U8 = ctypes.POINTER(ctypes.c_uint8)
+        L.orc_dpivot.restype = ctypes.c_int
+        L.orc_dpivot.argtypes = [_I64, _D, _D, _D, ctypes.c_int, _D, _U8, _D]
+        L.orc_ppt_dp.restype = ctypes.c_int
+        L.orc_ppt_dp.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _D, _D, _D, _D, _D, _D, _U8]
+        L.orc_ppt_dp_batch.restype = ctypes.c_int
+        L.orc_ppt_dp_batch.argtypes = [_I64, ctypes.c_int, ctypes.c_int, _D, _D, _D, _I64, _I64, _I64,
+                                       _D, _I64, _I64, _I64, _I64, _I64, _U8, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -164,6 +175,57 @@ def pdd(a, b, c, d, P: int, periodic: bool = False) -> np.ndarray:
 
 def ppt(a, b, c, d, P: int, periodic: bool = False) -> np.ndarray:
     return _line(lib().orc_ppt, "ppt", a, b, c, d, P, periodic)
+
+
+def _u8(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+# pivot kinds returned by dpivot / ppt_dp
+PIV_1X1, PIV_2X2_FIRST, PIV_2X2_SECOND = 1, 2, 0
+
+
+def dpivot(a, b, c, rhs):
+    """Solve one tridiagonal block (a[0], c[m-1] unused) by diagonal pivoting.
+    rhs: (m,) or (k, m) right-hand sides.  Returns (x, piv) with piv[t] = 1 (1x1
+    pivot), 2 (first row of a 2x2 pivot) or 0 (its second row)."""
+    a, b, c = map(_f64, (a, b, c))
+    R = np.array(rhs, dtype=np.float64, copy=True, order="C")
+    one = R.ndim == 1
+    R = np.atleast_2d(R)
+    m = b.size
+    assert R.shape[1] == m
+    piv = np.zeros(m, dtype=np.uint8)
+    work = np.empty(2 * m + 1)
+    _check(lib().orc_dpivot(m, _p(a), _p(b), _p(c), R.shape[0], _p(R), _u8(piv), _p(work)), "dpivot")
+    return (R[0] if one else R), piv
+
+
+def ppt_dp(a, b, c, d, P: int, periodic: bool = False):
+    """PPT (Eqs. (9)-(11)) whose partition blocks are solved by diagonal pivoting.
+    Returns (x, piv), piv the pivot kind of every row (see dpivot)."""
+    a, b, c, d = map(_f64, (a, b, c, d))
+    n = d.size
+    x = np.empty(n)
+    piv = np.zeros(n, dtype=np.uint8)
+    work = np.empty(int(lib().orc_line_work(n, P)) + 2 * n + 2 * (n // max(P, 1)) + 8)
+    _check(lib().orc_ppt_dp(n, int(P), int(bool(periodic)), _p(a), _p(b), _p(c), _p(d), _p(x), _p(work),
+                            _u8(piv)), "ppt_dp")
+    return x, piv
+
+
+def ppt_dp_batch(d: np.ndarray, n: int, nb0: int, nb1: int, s_j: int, s_b0: int, s_b1: int, a, b, c,
+                 cs_j: int, cs_b0: int, cs_b1: int, P: int, periodic: bool = False,
+                 nthreads: int = 0) -> np.ndarray:
+    """In-place ppt_dp over strided lines of the flat FP64 array d (per-line
+    coefficients at j*cs_j + b0*cs_b0 + b1*cs_b1).  Returns the pivot kinds as
+    a (nb1*nb0, n) uint8 array, line (b0, b1) in row b1*nb0 + b0."""
+    assert d.dtype == np.float64 and d.flags.c_contiguous
+    a, b, c = map(_f64, (a, b, c))
+    piv = np.zeros((nb0 * nb1, n), dtype=np.uint8)
+    _check(lib().orc_ppt_dp_batch(n, int(P), int(bool(periodic)), _p(a), _p(b), _p(c), cs_j, cs_b0, cs_b1,
+                                  _p(d), nb0, nb1, s_j, s_b0, s_b1, _u8(piv), int(nthreads)), "ppt_dp_batch")
+    return piv
 
 
 def reduced_system(a, b, c, d, P: int, periodic: bool = False) -> dict:

@@ -535,6 +535,225 @@ int orc_poisson(int method, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
     return status;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Diagonal pivoting for one tridiagonal block: the local solver the PPT    */
+/* paragraph of Sec. 3.2 names (the parallel solver of Chang et al. that it  */
+/* cites), i.e. Gaussian elimination without row interchanges whose pivots  */
+/* are 1x1 diagonal entries or 2x2 diagonal blocks.  The paper prints no    */
+/* pivot criterion; the one used here is the Bunch-Kaufman test in the      */
+/* form given for tridiagonal matrices: with delta the current (eliminated) */
+/* diagonal entry of row k and                                               */
+/*   sigma = max(|c_k|, |a_{k+1}|, |b_{k+1}|, |c_{k+1}|, |a_{k+2}|)          */
+/* (entries outside the block count as 0), row k is a 1x1 pivot when        */
+/*   |delta| sigma >= kappa |a_{k+1} c_k|,   kappa = (sqrt(5) - 1)/2,        */
+/* else rows k, k+1 form a 2x2 pivot.  The last row is always 1x1.          */
+/*                                                                            */
+/* After elimination every row reads x_k = p_k - q_k x_{k+s}: s = 1, or     */
+/* s = 2 for the first row of a 2x2 pivot (its partner row links to k+2 as  */
+/* well).  A 1x1 pivot takes exactly the steps of orc_thomas:               */
+/*   delta = b_k - a_k q_{k-1},  q_k = c_k/delta,  p_k = (d_k - a_k p_{k-1})/delta. */
+/* A 2x2 pivot with block [[delta, c_k], [a_{k+1}, b_{k+1}]], determinant   */
+/* D = delta b_{k+1} - c_k a_{k+1} and r = d_k - a_k p_{k-1}:               */
+/*   p_k = (b_{k+1} r - c_k d_{k+1})/D,      q_k = -c_k c_{k+1}/D,           */
+/*   p_{k+1} = (delta d_{k+1} - a_{k+1} r)/D, q_{k+1} = delta c_{k+1}/D.      */
+/* m rows: a[0] and c[m-1] are not read.  rhs holds nrhs right-hand sides   */
+/* of length m one after the other and is overwritten by the solutions      */
+/* (all share the pivots).  piv[k] (nullable): 1 for a 1x1 pivot, 2 for the */
+/* first row of a 2x2 pivot, 0 for its second row.  work: 2m doubles.       */
+/* ------------------------------------------------------------------------ */
+static const double kDpKappa = 0.6180339887498948482;   /* (sqrt(5) - 1)/2 */
+
+int orc_dpivot(int64_t m, const double *a, const double *b, const double *c, int nrhs,
+               double *rhs, unsigned char *piv, double *work)
+{
+    if (m < 1 || nrhs < 0) return ORC_E_SHAPE;
+    double *q = work;                    /* q_k */
+    unsigned char *kind = (unsigned char *)(work + m);   /* pivot kinds (m bytes) */
+#define AA(k) ((k) >= 1 && (k) < m ? a[k] : 0.0)
+#define CC(k) ((k) >= 0 && (k) < m - 1 ? c[k] : 0.0)
+    /* factorisation: pivot kinds and q (shared by every right-hand side) */
+    double qprev = 0.0;                  /* q of the row linked (s = 1) to row k */
+    int64_t k = 0;
+    while (k < m) {
+        const double delta = b[k] - AA(k) * qprev;
+        int two = 0;
+        if (k + 1 < m) {
+            double sigma = fabs(CC(k));
+            sigma = fmax(sigma, fabs(AA(k + 1)));
+            sigma = fmax(sigma, fabs(b[k + 1]));
+            sigma = fmax(sigma, fabs(CC(k + 1)));
+            sigma = fmax(sigma, fabs(AA(k + 2)));
+            two = fabs(delta) * sigma < kDpKappa * fabs(AA(k + 1) * CC(k));
+        }
+        if (!two) {
+            if (delta == 0.0) return ORC_E_ZERO_PIVOT;
+            q[k] = CC(k) / delta;
+            kind[k] = 1;
+            qprev = q[k];
+            k += 1;
+        } else {
+            const double D = delta * b[k + 1] - CC(k) * AA(k + 1);
+            if (D == 0.0) return ORC_E_ZERO_PIVOT;
+            q[k] = -CC(k) * CC(k + 1) / D;
+            q[k + 1] = delta * CC(k + 1) / D;
+            kind[k] = 2;
+            kind[k + 1] = 0;
+            qprev = q[k + 1];
+            k += 2;
+        }
+    }
+    /* each right-hand side: forward p, then back substitution */
+    for (int s = 0; s < nrhs; ++s) {
+        double *x = rhs + (int64_t)s * m;
+        double pprev = 0.0, qp = 0.0;
+        k = 0;
+        while (k < m) {
+            if (kind[k] == 1) {
+                const double delta = b[k] - AA(k) * qp;
+                x[k] = (x[k] - AA(k) * pprev) / delta;
+                qp = q[k];
+                pprev = x[k];
+                k += 1;
+            } else {
+                const double delta = b[k] - AA(k) * qp;
+                const double D = delta * b[k + 1] - CC(k) * AA(k + 1);
+                const double r = x[k] - AA(k) * pprev;
+                const double dn = x[k + 1];
+                x[k] = (b[k + 1] * r - CC(k) * dn) / D;
+                x[k + 1] = (delta * dn - AA(k + 1) * r) / D;
+                qp = q[k + 1];
+                pprev = x[k + 1];
+                k += 2;
+            }
+        }
+        for (int64_t t = m - 2; t >= 0; --t) {
+            const int64_t link = kind[t] == 2 ? t + 2 : t + 1;
+            x[t] = x[t] - q[t] * (link < m ? x[link] : 0.0);
+        }
+    }
+    if (piv)
+        for (int64_t t = 0; t < m; ++t) piv[t] = kind[t];
+#undef AA
+#undef CC
+    return ORC_OK;
+}
+
+/* Local solves of Eqs. (5), (6) with the diagonal-pivoting block solver:   */
+/* the three right-hand sides of partition r (its part of d, the a-corner   */
+/* column a_{rm} e_0, the c-corner column c_{rm+m-1} e_{m-1}) go through    */
+/* one factorisation of A~_r.  piv: n bytes (nullable).  scratch: 8m.       */
+static int local_solves_dp(int64_t n, int P, int periodic, const double *a, const double *b,
+                           const double *c, const double *d, double *xt, double *v, double *w,
+                           unsigned char *piv, double *scratch)
+{
+    const int64_t m = n / P;
+    double *at = scratch, *ct = scratch + m, *R = scratch + 2 * m, *fw = scratch + 5 * m;
+    for (int r = 0; r < P; ++r) {
+        const int64_t o = (int64_t)r * m;
+        for (int64_t t = 0; t < m; ++t) { at[t] = a[o + t]; ct[t] = c[o + t]; }
+        at[0] = 0.0;          /* Delta A: remove the a-corner of the block */
+        ct[m - 1] = 0.0;      /* Delta A: remove the c-corner of the block */
+        for (int64_t t = 0; t < 3 * m; ++t) R[t] = 0.0;
+        for (int64_t t = 0; t < m; ++t) R[t] = d[o + t];
+        if (r >= 1 || periodic) R[m] = a[o];
+        if (r <= P - 2 || periodic) R[2 * m + m - 1] = c[o + m - 1];
+        int st = orc_dpivot(m, at, b + o, ct, 3, R, piv ? piv + o : NULL, fw);
+        if (st) return st;
+        for (int64_t t = 0; t < m; ++t) {
+            xt[o + t] = R[t];
+            v[o + t] = R[m + t];
+            w[o + t] = R[2 * m + t];
+        }
+    }
+    return ORC_OK;
+}
+
+/* PPT (Eqs. (9)-(11)) with diagonal pivoting in the partition blocks: the  */
+/* local solves above, then the same Zbar assembly, GEPP and correction as  */
+/* orc_ppt.  piv (nullable): the pivot kind of every row of the line.       */
+/* work: orc_line_work(n, P) + 2n doubles.                                   */
+int orc_ppt_dp(int64_t n, int P, int periodic, const double *a, const double *b,
+               const double *c, const double *d, double *x, double *work, unsigned char *piv)
+{
+    int st = check_shape(n, P, periodic);
+    if (st) return st;
+    const int64_t m = n / P;
+    const int NI = n_interfaces(P, periodic), K = 2 * NI;
+    double *xt = work, *v = work + n, *w = work + 2 * n, *scratch = work + 3 * n;
+    double *Z = scratch + 8 * m, *Zbar = Z + K * K, *rhs = Zbar + K * K, *ybar = rhs + K;
+    double *y = ybar + K;
+    st = local_solves_dp(n, P, periodic, a, b, c, d, xt, v, w, piv, scratch);
+    if (st) return st;
+    if (P == 1 && !periodic) {
+        for (int64_t t = 0; t < n; ++t) x[t] = xt[t];
+        return ORC_OK;
+    }
+    assemble_Z(m, P, periodic, xt, v, w, Z, rhs);
+    for (int row = 0; row < K; ++row)
+        for (int col = 0; col < K; col += 2) {
+            Zbar[row * K + col] = Z[row * K + col + 1];
+            Zbar[row * K + col + 1] = Z[row * K + col];
+        }
+    for (int k = 0; k < K; ++k) ybar[k] = rhs[k];
+    st = gepp_solve(K, Zbar, ybar);                                    /* Eq. (10) */
+    if (st) return st;
+    permute_pairs(K, ybar, y);
+    correct(m, P, periodic, xt, v, w, y, x);                           /* Eq. (11) */
+    return ORC_OK;
+}
+
+/* Batched strided driver of orc_ppt_dp (layout as orc_solve_batch, with   */
+/* per-line coefficients allowed).  piv (nullable): nb0*nb1*n bytes, line  */
+/* (b0, b1) at (b1*nb0 + b0)*n.                                              */
+int orc_ppt_dp_batch(int64_t n, int P, int periodic, const double *a, const double *b,
+                     const double *c, int64_t cs_j, int64_t cs_b0, int64_t cs_b1, double *d,
+                     int64_t nb0, int64_t nb1, int64_t s_j, int64_t s_b0, int64_t s_b1,
+                     unsigned char *piv, int nthreads)
+{
+    if (!a || !b || !c || !d) return ORC_E_ARG;
+    int status = check_shape(n, P, periodic);
+    if (status) return status;
+    const int64_t nlines = nb0 * nb1;
+    const int64_t lw = orc_line_work(n, P) + 2 * n + 2 * (n / P);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(5 * n + lw));
+        if (!buf) {
+#pragma omp critical
+            status = ORC_E_NOMEM;
+        } else {
+            double *la = buf, *lb = buf + n, *lc = buf + 2 * n, *ld = buf + 3 * n;
+            double *lx = buf + 4 * n, *work = buf + 5 * n;
+#pragma omp for schedule(static)
+            for (int64_t L = 0; L < nlines; ++L) {
+                const int64_t b0 = L % nb0, b1 = L / nb0;
+                const int64_t o = b0 * s_b0 + b1 * s_b1, co = b0 * cs_b0 + b1 * cs_b1;
+                for (int64_t j = 0; j < n; ++j) {
+                    la[j] = a[co + j * cs_j];
+                    lb[j] = b[co + j * cs_j];
+                    lc[j] = c[co + j * cs_j];
+                    ld[j] = d[o + j * s_j];
+                }
+                const int st = orc_ppt_dp(n, P, periodic, la, lb, lc, ld, lx, work,
+                                          piv ? piv + L * n : NULL);
+                if (st) {
+#pragma omp critical
+                    if (status == ORC_OK) status = st;
+                    continue;
+                }
+                for (int64_t j = 0; j < n; ++j) d[o + j * s_j] = lx[j];
+            }
+            free(buf);
+        }
+    }
+    return status;
+}
+
 int orc_max_threads(void)
 {
 #ifdef _OPENMP

@@ -29,7 +29,7 @@ __all__ = [
     "tanh_faces", "momentum_uniform", "momentum_periodic", "momentum_stretched",
     "poisson_metric", "modified_wavenumbers", "spanwise_rfft",
     "cfg_independent", "cfg_field", "cfg_poisson_rhs", "random_tridiag",
-    "RAGGED_SUBGRIDS",
+    "random_tridiag_nondominant", "pivot_probe", "RAGGED_SUBGRIDS",
 ]
 
 NU = 1.0e-3
@@ -173,3 +173,44 @@ def random_tridiag(n: int, rng: np.random.Generator, margin: float = 1.0,
     sgn = np.where(rng.uniform(size=n) < 0.5, -1.0, 1.0)
     b = sgn * (np.abs(a) + np.abs(c) + margin * rng.uniform(0.5, 1.5, n))
     return a, b, c
+
+
+def pivot_probe(n: int, P: int, rng: np.random.Generator):
+    """A line whose diagonal-pivoting elimination is exact in FP64 and whose pivot
+    kinds are fixed by construction.
+
+    Every partition (m = n/P rows, decoupled from its neighbours: a = 0 at its first
+    row, c = 0 at its last) is a random sequence of
+    * single rows: b = +-2^e (e in 0..3), a = +-2^k coupling back (0 at the
+      partition's first row), c = 0;
+    * pairs of rows t, t+1 with b_t = b_{t+1} = 0 and c_t, a_{t+1} = +-2^k, a_t
+      coupling back, c_{t+1} coupling forward (0 at the partition's last row);
+    with k in {-1, 0, 1} and integer right-hand sides in [-8, 8].  A pair's first
+    row reaches elimination with a zero diagonal entry and so needs a 2x2 pivot;
+    every other row is a 1x1 pivot.  Returns (a, b, c, d, pair_starts)."""
+    m = n // P
+    pow2 = lambda: float(rng.choice([-1.0, 1.0])) * 2.0 ** int(rng.integers(-1, 2))
+    a = np.zeros(n)
+    b = np.zeros(n)
+    c = np.zeros(n)
+    d = rng.integers(-8, 9, n).astype(np.float64)
+    starts = []
+    for r in range(P):
+        t = 0
+        while t < m:
+            j = r * m + t
+            if t + 1 < m and rng.uniform() < 0.5:
+                c[j] = pow2()
+                a[j + 1] = pow2()
+                if t > 0:
+                    a[j] = pow2()
+                if t + 2 < m:
+                    c[j + 1] = pow2()
+                starts.append(j)
+                t += 2
+            else:
+                b[j] = float(rng.choice([-1.0, 1.0])) * 2.0 ** int(rng.integers(0, 4))
+                if t > 0:
+                    a[j] = pow2()
+                t += 1
+    return a, b, c, d, starts
