@@ -30,7 +30,15 @@
  * Right-hand sides are overwritten in place by the solution (Algorithm 1
  * returns its outputs in d1, d2, d3).  Work is queued on the context's
  * stream and the call returns without waiting, unless a tri_info is passed
- * (then the call waits for the stream to fill it in).
+ * (then the call waits for the stream to fill it in).  The library's own
+ * device memory is allocated only by the set-up calls (tri_create,
+ * tri_reserve, tri_plan_create): a solve never allocates or frees memory
+ * and waits only to fill a tri_info, so every solve called without one can
+ * be recorded into a HIP graph.  One-shot solves with a
+ * shared matrix keep its partition factors in the context workspace
+ * (64 MiB from tri_create, grown by tri_reserve); a call that needs more
+ * returns TRI_E_NOMEM before launching anything.  Calls on one context
+ * share that workspace and must be queued on one stream.
  *
  * Errors: argument and shape errors are returned before anything is launched
  * and leave the data untouched.  Conditions found on the device (a zero pivot
@@ -106,12 +114,23 @@ typedef struct {
 
 /* Create a context on HIP device `device`, queueing work on `hip_stream`
  * (a hipStream_t; NULL = the device's null stream).  Allocates the status
- * word.  *out receives the handle. */
+ * word and a 64 MiB workspace (see tri_reserve).  *out receives the
+ * handle. */
 tri_status tri_create(tri_ctx *out, int device, void *hip_stream);
 /* Release the context and its workspace (waits for its stream). */
 tri_status tri_destroy(tri_ctx ctx);
 /* Change the stream later calls queue on. */
 tri_status tri_set_stream(tri_ctx ctx, void *hip_stream);
+/* Grow the context workspace so that one-shot solves (tri_pdd_solve,
+ * tri_ppt_solve, adi_sweep, poisson_wavenumber_solve, projection_step) with
+ * up to `matrices` distinct shared matrices (a Poisson call has one per
+ * wavenumber; a matrix per b1 index counts nb1) of up to n rows at up to P
+ * partitions fit; never shrinks.  Waits for the context stream, then
+ * reallocates (a set-up call: never between the launches of a graph
+ * capture).  TRI_E_ARG for n < 1, P outside 1..TRI_MAX_PARTITIONS or
+ * matrices < 1; TRI_E_NOMEM if the device allocation fails (the context
+ * then holds no workspace until a later tri_reserve succeeds). */
+tri_status tri_reserve(tri_ctx ctx, int64_t n, int P, int64_t matrices);
 /* Strict PDD (Sec. 3.2 holds PDD accurate only where the entries it drops
  * from Z are negligible): with tol > 0, every later PDD solve of this
  * context -- one-shot calls, poisson_shifted_solve with TRI_PDD, and plans
@@ -220,8 +239,7 @@ tri_status poisson_shifted_solve(tri_ctx ctx, double *phihat, int64_t Nx, int64_
  * Nz must be even with Nz/2 = 2^a 3^b 5^c <= 512 (TRI_E_SHAPE for odd or
  * Nz < 2, TRI_E_UNSUPPORTED otherwise).  Arrays one call reads and writes
  * must not overlap (TRI_E_ARG), except where stated.  Calls are
- * asynchronous on the context stream; all but projection_step allocate
- * nothing. */
+ * asynchronous on the context stream and allocate nothing. */
 
 /* Real FFT along z of `lines` independent stations: for every station g,
  * xhat[k][g] = sum_n x[n][g] exp(-2 pi i k n / Nz), k = 0..Nz/2, with x of
@@ -256,8 +274,9 @@ tri_status projection_correct(tri_ctx ctx, const double *phihat, double *phi, do
  * velocity to be divergence free they must be the metric of this grid:
  * ay_j = 1/(dy_j h_j), cy_j = 1/(dy_j h_{j+1}), lam_k = (4/dz^2) sin^2(pi k/Nz)),
  * then projection_correct into phi.  The Poisson factors are computed on
- * every call, in the context workspace (grown as poisson_wavenumber_solve
- * grows it); a plan holding a Poisson item avoids both in a time loop. */
+ * every call, in the context workspace (TRI_E_NOMEM before any launch if it
+ * is too small, see tri_reserve); a plan holding a Poisson item factors
+ * them once. */
 tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, double dz,
                            const double *ay, const double *cy, const double *lam, double *phihat,
                            double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P);

@@ -26,7 +26,7 @@ __all__ = [
     "TriLines", "TriCoef", "TriInfo", "TriItem", "EXPORTED",
     "TRI_F64", "TRI_F32_REFINE", "TRI_REAL", "TRI_COMPLEX", "TRI_PDD", "TRI_PPT",
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
-    "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy",
+    "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
     "projection3d_correct", "projection3d_step",
@@ -48,7 +48,7 @@ EXPORTED = [
     "tri_create", "tri_destroy", "tri_set_stream", "tri_set_pdd_tolerance", "tri_sync_status", "tri_status_string",
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
-    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy",
+    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
     "projection3d_correct", "projection3d_step",
@@ -125,6 +125,7 @@ def lib():
         "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
         "tri_plan_destroy": (_I, [_V]),
         "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
+        "tri_reserve": (_I, [_V, _I64, _I, _I64]),
         "poisson_shifted_solve": (_I, [_V, _V, _I64, _I64, _I64, _V, _V, _V, _V, _I, _I]),
         "streamwise_dct": (_I, [_V, _V, _I64, _I64]),
         "streamwise_idct": (_I, [_V, _V, _I64, _I64]),
@@ -196,6 +197,12 @@ def tri_destroy(ctx) -> None:
 
 def tri_set_stream(ctx, stream: int | None) -> None:
     _check(lib().tri_set_stream(ctx, stream), "tri_set_stream", ctx)
+
+
+def tri_reserve(ctx, n: int, P: int, matrices: int) -> None:
+    """Grow the context workspace for one-shot solves with up to `matrices`
+    shared matrices of n rows at P partitions (waits for the stream)."""
+    _check(lib().tri_reserve(ctx, int(n), int(P), int(matrices)), "tri_reserve", ctx)
 
 
 def tri_set_pdd_tolerance(ctx, tol: float) -> None:

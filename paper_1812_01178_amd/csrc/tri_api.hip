@@ -491,7 +491,13 @@ Tables carve_tables(void *base, int64_t G, int64_t n, int P, int periodic, int m
     return T;
 }
 
-tri_status ensure_ws(tri_ctx ctx, size_t bytes)
+// The context workspace is allocated by tri_create and grown only by
+// tri_reserve (both set-up calls that may wait for the stream); a solve that
+// needs more refuses before its first launch instead of reallocating, so no
+// solve allocates, frees or waits.
+constexpr size_t kDefaultWorkspaceBytes = size_t(64) << 20;
+
+tri_status grow_ws(tri_ctx ctx, size_t bytes)
 {
     if (bytes <= ctx->ws_bytes) return TRI_OK;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -503,6 +509,14 @@ tri_status ensure_ws(tri_ctx ctx, size_t bytes)
     ctx->ws = p;
     ctx->ws_bytes = bytes;
     return TRI_OK;
+}
+
+tri_status need_ws(tri_ctx ctx, size_t bytes)
+{
+    if (bytes <= ctx->ws_bytes) return TRI_OK;
+    return fail(ctx, TRI_E_NOMEM,
+                "the call needs %zu workspace bytes, the context holds %zu: reserve them with tri_reserve", bytes,
+                ctx->ws_bytes);
 }
 
 tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info, bool refined = false)
@@ -582,7 +596,7 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
         HIP_TRY(ctx, launch_general(g, pb.method, ctx->stream));
         return fill_info(ctx, nullptr, info);
     }
-    tri_status st = ensure_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
+    tri_status st = need_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
     if (st) return st;
     Tables T = carve_tables(ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
     T.pdd_tol = prec == TRI_F32_REFINE ? 0.0 : ctx->pdd_tol;   // refinement reaches A^-1 d
@@ -728,8 +742,25 @@ tri_status tri_create(tri_ctx *out, int device, void *hip_stream)
         delete ctx;
         return TRI_E_HIP;
     }
+    if (grow_ws(ctx, kDefaultWorkspaceBytes) != TRI_OK) {
+        (void)hipFree(ctx->status_dev);
+        delete ctx;
+        return TRI_E_NOMEM;
+    }
     *out = ctx;
     return TRI_OK;
+}
+
+tri_status tri_reserve(tri_ctx ctx, int64_t n, int P, int64_t matrices)
+{
+    if (!ctx) return TRI_E_ARG;
+    if (n < 1 || P < 1 || P > TRI_MAX_PARTITIONS || matrices < 1)
+        return fail(ctx, TRI_E_ARG, "tri_reserve: n = %lld, P = %d, matrices = %lld", (long long)n, P,
+                    (long long)matrices);
+    if (n > (int64_t(1) << 32) || matrices > (int64_t(1) << 32) || n * matrices > (int64_t(1) << 34))
+        return fail(ctx, TRI_E_NOMEM, "tri_reserve: %lld matrices of %lld rows", (long long)matrices, (long long)n);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return grow_ws(ctx, tables_bytes(matrices, n, P));
 }
 
 tri_status tri_destroy(tri_ctx ctx)

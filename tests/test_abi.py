@@ -57,6 +57,7 @@ def test_null_context_and_status_strings(T):
     assert L.tri_plan_item_partitions(None, 0) == -1
     assert L.tri_stream_copy(None, None, None, 0) == T.TRI_E_ARG
     assert L.tri_set_pdd_tolerance(None, 1e-12) == T.TRI_E_ARG
+    assert L.tri_reserve(None, 64, 4, 1) == T.TRI_E_ARG
     # the pressure-step entry points refuse a null context before anything else
     assert L.spanwise_rfft(None, None, None, 4, 8) == T.TRI_E_ARG
     assert L.spanwise_irfft(None, None, None, 4, 8) == T.TRI_E_ARG
