@@ -17,7 +17,8 @@ wraps it for numpy arrays:
   diagonal pivoting that the PPT paragraph of Sec. 3.2 names, alone and as
   PPT's local solver; both also return every row's pivot kind
 * ``reduced_system`` -- Z (Eq. (7)), Zbar (Eq. (10)), E^T x~ and spikes
-* ``solve_batch`` / ``adi_sweep`` / ``poisson`` -- batched strided drivers
+* ``solve_batch`` / ``adi_sweep`` / ``poisson`` / ``poisson_shifted_batch`` --
+  batched strided drivers
 
 Function for function, every pin that checks these lives in
 ``tests/test_oracle_*.py``.
@@ -89,6 +90,9 @@ def lib():
         L.orc_poisson.argtypes = [ctypes.c_int, _D, _I64, _I64, _I64, _D, _D, _D,
                                   ctypes.c_int, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_poisson_shifted.restype = ctypes.c_int
+        L.orc_poisson_shifted.argtypes = [ctypes.c_int, _D, _I64, _I64, _I64, _D, _D, _D, _D,
+                                          ctypes.c_int, ctypes.c_int]
         _U8 = ctypes.POINTER(ctypes.c_uint8)
         L.orc_dpivot.restype = ctypes.c_int
         L.orc_dpivot.argtypes = [_I64, _D, _D, _D, ctypes.c_int, _D, _U8, _D]
@@ -276,6 +280,18 @@ def poisson(phihat: np.ndarray, ay, cy, lam, P: int, method: int = PPT,
     flat = phihat.view(np.float64)
     _check(lib().orc_poisson(int(method), _p(flat), Nx, Ny, Nk, _p(ay), _p(cy), _p(lam),
                              int(P), int(nthreads)), "poisson")
+
+
+def poisson_shifted_batch(phihat: np.ndarray, ay, cy, lamz, lamx, P: int, method: int = PPT,
+                          nthreads: int = 0) -> None:
+    """The solves of poisson_shifted below, every line in C (OpenMP over lines);
+    method PPT, PDD, EXACT or EXACT_LD."""
+    assert phihat.dtype == np.complex128 and phihat.flags.c_contiguous and phihat.ndim == 3
+    Nk, Ny, Nx = phihat.shape
+    ay, cy, lamz, lamx = map(_f64, (ay, cy, lamz, lamx))
+    assert lamz.size == Nk and lamx.size == Nx
+    _check(lib().orc_poisson_shifted(int(method), _p(phihat.view(np.float64)), Nx, Ny, Nk, _p(ay), _p(cy),
+                                     _p(lamz), _p(lamx), int(P), int(nthreads)), "poisson_shifted")
 
 
 def poisson_shifted(phihat: np.ndarray, ay, cy, lamz, lamx, P: int, method: int = PPT) -> None:

@@ -536,6 +536,76 @@ int orc_poisson(int method, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Wall-normal Poisson solves once both homogeneous directions are          */
+/* transformed (Sec. 2.2; PPT paragraph of Sec. 3.2): one real matrix per    */
+/* line (k, i) of phihat[Nk][Ny][Nx] complex128, a_j = ay_j, c_j = cy_j,      */
+/* b_j = -(ay_j + cy_j) - (lamz_k + lamx_i).  A line whose shift is 0 is the */
+/* singular Neumann operator: row 0 is replaced by x_0 = 0.  Real and        */
+/* imaginary parts are two right-hand sides of the same matrix, each solved  */
+/* by the method given (ORC_PPT, ORC_PDD, ORC_EXACT or ORC_EXACT_LD).        */
+/* ------------------------------------------------------------------------ */
+int orc_poisson_shifted(int method, double *phihat, int64_t Nx, int64_t Ny, int64_t Nk,
+                        const double *ay, const double *cy, const double *lamz,
+                        const double *lamx, int P, int nthreads)
+{
+    if (!phihat || !ay || !cy || !lamz || !lamx) return ORC_E_ARG;
+    if (method == ORC_PDD || method == ORC_PPT) {
+        int st = check_shape(Ny, P, 0);
+        if (st) return st;
+    }
+    const int64_t n = Ny, lw = orc_line_work(n, P);
+    int status = ORC_OK;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        double *buf = (double *)malloc(sizeof(double) * (size_t)(6 * n + lw));
+        if (!buf) {
+#pragma omp critical
+            status = ORC_E_NOMEM;
+        } else {
+            double *la = buf, *lb = buf + n, *lc = buf + 2 * n, *ld = buf + 3 * n;
+            double *lx = buf + 4 * n, *work = buf + 6 * n;
+#pragma omp for schedule(static)
+            for (int64_t L = 0; L < Nk * Nx; ++L) {
+                const int64_t k = L / Nx, i = L % Nx;
+                const double sigma = lamz[k] + lamx[i];
+                for (int64_t j = 0; j < n; ++j) {
+                    la[j] = ay[j];
+                    lc[j] = cy[j];
+                    lb[j] = -(ay[j] + cy[j]) - sigma;
+                }
+                if (sigma == 0.0) {           /* gauge: x_0 = 0 */
+                    lb[0] = 1.0;
+                    lc[0] = 0.0;
+                }
+                for (int part = 0; part < 2; ++part) {
+                    double *base = phihat + 2 * (k * Ny * Nx + i) + part;
+                    for (int64_t j = 0; j < n; ++j) ld[j] = base[2 * j * Nx];
+                    if (sigma == 0.0) ld[0] = 0.0;
+                    int st;
+                    if (method == ORC_PDD) st = orc_pdd(n, P, 0, la, lb, lc, ld, lx, work);
+                    else if (method == ORC_PPT) st = orc_ppt(n, P, 0, la, lb, lc, ld, lx, work);
+                    else if (method == ORC_EXACT_LD) st = orc_exact_ld(n, 0, la, lb, lc, ld, lx);
+                    else st = orc_exact(n, 0, la, lb, lc, ld, lx, work);
+                    if (st) {
+#pragma omp critical
+                        if (status == ORC_OK) status = st;
+                        break;
+                    }
+                    for (int64_t j = 0; j < n; ++j) base[2 * j * Nx] = lx[j];
+                }
+            }
+            free(buf);
+        }
+    }
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Diagonal pivoting for one tridiagonal block: the local solver the PPT    */
 /* paragraph of Sec. 3.2 names (the parallel solver of Chang et al. that it  */
 /* cites), i.e. Gaussian elimination without row interchanges whose pivots  */

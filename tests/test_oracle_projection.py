@@ -98,11 +98,13 @@ def test_spanwise_rfft_parseval_and_round_trip():
 
 # ---- shifted wall-normal systems (both homogeneous directions transformed) ----
 
-@pytest.mark.parametrize("P,method", [(4, "PPT"), (8, "PPT"), (1, "EXACT")])
-def test_shifted_poisson_manufactured_cosines(orc, P, method):
+@pytest.mark.parametrize("P,method,driver", [(P, m, d) for P, m in [(4, "PPT"), (8, "PPT"), (1, "EXACT")]
+                                               for d in ("loop", "batch")] + [(1, "EXACT_LD", "batch")])
+def test_shifted_poisson_manufactured_cosines(orc, P, method, driver):
     """Uniform Neumann mesh: cos(pi q (j + 1/2)/N) is an eigenvector of the cell-centred
     d2/dy2 with eigenvalue -(4/h^2) sin^2(pi q/(2N)); with the shift sigma the solution is
-    d / (eigenvalue - sigma) for every line, whatever its shift."""
+    d / (eigenvalue - sigma) for every line, whatever its shift.  Both drivers (the
+    per-line Python loop and the C batch over every line) are held to it."""
     ny, h = 64, 1.0 / 64
     ay = np.full(ny, 1 / h ** 2)
     cy = np.full(ny, 1 / h ** 2)
@@ -123,7 +125,8 @@ def test_shifted_poisson_manufactured_cosines(orc, P, method):
             sig = lamz[k] + lamx[i]
             ph[k, :, i] = d1 + 1j * d2
             want[k, :, i] = d1 / (e1 - sig) + 1j * d2 / (e2 - sig)
-    orc.poisson_shifted(ph, ay, cy, lamz, lamx, P, getattr(orc, method))
+    fn = orc.poisson_shifted if driver == "loop" else orc.poisson_shifted_batch
+    fn(ph, ay, cy, lamz, lamx, P, getattr(orc, method))
     assert np.max(np.abs(ph - want)) <= 1e-12 * np.max(np.abs(want))
 
 
@@ -143,6 +146,9 @@ def test_shifted_poisson_gauge_pinned_line(orc):
     orc.poisson_shifted(got, ay, cy, lamz, lamx, 4)
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
     assert np.all(got[0, 0, :] == 0)
+    got_b = ph.copy()
+    orc.poisson_shifted_batch(got_b, ay, cy, lamz, lamx, 4)
+    assert np.array_equal(got_b, got)           # same arithmetic, line by line
 
 
 # ---- the 3-D step: cosine transform in x -------------------------------------
