@@ -133,6 +133,10 @@ def main():
         u.copy_(du0)
         phi.copy_(dphi0)
         torch.cuda.synchronize()
+    # every solve's result on the pristine input, kept on the host for the
+    # comparison with the oracle in the CPU-baseline leg (outside any timing)
+    keep = args.cpu_seconds > 0 and not args.no_parity
+    pristine = {"fp64": pristine_outputs(plans, u, phi, du0, dphi0, ITEMS, T)} if keep else {}
 
     # ---------------- timed steps -----------------------------------------
     names = [it[0] for it in ITEMS]
@@ -187,14 +191,15 @@ def main():
     refine = None
     if not args.no_refine:
         refine = refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef,
-                                u0, phi0, ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, per_item_ms)
+                                u0, phi0, ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, per_item_ms,
+                                pristine if keep else None)
 
     # ---------------- ragged batch: eight sub-grids in one plan -----------
     ragged = None
     if not args.no_ragged:
         del u, phi, du0, dphi0
         torch.cuda.empty_cache()
-        ragged = ragged_section(T, ctx, stream, args)
+        ragged = ragged_section(T, ctx, stream, args, pristine if keep else None)
 
     # ---------------- pressure step: FFT + Poisson + correction -----------
     pressure = None
@@ -205,13 +210,26 @@ def main():
     # ---------------- independent systems with their own coefficients -----
     independent = None
     if not args.no_independent:
-        independent = independent_section(T, ctx, stream, args)
+        independent = independent_section(T, ctx, stream, args, pristine if keep else None)
 
     # ---------------- CPU oracle baseline (bounded sample) ----------------
+    # and, outside every timed region, each result's error against the oracle
     cpu = None
+    oracle_err = None
     if args.cpu_seconds > 0:
-        import oracle      # the CPU baseline is the only use of the oracle here
+        import oracle      # the CPU-baseline leg is the only use of the oracle here
         cpu = cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, args.cpu_seconds)
+        if keep:
+            oracle_err = oracle_parity(oracle, pristine, u0, phi0, coef, ay, cy, lam)
+            if refine is not None:
+                refine["oracle_err_max_line"] = oracle_err.pop("fp32_refine")
+            if ragged is not None:
+                for prec_name in ("fp64", "fp32_refine"):
+                    ragged[prec_name]["oracle_err_max_line"] = oracle_err.pop("ragged_" + prec_name)
+            if independent is not None:
+                for name, e in oracle_err.pop("independent").items():
+                    independent[name]["oracle_err_max_line"] = e
+            oracle_err = oracle_err["fp64"]
 
     out = {
         "metric": METRIC,
@@ -242,6 +260,11 @@ def main():
                      "copy_GB_s": copy["GB_s"], "copy_frac": kernels[dom]["copy_frac"]},
         "copy_ceiling": copy,
         "residual_max_line": residual,
+        "oracle_err_max_line": oracle_err,
+        "oracle_err_def": ("per line max_j |x - x_oracle| / max_j |x_oracle| on the pristine input, worst line; "
+                           "FP64 PDD/PPT against the oracle's PDD/PPT at the same P, FP32+refine against the "
+                           "oracle's extended-precision exact solve (Poisson modes k <= 2 against its PPT); "
+                           "ragged: per sub-grid, the composed x -> y -> z step and the Poisson solves"),
         "fp32_refine": refine,
         "ragged_batch": ragged,
         "pressure_step": pressure,
@@ -252,6 +275,100 @@ def main():
         T.tri_plan_destroy(p)
     T.tri_destroy(ctx)
     print(json.dumps(out), flush=True)
+
+
+def pristine_outputs(plans, u, phi, du0, dphi0, items, T):
+    """Each item's plan run once from the pristine input; its whole result
+    copied to the host (the field is restored afterwards)."""
+    out = {}
+    for name, *_ in items:
+        if name == "poisson":
+            phi.copy_(dphi0)
+            T.tri_plan_execute(plans[name])
+            out[name] = phi.cpu().numpy()
+        else:
+            u.copy_(du0)
+            T.tri_plan_execute(plans[name])
+            out[name] = u.cpu().numpy()
+    u.copy_(du0)
+    phi.copy_(dphi0)
+    return out
+
+
+def line_relerr(got, ref, axis):
+    """Worst per-line relative error max_j |x - x_ref| / max_j |x_ref| along `axis`."""
+    num = np.max(np.abs(got - ref), axis=axis)
+    den = np.max(np.abs(ref), axis=axis)
+    return float(np.max(num / np.where(den == 0, 1.0, den)))
+
+
+def oracle_parity(oracle, pristine, u0, phi0, coef, ay, cy, lam):
+    """Every result kept from a pristine-input run against the oracle, line by
+    line (the CPU-baseline leg; nothing here is timed).  FP64 PDD/PPT against
+    the oracle at the same P; FP32+refine against the extended-precision exact
+    solve, Poisson modes k <= 2 (kept FP64) against the oracle's PPT."""
+    t0 = time.perf_counter()
+    err = {}
+    LD = oracle.EXACT_LD
+
+    def adi_ref(d, P, method, u_in=u0, cf=coef):
+        ref = np.array(u_in, copy=True)
+        oracle.adi_sweep(method, d, ref, *cf["xyz"[d]], P, d == 2)
+        return ref
+
+    def poisson_ref(refine, P, p_in=phi0, a_=ay, c_=cy, l_=lam):
+        ref = np.array(p_in, copy=True)
+        oracle.poisson(ref, a_, c_, l_, P=P)
+        if refine:
+            ld = np.array(p_in, copy=True)
+            oracle.poisson(ld, a_, c_, l_, P=P, method=LD)
+            ref[3:] = ld[3:]
+        return ref
+
+    for prec in ("fp64", "fp32_refine"):
+        if prec not in pristine:
+            continue
+        e = {}
+        for name, d, P, per, meth in ITEMS:
+            got = pristine[prec][name]
+            if name == "poisson":
+                e[name] = line_relerr(got, poisson_ref(prec != "fp64", P), 1)
+            else:
+                e[name] = line_relerr(got, adi_ref(d, P, oracle.PDD if prec == "fp64" else LD), 2 - d)
+            log(f"oracle parity {prec} {name}: worst line {e[name]:.2e}")
+        err[prec] = e
+        del pristine[prec]
+    for prec in ("fp64", "fp32_refine"):
+        key = "ragged_" + prec
+        if key not in pristine:
+            continue
+        worst_adi = worst_poi = 0.0
+        for g in pristine.pop(key):
+            cf = dict(zip("xyz", g["coef"]))
+            ref = np.array(g["u0"], copy=True)
+            for d in range(3):
+                oracle.adi_sweep(oracle.PDD if prec == "fp64" else LD, d, ref, *cf["xyz"[d]], g["P"][d], d == 2)
+            worst_adi = max(worst_adi, line_relerr(g["u"], ref, 0))
+            pref = poisson_ref(prec != "fp64", g["P"][3], g["phi0"], *g["metric"], g["lam"])
+            worst_poi = max(worst_poi, line_relerr(g["phi"], pref, 1))
+        err[key] = {"adi_step": worst_adi, "poisson": worst_poi}
+        log(f"oracle parity ragged {prec}: ADI step {worst_adi:.2e}, Poisson {worst_poi:.2e}")
+    if "independent" in pristine:
+        ind = pristine.pop("independent")
+        r, d, P = ind["r"], ind["d"], ind["P"]
+        n, nlines = d.shape
+        e = {}
+        for name, method in (("pdd_fp64", oracle.PDD), ("ppt_fp64", oracle.PPT), ("ppt_fp32_refine", LD)):
+            if name not in ind:
+                continue
+            ref = np.array(d, copy=True).ravel()
+            oracle.solve_batch(method, ref, n, nlines, 1, s_j=nlines, s_b0=1, s_b1=0, a=-r, b=1 + 2 * r, c=-r,
+                               cs_j=0, cs_b0=1, cs_b1=0, P=P)
+            e[name] = line_relerr(ind[name], ref.reshape(n, nlines), 0)
+            log(f"oracle parity independent {name}: worst line {e[name]:.2e}")
+        err["independent"] = e
+    log(f"oracle parity of every kept result: {time.perf_counter() - t0:.1f}s")
+    return err
 
 
 def sampled_lines(u, u0, direction, nsamp, rng):
@@ -415,7 +532,7 @@ REFINE_P = {"adi_z": 4}
 
 
 def refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef, u0, phi0,
-                   ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, fp64_ms):
+                   ay, cy, lam, nx, ny, nz, nk, args, unknowns, bytes_per, fp64_ms, pristine=None):
     """FP32 elimination + FP64 residual refinement (Poisson modes k <= 2 in
     FP64) on the step's four solves, timed like the FP64 step; the backward
     error of sampled lines is checked (the refined result is the exact
@@ -446,6 +563,8 @@ def refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, co
         status = "converged"
     except T.TriError as ex:
         status = str(ex)
+    if pristine is not None:
+        pristine["fp32_refine"] = pristine_outputs(plans, u, phi, du0, dphi0, items, T)
     u.copy_(du0)
     phi.copy_(dphi0)
     torch.cuda.synchronize()
@@ -665,7 +784,7 @@ def pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy_gbs):
     return out
 
 
-def independent_section(T, ctx, stream, args):
+def independent_section(T, ctx, stream, args, pristine=None):
     """4096 independent systems of 64 unknowns, a = c = -r, b = 1 + 2r with one
     r ~ U[0.1, 10] per system, d ~ U[-1, 1] (seed 0), P = 4, lines side by side
     (row j of system s at j * 4096 + s): FP64 PDD and PPT and FP32 + refinement
@@ -691,6 +810,8 @@ def independent_section(T, ctx, stream, args):
         info = fn(ctx, da, db, dc, x, lines, coef_strides=(0, 1, 0), P=P, prec=prec, info=True)
         T.tri_sync_status(ctx)
         got = x.cpu().numpy()
+        if pristine is not None:
+            pristine.setdefault("independent", {"r": r, "d": d, "P": P})[name] = got
         reps = 50
         for _ in range(3):
             fn(ctx, da, db, dc, x, lines, coef_strides=(0, 1, 0), P=P, prec=prec)
@@ -712,7 +833,7 @@ def independent_section(T, ctx, stream, args):
     return out
 
 
-def ragged_section(T, ctx, stream, args):
+def ragged_section(T, ctx, stream, args, pristine=None):
     """The batched ragged workload: eight sub-grids (Nx, Ny, Nz) covering
     Nx in {256..2048}, Ny in {128, 256}, Nz in {96, 288}, each with an x, y and
     periodic-z momentum sweep (PDD) and its Poisson wavenumber solves (PPT),
@@ -815,6 +936,11 @@ def ragged_section(T, ctx, stream, args):
         reset()
         T.tri_plan_execute(plan)
         T.tri_sync_status(ctx)
+        if pristine is not None:
+            pristine["ragged_" + prec_name] = [
+                dict(shape=g["shape"], u0=g["u0"], phi0=g["phi0"], coef=g["coef"], metric=g["metric"], lam=g["lam"],
+                     P=Ps[4 * s_:4 * s_ + 4], u=g["u"].cpu().numpy(), phi=g["phi"].cpu().numpy())
+                for s_, g in enumerate(grids)]
         errs = [ragged_residual(grids[s_]) for s_ in (range(len(grids)) if prec == T.TRI_F64 else (0, 3, 4))]
         parity = max(max(e) for e in errs)
         # in-place solves re-solve their own output; each field is reset

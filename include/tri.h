@@ -182,6 +182,18 @@ tri_status tri_ppt_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lin
                          tri_field field, void *d_inout, int P, int periodic,
                          tri_prec prec, tri_info *info);
 
+/* The per-line PPT solve of tri_ppt_solve (TRI_REAL, TRI_F64, coefficients
+ * per line: coef->cs_b0 != 0) that also records the decision of the
+ * diagonal-pivoting local solver (PPT paragraph of Sec. 3.2) at every row,
+ * for callers that check those decisions.  piv: device array of
+ * nb0*nb1*n bytes, caller-owned; line (b0, b1) at (b1*nb0 + b0)*n, row j at
+ * +j: 1 = 1x1 pivot, 2 = first row of a 2x2 pivot, 0 = its second row.
+ * d_inout is overwritten by x exactly as tri_ppt_solve would.  Errors as
+ * tri_ppt_solve; TRI_E_UNSUPPORTED for a shared matrix (cs_b0 == 0, whose
+ * tables hold 1x1 pivots), TRI_E_ARG for a null piv with lines to solve. */
+tri_status tri_ppt_pivots(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines,
+                          double *d_inout, int P, int periodic, unsigned char *piv);
+
 /* One ADI sweep (Sec. 2.2, Sec. 3: one tridiagonal system per direction) over
  * the field u[Nz][Ny][Nx] (x fastest), in place.  dir: TRI_DIR_X (lines of
  * length Nx, rows contiguous), TRI_DIR_Y (length Ny, row stride Nx) or
@@ -314,7 +326,9 @@ tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, 
  * streamwise_dct, poisson_shifted_solve (PPT, P partitions; ay, cy, lamz,
  * lamx the metric of this grid for the result to be divergence free),
  * streamwise_idct, projection3d_correct into phi.  Every argument is checked
- * before the first launch; allocates nothing. */
+ * before the first launch (TRI_E_SHAPE for an odd Nx or a P that does not
+ * split Ny as the solves require; TRI_E_UNSUPPORTED for an Nx that is not
+ * 2^a 3^b 5^c <= 4096 or more than 32 rows a partition); allocates nothing. */
 tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, double dx,
                              const double *dy, double dz, const double *ay, const double *cy,
                              const double *lamz, const double *lamx, double *phihat, double *phi,

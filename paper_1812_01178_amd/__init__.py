@@ -29,7 +29,7 @@ __all__ = [
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
-    "projection3d_correct", "projection3d_step",
+    "projection3d_correct", "projection3d_step", "tri_ppt_pivots",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -51,7 +51,7 @@ EXPORTED = [
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
-    "projection3d_correct", "projection3d_step",
+    "projection3d_correct", "projection3d_step", "tri_ppt_pivots",
 ]
 
 
@@ -113,6 +113,7 @@ def lib():
                                _I, ctypes.POINTER(TriInfo)]),
         "tri_ppt_solve": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _I, _V, _I, _I,
                                _I, ctypes.POINTER(TriInfo)]),
+        "tri_ppt_pivots": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _V, _I, _I, _V]),
         "adi_sweep": (_I, [_V, _I, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I, _I,
                            ctypes.POINTER(TriInfo)]),
         "poisson_wavenumber_solve": (_I, [_V, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I,
@@ -244,6 +245,17 @@ def tri_ppt_solve(ctx, a, b, c, d, lines, coef_strides=(1, 0, 0), complex_field=
                   periodic=False, prec=TRI_F64, info=False):
     return _solve(lib().tri_ppt_solve, "tri_ppt_solve", ctx, a, b, c, d, lines, coef_strides,
                   complex_field, P, periodic, prec, info)
+
+
+def tri_ppt_pivots(ctx, a, b, c, d, lines, coef_strides, piv, P=1, periodic=False) -> None:
+    """Per-line PPT (real, FP64) that also writes every row's pivot kind into
+    the uint8 device tensor piv (nb0*nb1*n bytes; 1, 2 = first row of a 2x2
+    pivot, 0 = its second row)."""
+    coef = TriCoef(_ptr(a), _ptr(b), _ptr(c), *[int(s) for s in coef_strides])
+    ln = _lines(*lines)
+    st = lib().tri_ppt_pivots(ctx, ctypes.byref(coef), ctypes.byref(ln), _ptr(d), int(P), int(bool(periodic)),
+                              _ptr(piv))
+    _check(st, "tri_ppt_pivots", ctx)
 
 
 def adi_sweep(ctx, direction: int, u, a, b, c, P: int, periodic=False, method=TRI_PDD,

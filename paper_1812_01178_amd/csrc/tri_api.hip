@@ -66,6 +66,7 @@ struct Problem {
     // per-line coefficients
     const double *ga = nullptr, *gb = nullptr, *gc = nullptr;
     int64_t cs_j = 0, cs_b0 = 0, cs_b1 = 0;
+    unsigned char *piv = nullptr;   // per-line PPT: pivot kinds out (nullable)
 };
 
 // Kernel choice for a shared-matrix problem.
@@ -583,6 +584,7 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
         g.cs_b1 = pb.cs_b1;
         g.status = ctx->status_dev;
         g.pdd_tol = ctx->pdd_tol;
+        g.piv = pb.piv;
         if (prec == TRI_F32_REFINE) {
             if (m > kGeneralRefineMaxM || pb.P > 8)
                 return fail(ctx, TRI_E_UNSUPPORTED, "TRI_F32_REFINE with per-line coefficients needs m <= %d, P <= 8",
@@ -838,6 +840,19 @@ tri_status tri_ppt_solve(tri_ctx ctx, const tri_coef *coef, const tri_lines *lin
     tri_status st = make_problem(ctx, TRI_PPT, coef, lines, field, d_inout, P, periodic, pb);
     if (st) return st;
     return run_problem(ctx, pb, prec, info);
+}
+
+tri_status tri_ppt_pivots(tri_ctx ctx, const tri_coef *coef, const tri_lines *lines, double *d_inout, int P,
+                          int periodic, unsigned char *piv)
+{
+    if (!ctx) return TRI_E_ARG;
+    Problem pb;
+    tri_status st = make_problem(ctx, TRI_PPT, coef, lines, TRI_REAL, d_inout, P, periodic, pb);
+    if (st) return st;
+    if (!pb.general) return fail(ctx, TRI_E_UNSUPPORTED, "pivot kinds are recorded for per-line coefficients only");
+    if (pb.L.nb0 * pb.L.nb1 > 0 && !piv) return fail(ctx, TRI_E_ARG, "null pivot array");
+    pb.piv = piv;
+    return run_problem(ctx, pb, TRI_F64, nullptr);
 }
 
 tri_status adi_sweep(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t Ny, int64_t Nz,
@@ -1142,11 +1157,14 @@ tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, doubl
     FftShape S, Sx;
     tri_status st = grid_check(ctx, Nx, Ny, Nz, dy, dz, S, "projection3d_step");
     if (st) return st;
-    if (Nx < 2 || (Nx & 1) || !dct_shape(Nx, Sx))
-        return fail(ctx, TRI_E_UNSUPPORTED, "projection3d_step: Nx = %lld is not even 2^a 3^b 5^c <= %d",
+    if (Nx < 2 || (Nx & 1)) return fail(ctx, TRI_E_SHAPE, "projection3d_step: Nx = %lld must be even", (long long)Nx);
+    if (!dct_shape(Nx, Sx))
+        return fail(ctx, TRI_E_UNSUPPORTED, "projection3d_step: Nx = %lld is not 2^a 3^b 5^c <= %d",
                     (long long)Nx, kDctMaxN);
-    const int m = (int)(Ny / std::max(P, 1));
-    if (P < 1 || Ny % P || m > kGeneralMaxM || (m > 16 && P > 8))
+    st = check_partition(ctx, Ny, P, 0);
+    if (st) return st;
+    const int m = (int)(Ny / P);
+    if (m > kGeneralMaxM || (m > 16 && P > 8))
         return fail(ctx, TRI_E_UNSUPPORTED, "projection3d_step: P = %d does not split Ny = %lld into <= 32 rows", P,
                     (long long)Ny);
     if (!ay || !cy || !lamz || !lamx || !phihat || !phi || !u || !v || !w)
@@ -1610,6 +1628,10 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
         const tri_item &it = items[i];
         tri_plan_s::Item &pi = plan->items[(size_t)i];
         int P = it.P;
+        if (it.kind < TRI_ITEM_ADI_X || it.kind > TRI_ITEM_POISSON) {
+            tri_plan_destroy(plan);
+            return fail(ctx, TRI_E_ARG, "item %d: bad kind %d", i, it.kind);
+        }
         tri_status st = P == 0 ? choose_partitions(ctx, it, prec, P) : TRI_OK;
         if (!st) st = item_problem(ctx, it, P, pi.pb);
         if (st) {

@@ -145,6 +145,10 @@ struct GeneralArgs {
     // gauge pinned (row 0 replaced by x_0 = 0).
     const double *lamz = nullptr, *lamx = nullptr;
     double pdd_tol = 0.0;    // > 0: PDD lines with a dropped entry above it set kStatusPddUnsafe
+    // PPT with diagonal pivoting only (nullable): every row's pivot kind, line
+    // (b0, b1) at (b1 nb0 + b0) n: 1 = 1x1 pivot, 2 = first row of a 2x2 pivot,
+    // 0 = its second row
+    unsigned char *piv = nullptr;
 };
 
 // Host launchers (tri_kernels.hip).  All return hipError_t of the launch.

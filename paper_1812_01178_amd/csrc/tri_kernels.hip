@@ -1214,6 +1214,11 @@ __global__ void __launch_bounds__(MAXT) k_general(const GeneralArgs A)
         }
     }
     if (bad && active) atomicOr(A.status, kStatusZeroPivot);
+    if (A.piv && active) {
+        unsigned char *pk = A.piv + (b1 * A.nb0 + b0) * A.n + (int64_t)r * m;
+        for (int t = 0; t < m; ++t)
+            pk[t] = ((two >> t) & 1) ? 2 : ((t > 0 && ((two >> (t - 1)) & 1)) ? 0 : 1);
+    }
     // back substitution of x~, v (a-corner spike) and w (c-corner spike),
     // keeping the values of the two rows below
     double x1 = 0.0, x2 = 0.0, v1 = 0.0, v2 = 0.0, w1 = 0.0, w2 = 0.0;

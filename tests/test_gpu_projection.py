@@ -489,7 +489,8 @@ def test_projection_steps_refuse_before_any_launch(T, ctx):
     assert step3(ptr(ph), ptr(ph)) == T.TRI_E_ARG                 # phi inside phihat
     assert step3(ptr(ph) + 8, ptr(phi)) == T.TRI_E_ARG             # spectrum not 16-byte aligned
     assert step3(ptr(ph), ptr(u)) == T.TRI_E_ARG                   # phi over u
-    assert step3(ptr(ph), ptr(phi), P=3) == T.TRI_E_UNSUPPORTED    # 32 rows do not split in 3
+    assert step3(ptr(ph), ptr(phi), P=3) == T.TRI_E_SHAPE          # 32 rows do not split in 3
+    assert step3(ptr(ph), ptr(phi), Nx=15) == T.TRI_E_SHAPE         # odd
     assert step3(ptr(ph), ptr(phi), Nx=14) == T.TRI_E_UNSUPPORTED  # 7 is not a supported factor
     assert L.projection_step(ctx, ptr(v), ptr(w), ptr(dd[0]), dz, ptr(dd[1]), ptr(dd[2]), ptr(dd[3]), ptr(ph),
                              ptr(ph), nx, ny, nz, 4) == T.TRI_E_ARG

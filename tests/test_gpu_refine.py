@@ -227,9 +227,9 @@ def test_refine_independent_lines_pdd_inner(T, ctx, orc):
 @pytest.mark.parametrize("periodic", [False, True])
 @pytest.mark.parametrize("n,P", [(48, 4), (16, 2), (96, 8)])
 def test_refine_general_per_element(T, ctx, orc, periodic, n, P):
-    """Fully general rows (a, b, c per element), PPT inner solver."""
-    if periodic and P > 4:
-        pytest.skip("per-line periodic PPT takes P <= 4")
+    """Fully general rows (a, b, c per element), PPT inner solver.  Per-line
+    periodic PPT takes P <= 4: at P = 8 the call is refused before any launch
+    and the data is left as it was."""
     nlines = 130
     rng = np.random.default_rng(41 + n)
     A = np.empty((nlines, n)); B = np.empty((nlines, n)); C = np.empty((nlines, n))
@@ -241,6 +241,14 @@ def test_refine_general_per_element(T, ctx, orc, periodic, n, P):
     orc.solve_batch(orc.EXACT_LD, ref, n, nlines, 1, s_j=nlines, s_b0=1, s_b1=0,
                     a=At.ravel(), b=Bt.ravel(), c=Ct.ravel(), cs_j=nlines, cs_b0=1, cs_b1=0, periodic=periodic)
     dd = dev(D)
+    if periodic and P > 4:
+        with pytest.raises(T.TriError) as e:
+            T.tri_ppt_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0),
+                            coef_strides=(nlines, 1, 0), P=P, periodic=periodic, prec=T.TRI_F32_REFINE)
+        assert e.value.status == T.TRI_E_UNSUPPORTED
+        T.tri_sync_status(ctx)
+        assert np.array_equal(host(dd), D)
+        return
     T.tri_ppt_solve(ctx, dev(At), dev(Bt), dev(Ct), dd, (n, nlines, 1, nlines, 1, 0), coef_strides=(nlines, 1, 0),
                     P=P, periodic=periodic, prec=T.TRI_F32_REFINE)
     T.tri_sync_status(ctx)

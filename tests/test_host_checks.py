@@ -126,3 +126,40 @@ def test_spikes_of_dominant_blocks_sum_to_at_most_one():
             assert np.max(s) <= 1.0 + 1e-12
             if sigma == 0.0 and lo + m < 256:
                 assert np.max(s) > 1.0 - 1e-9       # tight: constants solve the homogeneous rows
+
+
+def test_bench_oracle_parity_scores_every_kept_result(orc):
+    """bench.py's CPU-baseline leg compares every kept pristine-input result with
+    the oracle: results equal to the oracle's score 0, and one perturbed entry
+    anywhere in a field shows up in that solve's worst-line error."""
+    bench = _bench()
+    nz, ny, nx = 32, 32, 64
+    rng = np.random.default_rng(8)
+    u0 = rng.standard_normal((nz, ny, nx))
+    phi0 = rng.standard_normal((nz // 2 + 1, ny, nx)) + 1j * rng.standard_normal((nz // 2 + 1, ny, nx))
+    coef = {"x": W.momentum_uniform(nx), "y": W.momentum_stretched(ny), "z": W.momentum_periodic(nz)}
+    ay, cy = W.poisson_metric(ny)
+    lam = W.modified_wavenumbers(nz)
+
+    def results(ld):
+        out = {}
+        for name, d, P, per, _ in bench.ITEMS:
+            if name == "poisson":
+                ref = phi0.copy()
+                orc.poisson(ref, ay, cy, lam, P=P)
+                if ld:
+                    x = phi0.copy()
+                    orc.poisson(x, ay, cy, lam, P=P, method=orc.EXACT_LD)
+                    ref[3:] = x[3:]
+            else:
+                ref = u0.copy()
+                orc.adi_sweep(orc.EXACT_LD if ld else orc.PDD, d, ref, *coef["xyz"[d]], P, per)
+            out[name] = ref
+        return out
+
+    pristine = {"fp64": results(False), "fp32_refine": results(True)}
+    pristine["fp64"]["adi_y"][5, 7, 9] += 1e-9 * np.max(np.abs(pristine["fp64"]["adi_y"]))
+    err = bench.oracle_parity(orc, pristine, u0, phi0, coef, ay, cy, lam)
+    assert err["fp64"]["adi_x"] == 0 and err["fp64"]["adi_z"] == 0 and err["fp64"]["poisson"] == 0
+    assert err["fp64"]["adi_y"] > 1e-10
+    assert max(err["fp32_refine"].values()) == 0
