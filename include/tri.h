@@ -204,6 +204,22 @@ tri_status adi_sweep(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t 
                      int64_t Nz, const double *a, const double *b, const double *c,
                      int P, int periodic, int method, tri_prec prec, tri_info *info);
 
+/* adi_sweep for callers that cannot allocate device memory or wait (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same sweep, kernels and result as adi_sweep without a
+ * tri_info, with the partition factor tables in the library's static device
+ * scratch of TRI_NOALLOC_SCRATCH_BYTES per GPU instead of the context
+ * workspace.  Calls no hipMalloc/hipFree and never synchronises.  A sweep
+ * whose tables do not fit (about 84 bytes per row of the sweep direction,
+ * plus 32 P^2 bytes) returns TRI_E_NOMEM before any launch, data untouched.
+ * Every call on one GPU, from any context or stream, shares that scratch:
+ * calls that overlap in time race on it and must be serialised by the
+ * caller (calls queued on one stream are).  Other errors as adi_sweep. */
+#define TRI_NOALLOC_SCRATCH_BYTES (1u << 20)
+tri_status adi_sweep_noalloc(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t Ny,
+                             int64_t Nz, const double *a, const double *b, const double *c,
+                             int P, int periodic, int method, tri_prec prec);
+
 /* Wall-normal Poisson solves per spanwise wavenumber (Sec. 2.2; PPT
  * paragraph of Sec. 3.2), in place on phihat[Nk][Ny][Nx] complex128
  * (interleaved re, im).  For mode k and every x-station the real matrix is

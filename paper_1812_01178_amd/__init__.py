@@ -29,7 +29,7 @@ __all__ = [
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
-    "projection3d_correct", "projection3d_step", "tri_ppt_pivots",
+    "projection3d_correct", "projection3d_step", "tri_ppt_pivots", "adi_sweep_noalloc",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -42,6 +42,7 @@ TRI_PDD, TRI_PPT = 0, 1
 TRI_DIR_X, TRI_DIR_Y, TRI_DIR_Z = 0, 1, 2
 TRI_ITEM_ADI_X, TRI_ITEM_ADI_Y, TRI_ITEM_ADI_Z, TRI_ITEM_POISSON = 0, 1, 2, 3
 TRI_MAX_PARTITIONS = 16
+TRI_NOALLOC_SCRATCH_BYTES = 1 << 20
 
 # every symbol include/tri.h declares
 EXPORTED = [
@@ -51,7 +52,7 @@ EXPORTED = [
     "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
-    "projection3d_correct", "projection3d_step", "tri_ppt_pivots",
+    "projection3d_correct", "projection3d_step", "tri_ppt_pivots", "adi_sweep_noalloc",
 ]
 
 
@@ -114,6 +115,7 @@ def lib():
         "tri_ppt_solve": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _I, _V, _I, _I,
                                _I, ctypes.POINTER(TriInfo)]),
         "tri_ppt_pivots": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _V, _I, _I, _V]),
+        "adi_sweep_noalloc": (_I, [_V, _I, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I, _I]),
         "adi_sweep": (_I, [_V, _I, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I, _I,
                            ctypes.POINTER(TriInfo)]),
         "poisson_wavenumber_solve": (_I, [_V, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I,
@@ -268,6 +270,16 @@ def adi_sweep(ctx, direction: int, u, a, b, c, P: int, periodic=False, method=TR
                          ctypes.byref(inf) if inf else None)
     _check(st, "adi_sweep", ctx)
     return _info_dict(inf)
+
+
+def adi_sweep_noalloc(ctx, direction: int, u, a, b, c, P: int, periodic=False, method=TRI_PDD,
+                      prec=TRI_F64, shape=None) -> None:
+    """adi_sweep with the factor tables in the library's static device scratch:
+    no allocation, no synchronisation (calls on one GPU must not overlap)."""
+    Nz, Ny, Nx = shape if shape is not None else tuple(u.shape)
+    st = lib().adi_sweep_noalloc(ctx, int(direction), _ptr(u), Nx, Ny, Nz, _ptr(a), _ptr(b), _ptr(c), int(P),
+                                 int(bool(periodic)), int(method), int(prec))
+    _check(st, "adi_sweep_noalloc", ctx)
 
 
 def poisson_wavenumber_solve(ctx, phihat, ay, cy, lam, P: int = 4, prec=TRI_F64,

@@ -28,6 +28,7 @@ struct tri_ctx_s {
     void *ws = nullptr;
     size_t ws_bytes = 0;
     double pdd_tol = 0.0;                 // strict PDD: > 0 reports dropped entries above it
+    void *scratch = nullptr;              // this device's static scratch (adi_sweep_noalloc)
     std::string last_error;
 };
 
@@ -545,8 +546,10 @@ tri_status fill_info(tri_ctx ctx, const Tables *T, tri_info *info, bool refined 
     return TRI_OK;
 }
 
-// Run one validated problem through the context workspace.
-tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *info)
+// Run one validated problem through the context workspace, or, when `tables`
+// is given, with the factor tables in that memory of `tables_cap` bytes.
+tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *info, void *tables = nullptr,
+                       size_t tables_cap = 0)
 {
     if (prec != TRI_F64 && prec != TRI_F32_REFINE) return fail(ctx, TRI_E_ARG, "bad precision %d", (int)prec);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
@@ -598,9 +601,13 @@ tri_status run_problem(tri_ctx ctx, const Problem &pb, tri_prec prec, tri_info *
         HIP_TRY(ctx, launch_general(g, pb.method, ctx->stream));
         return fill_info(ctx, nullptr, info);
     }
-    tri_status st = need_ws(ctx, tables_bytes(pb.G, pb.L.n, pb.P));
+    const size_t tb = tables_bytes(pb.G, pb.L.n, pb.P);
+    tri_status st = TRI_OK;
+    if (tables && tb > tables_cap)
+        return fail(ctx, TRI_E_NOMEM, "the factor tables need %zu bytes, the static scratch holds %zu", tb, tables_cap);
+    if (!tables) st = need_ws(ctx, tb);
     if (st) return st;
-    Tables T = carve_tables(ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+    Tables T = carve_tables(tables ? tables : ctx->ws, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
     T.pdd_tol = prec == TRI_F32_REFINE ? 0.0 : ctx->pdd_tol;   // refinement reaches A^-1 d
     std::vector<Launch> ls;
     st = build_launches(ctx, pb, T, prec, ls);
@@ -693,6 +700,39 @@ tri_status poisson_problem(tri_ctx ctx, double *phihat, int64_t Nx, int64_t Ny, 
     return TRI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of adi_sweep_noalloc: the factor tables of one call live in
+// this file-scope device array instead of the context workspace, so that the
+// call allocates nothing.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in, not a device address):
+// tri_create looks up the device address once per device with
+// hipGetSymbolAddress, with that device current, and every use goes through
+// that address.  Calls on one GPU share the array: calls that overlap in time
+// (other streams or contexts) race on it.  The factor kernel writes every
+// table entry a solve reads, so nothing needs clearing between calls.
+constexpr size_t kNoallocScratchBytes = TRI_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxScratchDevices] = {};
+
+// The device address of this device's scratch (the device must be current);
+// nullptr for device ordinals beyond the table.
+tri_status bind_scratch(int device, void **out)
+{
+    *out = nullptr;
+    if (device >= kMaxScratchDevices) return TRI_OK;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return TRI_E_HIP;
+        g_scratch_dev[device] = p;
+    }
+    *out = g_scratch_dev[device];
+    return TRI_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -726,9 +766,12 @@ tri_status tri_create(tri_ctx *out, int device, void *hip_stream)
     if (hipGetDeviceCount(&count) != hipSuccess || count == 0) return TRI_E_HIP;
     if (device < 0 || device >= count) return TRI_E_ARG;
     if (hipSetDevice(device) != hipSuccess) return TRI_E_HIP;
+    void *scr = nullptr;
+    if (bind_scratch(device, &scr) != TRI_OK) return TRI_E_HIP;
     tri_ctx ctx = new (std::nothrow) tri_ctx_s;
     if (!ctx) return TRI_E_NOMEM;
     ctx->device = device;
+    ctx->scratch = scr;
     ctx->stream = (hipStream_t)hip_stream;
     void *words = nullptr;
     if (hipMalloc(&words, 64) != hipSuccess) {
@@ -864,6 +907,19 @@ tri_status adi_sweep(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t 
     tri_status st = adi_problem(ctx, dir, u_inout, Nx, Ny, Nz, a, b, c, P, periodic, method, pb);
     if (st) return st;
     return run_problem(ctx, pb, prec, info);
+}
+
+tri_status adi_sweep_noalloc(tri_ctx ctx, int dir, double *u_inout, int64_t Nx, int64_t Ny, int64_t Nz,
+                             const double *a, const double *b, const double *c, int P, int periodic, int method,
+                             tri_prec prec)
+{
+    if (!ctx) return TRI_E_ARG;
+    Problem pb;
+    tri_status st = adi_problem(ctx, dir, u_inout, Nx, Ny, Nz, a, b, c, P, periodic, method, pb);
+    if (st) return st;
+    if (!ctx->scratch)
+        return fail(ctx, TRI_E_UNSUPPORTED, "adi_sweep_noalloc: no static scratch on device %d", ctx->device);
+    return run_problem(ctx, pb, prec, nullptr, ctx->scratch, kNoallocScratchBytes);
 }
 
 tri_status poisson_wavenumber_solve(tri_ctx ctx, double *phihat_inout, int64_t Nx, int64_t Ny,
@@ -1751,3 +1807,4 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
 }
 
 }  // extern "C"
+

@@ -102,6 +102,31 @@ int main()
         CHECK(g_mallocs == m0 && g_frees == f0 && g_syncs == s0);
     }
 
+    // ---- the allocation-free sweep: static scratch, looked up once per device
+    {
+        CHECK(g_symbol_lookups == 1);
+        tri_ctx ctx2 = nullptr;
+        CHECK(tri_create(&ctx2, 0, nullptr) == TRI_OK);
+        CHECK(g_symbol_lookups == 1);                      // already bound for device 0
+        CHECK(tri_destroy(ctx2) == TRI_OK);
+        const int l0 = g_launches, m0 = g_mallocs, f0 = g_frees, s0 = g_syncs;
+        for (int d = 0; d < 3; ++d) {
+            const double *A = d == 0 ? ax.data() : (d == 1 ? ay.data() : az.data());
+            const double *B = d == 0 ? bx.data() : (d == 1 ? by.data() : bz.data());
+            const double *Cc = d == 0 ? cx.data() : (d == 1 ? cy.data() : cz.data());
+            CHECK(adi_sweep_noalloc(ctx, d, u.data(), Nx, Ny, Nz, A, B, Cc, 4, d == 2, TRI_PDD, TRI_F64) == TRI_OK);
+        }
+        CHECK(g_launches > l0 && g_mallocs == m0 && g_frees == f0 && g_syncs == s0);
+        // 16384 rows: about 1.4 MB of tables, beyond the 1 MiB scratch
+        std::vector<double> big(16384, 1.0), ab(16384, -0.1), bb(16384, 1.2), cb(16384, -0.1);
+        REFUSED(adi_sweep_noalloc(ctx, 0, big.data(), 16384, 1, 1, ab.data(), bb.data(), cb.data(), 8, 0, TRI_PDD,
+                                  TRI_F64), TRI_E_NOMEM, big);
+        REFUSED(adi_sweep_noalloc(nullptr, 0, big.data(), 16384, 1, 1, ab.data(), bb.data(), cb.data(), 8, 0,
+                                  TRI_PDD, TRI_F64), TRI_E_ARG, big);
+        REFUSED(adi_sweep_noalloc(ctx, 0, big.data(), 16384, 1, 1, ab.data(), bb.data(), cb.data(), 3, 0, TRI_PDD,
+                                  TRI_F64), TRI_E_SHAPE, big);
+    }
+
     // ---- workspace: a call whose tables do not fit is refused, tri_reserve grows it
     {
         const int64_t Nk = 200000;   // 200000 matrices of 32 rows: beyond the 64 MiB workspace
