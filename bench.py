@@ -261,10 +261,10 @@ def main():
         "copy_ceiling": copy,
         "residual_max_line": residual,
         "oracle_err_max_line": oracle_err,
-        "oracle_err_def": ("per line max_j |x - x_oracle| / max_j |x_oracle| on the pristine input, worst line; "
-                           "FP64 PDD/PPT against the oracle's PDD/PPT at the same P, FP32+refine against the "
-                           "oracle's extended-precision exact solve (Poisson modes k <= 2 against its PPT); "
-                           "ragged: per sub-grid, the composed x -> y -> z step and the Poisson solves"),
+        "oracle_err_def": ("per line max_j |x - x_oracle| / max_j |x_oracle| on the pristine input, worst line, "
+                           "against the FP64 oracle: PDD/PPT at the FP64 run's P (PDD exact to round-off there), "
+                           "the same solve for FP32+refine; ragged: per sub-grid, the composed x -> y -> z step "
+                           "and the Poisson solves"),
         "fp32_refine": refine,
         "ragged_batch": ragged,
         "pressure_step": pressure,
@@ -303,53 +303,49 @@ def line_relerr(got, ref, axis):
 
 
 def oracle_parity(oracle, pristine, u0, phi0, coef, ay, cy, lam):
-    """Every result kept from a pristine-input run against the oracle, line by
-    line (the CPU-baseline leg; nothing here is timed).  FP64 PDD/PPT against
-    the oracle at the same P; FP32+refine against the extended-precision exact
-    solve, Poisson modes k <= 2 (kept FP64) against the oracle's PPT."""
+    """Every result kept from a pristine-input run against the FP64 oracle, line
+    by line (the CPU-baseline leg; nothing here is timed).  FP64 PDD/PPT against
+    the oracle at the same P.  FP32+refine converges to A^-1 d, so it is held to
+    the same oracle solve: PDD at the benchmark's P drops entries below 1e-15
+    (1e-21 for the spanwise lines), so the oracle's PDD is the exact solution to
+    round-off, and the Poisson reference is the oracle's PPT (exact)."""
     t0 = time.perf_counter()
     err = {}
-    LD = oracle.EXACT_LD
-
-    def adi_ref(d, P, method, u_in=u0, cf=coef):
-        ref = np.array(u_in, copy=True)
-        oracle.adi_sweep(method, d, ref, *cf["xyz"[d]], P, d == 2)
-        return ref
-
-    def poisson_ref(refine, P, p_in=phi0, a_=ay, c_=cy, l_=lam):
-        ref = np.array(p_in, copy=True)
-        oracle.poisson(ref, a_, c_, l_, P=P)
-        if refine:
-            ld = np.array(p_in, copy=True)
-            oracle.poisson(ld, a_, c_, l_, P=P, method=LD)
-            ref[3:] = ld[3:]
-        return ref
-
+    for name, d, P, per, meth in ITEMS:
+        if name == "poisson":
+            ref = np.array(phi0, copy=True)
+            oracle.poisson(ref, ay, cy, lam, P=P)
+            axis = 1
+        else:
+            ref = np.array(u0, copy=True)
+            oracle.adi_sweep(oracle.PDD, d, ref, *coef["xyz"[d]], P, per)
+            axis = 2 - d
+        for prec in ("fp64", "fp32_refine"):
+            if prec in pristine:
+                e = line_relerr(pristine[prec].pop(name), ref, axis)
+                err.setdefault(prec, {})[name] = e
+                log(f"oracle parity {prec} {name}: worst line {e:.2e}")
+        del ref
     for prec in ("fp64", "fp32_refine"):
-        if prec not in pristine:
-            continue
-        e = {}
-        for name, d, P, per, meth in ITEMS:
-            got = pristine[prec][name]
-            if name == "poisson":
-                e[name] = line_relerr(got, poisson_ref(prec != "fp64", P), 1)
-            else:
-                e[name] = line_relerr(got, adi_ref(d, P, oracle.PDD if prec == "fp64" else LD), 2 - d)
-            log(f"oracle parity {prec} {name}: worst line {e[name]:.2e}")
-        err[prec] = e
-        del pristine[prec]
+        pristine.pop(prec, None)
+    refs = {}
     for prec in ("fp64", "fp32_refine"):
         key = "ragged_" + prec
         if key not in pristine:
             continue
         worst_adi = worst_poi = 0.0
-        for g in pristine.pop(key):
-            cf = dict(zip("xyz", g["coef"]))
-            ref = np.array(g["u0"], copy=True)
-            for d in range(3):
-                oracle.adi_sweep(oracle.PDD if prec == "fp64" else LD, d, ref, *cf["xyz"[d]], g["P"][d], d == 2)
+        for s_, g in enumerate(pristine.pop(key)):
+            if s_ not in refs:
+                # the FP64 plan's partition counts (PDD admitted only where it is exact to round-off)
+                cf = dict(zip("xyz", g["coef"]))
+                ref = np.array(g["u0"], copy=True)
+                for d in range(3):
+                    oracle.adi_sweep(oracle.PDD, d, ref, *cf["xyz"[d]], g["P"][d], d == 2)
+                pref = np.array(g["phi0"], copy=True)
+                oracle.poisson(pref, *g["metric"], g["lam"], P=g["P"][3])
+                refs[s_] = (ref, pref)
+            ref, pref = refs[s_]
             worst_adi = max(worst_adi, line_relerr(g["u"], ref, 0))
-            pref = poisson_ref(prec != "fp64", g["P"][3], g["phi0"], *g["metric"], g["lam"])
             worst_poi = max(worst_poi, line_relerr(g["phi"], pref, 1))
         err[key] = {"adi_step": worst_adi, "poisson": worst_poi}
         log(f"oracle parity ragged {prec}: ADI step {worst_adi:.2e}, Poisson {worst_poi:.2e}")
@@ -358,7 +354,7 @@ def oracle_parity(oracle, pristine, u0, phi0, coef, ay, cy, lam):
         r, d, P = ind["r"], ind["d"], ind["P"]
         n, nlines = d.shape
         e = {}
-        for name, method in (("pdd_fp64", oracle.PDD), ("ppt_fp64", oracle.PPT), ("ppt_fp32_refine", LD)):
+        for name, method in (("pdd_fp64", oracle.PDD), ("ppt_fp64", oracle.PPT), ("ppt_fp32_refine", oracle.PPT)):
             if name not in ind:
                 continue
             ref = np.array(d, copy=True).ravel()
@@ -990,21 +986,21 @@ def cpu_baseline(oracle, u0, phi0, coef, ay, cy, lam, target_s):
         t_item, n_item = {}, {}
         # x lines: sample z-planes
         qz = max(1, int(round(1 / frac_outer)))
-        sub = np.ascontiguousarray(u0[::qz])
+        sub = np.array(u0[::qz], copy=True, order="C")     # the inputs stay pristine
         t0 = time.perf_counter()
         oracle.adi_sweep(oracle.PDD, 0, sub, *coef["x"], ITEMS[0][2], False, nthreads=threads)
         t_item["adi_x"], n_item["adi_x"] = time.perf_counter() - t0, sub.size
-        sub = np.ascontiguousarray(u0[::qz])
+        sub = np.array(u0[::qz], copy=True, order="C")
         t0 = time.perf_counter()
         oracle.adi_sweep(oracle.PDD, 1, sub, *coef["y"], ITEMS[1][2], False, nthreads=threads)
         t_item["adi_y"], n_item["adi_y"] = time.perf_counter() - t0, sub.size
         qy = max(1, int(round(1 / frac_outer)))
-        sub = np.ascontiguousarray(u0[:, ::qy])
+        sub = np.array(u0[:, ::qy], copy=True, order="C")
         t0 = time.perf_counter()
         oracle.adi_sweep(oracle.PDD, 2, sub, *coef["z"], ITEMS[2][2], True, nthreads=threads)
         t_item["adi_z"], n_item["adi_z"] = time.perf_counter() - t0, sub.size
         qk = max(1, int(round(1 / frac_outer)))
-        sub = np.ascontiguousarray(phi0[::qk])
+        sub = np.array(phi0[::qk], copy=True, order="C")
         t0 = time.perf_counter()
         oracle.poisson(sub, ay, cy, lam[::qk], P=ITEMS[3][2], nthreads=threads)
         t_item["poisson"], n_item["poisson"] = time.perf_counter() - t0, sub.size
