@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged eight-sub-grid batch")
     ap.add_argument("--no-independent", action="store_true", help="skip the independent-systems section")
     ap.add_argument("--no-pressure", action="store_true", help="skip the pressure-step (projection) section")
+    ap.add_argument("--no-ns", action="store_true", help="skip the fractional-step time step section")
     ap.add_argument("--nx", type=int, default=NX)
     ap.add_argument("--ny", type=int, default=NY)
     ap.add_argument("--nz", type=int, default=NZ)
@@ -207,6 +208,11 @@ def main():
         pressure = pressure_section(T, ctx, stream, args, nx, ny, nz, copy["GB_s"])
         pressure["three_d"] = pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy["GB_s"])
 
+    # ---------------- the whole fractional-step time step -----------------
+    fractional = None
+    if not args.no_ns:
+        fractional = fractional_step_section(T, ctx, stream, args, nx, ny, nz)
+
     # ---------------- independent systems with their own coefficients -----
     independent = None
     if not args.no_independent:
@@ -268,6 +274,7 @@ def main():
         "fp32_refine": refine,
         "ragged_batch": ragged,
         "pressure_step": pressure,
+        "fractional_step": fractional,
         "independent_systems": independent,
         "cpu_baseline": cpu,
     }
@@ -776,6 +783,78 @@ def pressure3d_section(T, ctx, stream, args, nx, ny, nz, copy_gbs):
            "divergence_before": div0, "divergence_after": div1, "divergence_ratio": div1 / div0}
     log(f"pressure 3-D step: {ms_step:.3f} ms, {out['GB_s']:.0f} GB/s over the step")
     del u, v, w, ph, phi
+    torch.cuda.empty_cache()
+    return out
+
+
+# Table 1 of the paper (4 Tesla P100, FP64): wall-clock seconds per time step
+# (three sub-steps) for two of its grids, as context only
+PAPER_TABLE1 = [{"grid": [1024, 256, 512], "s_per_step": 2.60, "hardware": "4x Tesla P100"},
+                {"grid": [2048, 256, 1024], "s_per_step": 7.74, "hardware": "4x Tesla P100"}]
+
+
+def fractional_step_section(T, ctx, stream, args, nx, ny, nz):
+    """The whole fractional-step time step (ns_step: three Runge-Kutta sub-steps,
+    each the momentum right-hand side, nine PDD sweeps (x, y, z of u, v, w at
+    P = 8, 4, 16), the velocity update, the 3-D projection with PPT shifted
+    solves at P = 8, the pressure update) on the benchmark grid, dt = 1e-3,
+    nu = 1e-3, from a random state (N(0,1)/10 from torch's device generator,
+    seed 4, wall faces zero).  Checked before timing: one step leaves the
+    velocity divergence free to round-off.  The oracle parity of the step is in
+    the GPU tests (grids up to 256 x 64 x 48)."""
+    import torch
+    import workloads as W
+    dx, dz = 1.0 / nx, 1.0 / nz
+    dy = np.diff(W.tanh_faces(ny))
+    ddy = torch.as_tensor(dy).cuda()
+    g = torch.Generator(device="cuda").manual_seed(4)
+    u = 0.1 * torch.randn((nz, ny, nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u[:, :, 0] = 0.0
+    u[:, :, nx] = 0.0
+    v = 0.1 * torch.randn((nz, ny + 1, nx), dtype=torch.float64, device="cuda", generator=g)
+    v[:, 0, :] = 0.0
+    v[:, ny, :] = 0.0
+    w = 0.1 * torch.randn((nz, ny, nx), dtype=torch.float64, device="cuda", generator=g)
+    p = torch.zeros((nz, ny, nx), dtype=torch.float64, device="cuda")
+
+    def div():
+        return ((u[:, :, 1:] - u[:, :, :-1]) / dx + (v[:, 1:, :] - v[:, :-1, :]) / ddy[None, :, None]
+                + (torch.roll(w, -1, 0) - w) / dz).abs().max().item()
+    P_adi, P_poi = (8, 4, 16), 8
+    t0 = time.perf_counter()
+    ns = T.ns_create(ctx, nx, ny, nz, dx, dz, dy, 1e-3, 1e-3, P_adi, P_poi)
+    create_s = time.perf_counter() - t0
+    try:
+        d0 = div()
+        T.ns_step(ns, u, v, w, p, ctx)
+        T.tri_sync_status(ctx)
+        d1 = div()
+        log(f"fractional step: max |div| {d0:.3e} -> {d1:.3e} ({d1 / d0:.1e})")
+        for _ in range(args.warmup):
+            T.ns_step(ns, u, v, w, p, ctx)
+        torch.cuda.synchronize()
+        steps = max(3, args.steps // 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            T.ns_step(ns, u, v, w, p, ctx)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        T.tri_sync_status(ctx)
+        ms = e0.elapsed_time(e1) / steps
+        finite = bool(torch.isfinite(u).all() and torch.isfinite(v).all() and torch.isfinite(w).all())
+    finally:
+        T.ns_destroy(ns)
+    cells = nx * ny * nz
+    out = {"grid": [nx, ny, nz], "P_adi": list(P_adi), "P_poisson": P_poi, "dt": 1e-3, "nu": 1e-3,
+           "ms_per_step": round(ms, 3), "steps": steps, "cells_per_s": cells / (ms * 1e-3),
+           "plan_create_s": round(create_s, 2), "divergence_before": d0, "divergence_after_first_step": d1,
+           "divergence_ratio": d1 / d0, "finite": finite,
+           "paper_table1_context": [dict(r, cells_per_s=r["grid"][0] * r["grid"][1] * r["grid"][2] / r["s_per_step"])
+                                    for r in PAPER_TABLE1]}
+    log(f"fractional step: {ms:.2f} ms per time step (3 sub-steps), {cells / (ms * 1e-3) / 1e9:.2f} G cells/s; "
+        f"Table 1 context: 1024x256x512 in 2.60 s, 2048x256x1024 in 7.74 s on 4 P100")
+    del u, v, w, p
     torch.cuda.empty_cache()
     return out
 

@@ -350,6 +350,42 @@ tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, doubl
                              const double *lamz, const double *lamx, double *phihat, double *phi,
                              int64_t Nx, int64_t Ny, int64_t Nz, int P);
 
+/* ---- the fractional-step time step (Sec. 2.1-2.2) -------------------------
+ *
+ * One time step of the semi-implicit fractional-step method on the staggered
+ * grid of the 3-D pressure step (u[Nz][Ny][Nx+1] on x-faces, v[Nz][Ny+1][Nx]
+ * on y-faces, w[Nz][Ny][Nx] on z-faces, p[Nz][Ny][Nx] at cells; walls at both
+ * x-ends and at y = 0, the top at y = Ny, z periodic): three sub-steps of the
+ * low-storage third-order Runge-Kutta scheme (gamma = 8/15, 5/12, 3/4,
+ * zeta = 0, -17/60, -5/12, alpha = gamma + zeta) for the convection terms
+ * -d(u_i u_j)/dx_j (second-order central differences), Crank-Nicolson for the
+ * viscous terms nu L u, approximately factored into x, y, z tridiagonal sweeps
+ * of every velocity component (PDD, the paper's ADI), the previous pressure in
+ * the predictor, the 3-D projection (projection3d_step, PPT shifted solves)
+ * and the pressure update p += phi / (alpha dt).  Tangential components:
+ * no-slip at y = 0, stress-free at the top, slip at the x-ends.  The wall faces
+ * (u at i = 0, Nx; v at j = 0, Ny) must hold 0 and are left as they are. */
+typedef struct tri_ns_s *tri_ns;
+typedef struct {
+    int64_t Nx, Ny, Nz;      /* cells                                               */
+    double dx, dz;           /* uniform spacings                                    */
+    const double *dy;        /* HOST array of Ny cell widths (read at ns_create)     */
+    double dt, nu;           /* time step, kinematic viscosity (1/Re)               */
+    int P_adi[3];            /* PDD partitions of the x, y, z sweeps                */
+    int P_poisson;           /* PPT partitions of the shifted wall-normal solves    */
+} tri_ns_config;
+/* Set-up: validate the grid (Nx even and 2^a 3^b 5^c <= 4096, Nz even with
+ * Nz/2 = 2^a 3^b 5^c <= 512, P_poisson splitting Ny into <= 32 rows, P_adi as
+ * the sweeps require), allocate the metric, sweep coefficients and work fields
+ * (7 fields of Nx Ny Nz doubles and one spectrum) and create one sweep plan
+ * per sub-step (factors computed here).  Synchronises the context stream. */
+tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out);
+/* One time step, in place on the caller's device fields u, v, w, p (disjoint,
+ * 8-byte aligned); asynchronous on the context stream, allocates nothing.
+ * Zero pivots and PDD checks are reported by tri_sync_status. */
+tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p);
+tri_status ns_destroy(tri_ns ns);
+
 /* ---- plans: factor once, execute many times, capture as a HIP graph ------ */
 
 typedef enum { TRI_ITEM_ADI_X = 0, TRI_ITEM_ADI_Y = 1, TRI_ITEM_ADI_Z = 2,

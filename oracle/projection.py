@@ -115,12 +115,12 @@ def correct3d(phihat: np.ndarray, u: np.ndarray, v: np.ndarray, w: np.ndarray, d
 def project3d(u: np.ndarray, v: np.ndarray, w: np.ndarray, dx: float, dy: np.ndarray, dz: float,
               P: int = 8, method: int = PPT):
     """Return (u_new, v_new, w_new, phi) with div(u_new, v_new, w_new) = 0 to round-off."""
-    from . import poisson_shifted
+    from . import poisson_shifted_batch
     Nz, Ny, Nx = w.shape
     ay, cy, lamz = metric(dy, Nz, dz)
     lamx = metric_x(Nx, dx)
     Dhat = streamwise_dct(spanwise_rfft(divergence3d(u, v, w, dx, dy, dz)))
-    poisson_shifted(Dhat, ay, cy, lamz, lamx, P, method)
+    poisson_shifted_batch(Dhat, ay, cy, lamz, lamx, P, method)
     return correct3d(streamwise_idct(Dhat), u, v, w, dx, dy, dz)
 
 

@@ -30,6 +30,7 @@ __all__ = [
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
     "projection3d_correct", "projection3d_step", "tri_ppt_pivots", "adi_sweep_noalloc",
+    "TriNsConfig", "ns_create", "ns_step", "ns_destroy",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtri.so")
@@ -53,6 +54,7 @@ EXPORTED = [
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
     "projection3d_correct", "projection3d_step", "tri_ppt_pivots", "adi_sweep_noalloc",
+    "ns_create", "ns_step", "ns_destroy",
 ]
 
 
@@ -87,6 +89,13 @@ class TriItem(ctypes.Structure):
                 ("method", ctypes.c_int)]
 
 
+class TriNsConfig(ctypes.Structure):
+    _fields_ = [("Nx", ctypes.c_int64), ("Ny", ctypes.c_int64), ("Nz", ctypes.c_int64),
+                ("dx", ctypes.c_double), ("dz", ctypes.c_double), ("dy", ctypes.POINTER(ctypes.c_double)),
+                ("dt", ctypes.c_double), ("nu", ctypes.c_double), ("P_adi", ctypes.c_int * 3),
+                ("P_poisson", ctypes.c_int)]
+
+
 _lib = None
 _V = ctypes.c_void_p
 _I = ctypes.c_int
@@ -115,6 +124,9 @@ def lib():
         "tri_ppt_solve": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _I, _V, _I, _I,
                                _I, ctypes.POINTER(TriInfo)]),
         "tri_ppt_pivots": (_I, [_V, ctypes.POINTER(TriCoef), ctypes.POINTER(TriLines), _V, _I, _I, _V]),
+        "ns_create": (_I, [_V, ctypes.POINTER(TriNsConfig), ctypes.POINTER(_V)]),
+        "ns_step": (_I, [_V, _V, _V, _V, _V]),
+        "ns_destroy": (_I, [_V]),
         "adi_sweep_noalloc": (_I, [_V, _I, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I, _I]),
         "adi_sweep": (_I, [_V, _I, _V, _I64, _I64, _I64, _V, _V, _V, _I, _I, _I, _I,
                            ctypes.POINTER(TriInfo)]),
@@ -280,6 +292,29 @@ def adi_sweep_noalloc(ctx, direction: int, u, a, b, c, P: int, periodic=False, m
     st = lib().adi_sweep_noalloc(ctx, int(direction), _ptr(u), Nx, Ny, Nz, _ptr(a), _ptr(b), _ptr(c), int(P),
                                  int(bool(periodic)), int(method), int(prec))
     _check(st, "adi_sweep_noalloc", ctx)
+
+
+def ns_create(ctx, Nx: int, Ny: int, Nz: int, dx: float, dz: float, dy, dt: float, nu: float,
+              P_adi=(8, 4, 16), P_poisson: int = 8):
+    """Set up the fractional-step time step on an Nx x Ny x Nz grid; dy is a host
+    (numpy) array of Ny cell widths.  Returns an opaque handle."""
+    import numpy as np
+    dyh = np.ascontiguousarray(dy, dtype=np.float64)
+    cfg = TriNsConfig(int(Nx), int(Ny), int(Nz), float(dx), float(dz),
+                      dyh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(dt), float(nu),
+                      (ctypes.c_int * 3)(*[int(p) for p in P_adi]), int(P_poisson))
+    h = _V()
+    _check(lib().ns_create(ctx, ctypes.byref(cfg), ctypes.byref(h)), "ns_create", ctx)
+    return h
+
+
+def ns_step(ns, u, v, w, p, ctx=None) -> None:
+    """One time step in place on u[Nz][Ny][Nx+1], v[Nz][Ny+1][Nx], w[Nz][Ny][Nx], p[Nz][Ny][Nx]."""
+    _check(lib().ns_step(ns, _ptr(u), _ptr(v), _ptr(w), _ptr(p)), "ns_step", ctx)
+
+
+def ns_destroy(ns) -> None:
+    _check(lib().ns_destroy(ns), "ns_destroy")
 
 
 def poisson_wavenumber_solve(ctx, phihat, ay, cy, lam, P: int = 4, prec=TRI_F64,

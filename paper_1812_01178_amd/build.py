@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libtri.so")
 SOURCES = ["tri_api.hip", "tri_kernels.hip", "tri_contig_reg.hip", "tri_refine.hip", "tri_contig_refine.hip",
-           "tri_general_refine.hip", "tri_copy.hip", "tri_fft.hip"]
+           "tri_general_refine.hip", "tri_copy.hip", "tri_fft.hip", "tri_ns.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

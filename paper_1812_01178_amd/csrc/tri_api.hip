@@ -1507,8 +1507,50 @@ double max_drop(const Tables &T)
 // factored and timed on scratch memory; PDD candidates whose dropped
 // reduced-system entries exceed kPddSafeDrop are skipped (P = 1 is plain
 // Thomas and always exact).  Returns the fastest admissible P.
+// Key of an item's partition-count choice in the tuning table (the choice
+// depends on the item's kind, shape, method and precision; for PDD also on
+// the coefficients, which is why a listed PDD choice is re-checked).
+std::string partition_key(const tri_item &it, tri_prec prec)
+{
+    char buf[160];
+    snprintf(buf, sizeof buf, "partitions k%d m%d per%d prec%d Nx%lld Ny%lld Nz%lld", it.kind, it.method,
+             it.periodic, (int)prec, (long long)it.Nx, (long long)it.Ny, (long long)it.Nz);
+    return buf;
+}
+
+// The PDD admission rule for one partition count: the dropped reduced-system
+// entries of the item's matrices are <= kPddSafeDrop (PPT and P = 1 always pass).
+bool partitions_admissible(tri_ctx ctx, const Problem &pb)
+{
+    if (pb.method != TRI_PDD || pb.P == 1) return true;
+    void *mem = nullptr;
+    if (hipMalloc(&mem, tables_bytes(pb.G, pb.L.n, pb.P)) != hipSuccess) return false;
+    Tables T = carve_tables(mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+    const bool ok = launch_factor(pb.src, T, ctx->status_dev, ctx->stream) == hipSuccess &&
+                    hipStreamSynchronize(ctx->stream) == hipSuccess && max_drop(T) <= kPddSafeDrop;
+    (void)hipFree(mem);
+    return ok;
+}
+
 tri_status choose_partitions(tri_ctx ctx, const tri_item &it, tri_prec prec, int &P_out)
 {
+    // a choice listed in the tuning table (or the cache file) is taken as it is,
+    // after the PDD admission check for these coefficients
+    const std::string pkey = partition_key(it, prec);
+    int listed = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_load();
+        auto f = g_tune_cache.find(pkey);
+        if (f != g_tune_cache.end()) listed = f->second;
+    }
+    if (listed > 0) {
+        Problem pb;
+        if (item_problem(ctx, it, listed, pb) == TRI_OK && partitions_admissible(ctx, pb)) {
+            P_out = listed;
+            return TRI_OK;
+        }
+    }
     int best = 0;
     float best_ms = 1e30f;
     for (int P : {1, 2, 4, 8, 16}) {
@@ -1531,6 +1573,10 @@ tri_status choose_partitions(tri_ctx ctx, const tri_item &it, tri_prec prec, int
         }
     }
     if (best == 0) return fail(ctx, TRI_E_UNSUPPORTED, "no admissible partition count for item kind %d", it.kind);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_cache_store(pkey, best);
+    }
     P_out = best;
     return TRI_OK;
 }
@@ -1808,3 +1854,284 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
 
 }  // extern "C"
 
+// ============================================================================
+// Fractional-step time step (Sec. 2.2): three Runge-Kutta sub-steps, each the
+// momentum right-hand side, ADI sweeps x -> y -> z of the three velocity
+// components (one plan per sub-step), the velocity update, the 3-D projection
+// and the pressure update.
+// ============================================================================
+struct tri_ns_s {
+    tri_ctx ctx = nullptr;
+    int64_t Nx = 0, Ny = 0, Nz = 0;
+    double dx = 0.0, dz = 0.0, dt = 0.0, nu = 0.0;
+    int P_poisson = 8;
+    void *mem = nullptr;                  // metric, sweep coefficients and work fields, one allocation
+    double *dy = nullptr, *ay = nullptr, *cy = nullptr, *lamz = nullptr, *lamx = nullptr;
+    double *N[3] = {}, *D[3] = {};        // convection of the last sub-step; sweep right-hand sides
+    double *phihat = nullptr, *phi = nullptr;
+    tri_plan plans[3] = {};
+};
+
+namespace {
+
+constexpr double kRkGamma[3] = {8.0 / 15.0, 5.0 / 12.0, 3.0 / 4.0};
+constexpr double kRkZeta[3] = {0.0, -17.0 / 60.0, -5.0 / 12.0};
+
+enum { kLapFaceX = 0, kLapCellSlipX = 1, kLapCellWallY = 2, kLapFaceY = 3, kLapPeriodic = 4 };
+
+// Second difference along one sweep line, row t: lo_t q_{t-1} + diag_t q_t +
+// up_t q_{t+1}.  kLapFaceX: u on x-faces 0..n-1 with walls at faces 0 and n
+// (row 0 empty); kLapCellSlipX: cells with zero flux through both ends;
+// kLapCellWallY: cells with the no-slip wall below cell 0 (mirror value -q at
+// distance dy_0) and zero flux through the top; kLapFaceY: v on y-faces
+// 0..n-1 with walls at faces 0 and n (row 0 empty); kLapPeriodic: uniform,
+// periodic.
+void ns_lap_rows(int kind, int64_t n, double h, const std::vector<double> &dy, std::vector<double> &lo,
+                 std::vector<double> &diag, std::vector<double> &up)
+{
+    lo.assign((size_t)n, 0.0);
+    diag.assign((size_t)n, 0.0);
+    up.assign((size_t)n, 0.0);
+    const double ih2 = 1.0 / (h * h);
+    for (int64_t t = 0; t < n; ++t) {
+        switch (kind) {
+        case kLapFaceX:
+            if (t >= 1) {
+                lo[t] = ih2;
+                up[t] = (t <= n - 2) ? ih2 : 0.0;
+                diag[t] = -2.0 * ih2;
+            }
+            break;
+        case kLapCellSlipX:
+            lo[t] = (t >= 1) ? ih2 : 0.0;
+            up[t] = (t <= n - 2) ? ih2 : 0.0;
+            diag[t] = -(lo[t] + up[t]);
+            break;
+        case kLapCellWallY:
+            lo[t] = (t >= 1) ? 1.0 / (dy[t] * (0.5 * (dy[t - 1] + dy[t]))) : 0.0;
+            up[t] = (t <= n - 2) ? 1.0 / (dy[t] * (0.5 * (dy[t] + dy[t + 1]))) : 0.0;
+            diag[t] = -(lo[t] + up[t]);
+            if (t == 0) diag[t] -= 2.0 / (dy[0] * dy[0]);
+            break;
+        case kLapFaceY:
+            if (t >= 1) {
+                const double hj = 0.5 * (dy[t - 1] + dy[t]);
+                lo[t] = 1.0 / (hj * dy[t - 1]);
+                const double upf = 1.0 / (hj * dy[t]);
+                diag[t] = -(lo[t] + upf);
+                up[t] = (t <= n - 2) ? upf : 0.0;
+            }
+            break;
+        default:
+            lo[t] = up[t] = ih2;
+            diag[t] = -2.0 * ih2;
+        }
+    }
+}
+
+void ns_release(tri_ns ns)
+{
+    for (tri_plan &p : ns->plans)
+        if (p) {
+            (void)tri_plan_destroy(p);
+            p = nullptr;
+        }
+    if (ns->mem) (void)hipFree(ns->mem);
+    delete ns;
+}
+
+bool ns_overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" {
+
+tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
+{
+    if (!ctx || !out) return TRI_E_ARG;
+    *out = nullptr;
+    if (!cfg || !cfg->dy) return fail(ctx, TRI_E_ARG, "ns_create: null config or dy");
+    const int64_t Nx = cfg->Nx, Ny = cfg->Ny, Nz = cfg->Nz;
+    if (Nx < 2 || Ny < 2 || Nz < 2) return fail(ctx, TRI_E_SHAPE, "ns_create: grid %lld x %lld x %lld",
+                                                 (long long)Nx, (long long)Ny, (long long)Nz);
+    if (!(cfg->dx > 0.0) || !(cfg->dz > 0.0) || !(cfg->dt > 0.0) || !(cfg->nu >= 0.0))
+        return fail(ctx, TRI_E_ARG, "ns_create: dx, dz, dt must be > 0 and nu >= 0");
+    for (int64_t j = 0; j < Ny; ++j)
+        if (!(cfg->dy[j] > 0.0) || !std::isfinite(cfg->dy[j]))
+            return fail(ctx, TRI_E_ARG, "ns_create: dy[%lld] = %g", (long long)j, cfg->dy[j]);
+    // the projection's requirements, checked here so that a step never fails on them
+    FftShape S;
+    if ((Nz & 1) || (Nx & 1)) return fail(ctx, TRI_E_SHAPE, "ns_create: Nx and Nz must be even");
+    if (!fft_shape(Nz, S) || !dct_shape(Nx, S))
+        return fail(ctx, TRI_E_UNSUPPORTED, "ns_create: Nz/2 or Nx is not 2^a 3^b 5^c within the transform limits");
+    tri_status st = check_partition(ctx, Ny, cfg->P_poisson, 0);
+    if (st) return st;
+    const int mp = (int)(Ny / cfg->P_poisson);
+    if (mp > kGeneralMaxM || (mp > 16 && cfg->P_poisson > 8))
+        return fail(ctx, TRI_E_UNSUPPORTED, "ns_create: the shifted solves take at most 32 rows a partition");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+
+    tri_ns ns = new (std::nothrow) tri_ns_s;
+    if (!ns) return TRI_E_NOMEM;
+    ns->ctx = ctx;
+    ns->Nx = Nx;
+    ns->Ny = Ny;
+    ns->Nz = Nz;
+    ns->dx = cfg->dx;
+    ns->dz = cfg->dz;
+    ns->dt = cfg->dt;
+    ns->nu = cfg->nu;
+    ns->P_poisson = cfg->P_poisson;
+    const int64_t cells = Nx * Ny * Nz, Nk = Nz / 2 + 1;
+    const int64_t nmax = std::max(Nx, std::max(Ny, Nz));
+    // layout (doubles): dy ay cy [Ny each], lamz [Nk], lamx [Nx], coefficients
+    // [3 sub-steps][9 sweeps][3][nmax], then 16-byte aligned: N[3], D[3], phi
+    // [cells each], phihat [2 Nk Ny Nx]
+    const int64_t head = 3 * Ny + Nk + Nx + 3 * 9 * 3 * nmax;
+    const int64_t head_al = (head + 31) / 32 * 32;
+    const size_t bytes = sizeof(double) * (size_t)(head_al + 7 * cells + 2 * Nk * Ny * Nx);
+    if (hipMalloc(&ns->mem, bytes) != hipSuccess) {
+        ns->mem = nullptr;
+        ns_release(ns);
+        return fail(ctx, TRI_E_NOMEM, "ns_create: %zu bytes", bytes);
+    }
+    double *base = (double *)ns->mem;
+    ns->dy = base;
+    ns->ay = base + Ny;
+    ns->cy = base + 2 * Ny;
+    ns->lamz = base + 3 * Ny;
+    ns->lamx = ns->lamz + Nk;
+    double *coef = ns->lamx + Nx;
+    double *fields = base + head_al;
+    for (int c = 0; c < 3; ++c) {
+        ns->N[c] = fields + (int64_t)c * cells;
+        ns->D[c] = fields + (int64_t)(3 + c) * cells;
+    }
+    ns->phi = fields + 6 * cells;
+    ns->phihat = fields + 7 * cells;
+
+    // metric of the projection (cell-centred Neumann second difference in y,
+    // modified wavenumbers of the z Fourier and x cosine transforms)
+    std::vector<double> dy(cfg->dy, cfg->dy + Ny), host((size_t)head, 0.0);
+    for (int64_t j = 0; j < Ny; ++j) {
+        host[(size_t)j] = dy[(size_t)j];
+        if (j >= 1) host[(size_t)(Ny + j)] = 1.0 / (dy[(size_t)j] * (0.5 * (dy[(size_t)(j - 1)] + dy[(size_t)j])));
+        if (j <= Ny - 2) host[(size_t)(2 * Ny + j)] = 1.0 / (dy[(size_t)j] * (0.5 * (dy[(size_t)j] + dy[(size_t)(j + 1)])));
+    }
+    const double pi = 3.14159265358979323846;
+    for (int64_t k = 0; k < Nk; ++k) {
+        const double s = std::sin(pi * (double)k / (double)Nz);
+        host[(size_t)(3 * Ny + k)] = (4.0 / (cfg->dz * cfg->dz)) * s * s;
+    }
+    for (int64_t i = 0; i < Nx; ++i) {
+        const double s = std::sin(pi * (double)i / (2.0 * (double)Nx));
+        host[(size_t)(3 * Ny + Nk + i)] = (4.0 / (cfg->dx * cfg->dx)) * s * s;
+    }
+    // sweep coefficients (1 - beta L_d), beta = alpha_s dt nu / 2; sweeps in the
+    // order du x, y, z; dv x, y, z; dw x, y, z
+    static const int kind[9] = {kLapFaceX, kLapCellWallY, kLapPeriodic, kLapCellSlipX, kLapFaceY, kLapPeriodic,
+                                kLapCellSlipX, kLapCellWallY, kLapPeriodic};
+    std::vector<double> lo, diag, up;
+    const int64_t coef_off = 3 * Ny + Nk + Nx;
+    for (int s = 0; s < 3; ++s) {
+        const double beta = (kRkGamma[s] + kRkZeta[s]) * cfg->dt * cfg->nu / 2.0;
+        for (int q = 0; q < 9; ++q) {
+            const int dir = q % 3;
+            const int64_t n = dir == 0 ? Nx : (dir == 1 ? Ny : Nz);
+            ns_lap_rows(kind[q], n, dir == 0 ? cfg->dx : cfg->dz, dy, lo, diag, up);
+            double *row = host.data() + coef_off + ((int64_t)(s * 9 + q) * 3) * nmax;
+            for (int64_t t = 0; t < n; ++t) {
+                row[t] = -beta * lo[(size_t)t];
+                row[nmax + t] = 1.0 - beta * diag[(size_t)t];
+                row[2 * nmax + t] = -beta * up[(size_t)t];
+            }
+        }
+    }
+    if (hipMemcpy(base, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        ns_release(ns);
+        return fail(ctx, TRI_E_HIP, "ns_create: upload");
+    }
+    // one plan per sub-step: the nine sweeps (x sweeps of the three fields form
+    // one dependency level, then y, then z)
+    for (int s = 0; s < 3; ++s) {
+        tri_item items[9];
+        for (int q = 0; q < 9; ++q) {
+            const int dir = q % 3, c = q / 3;
+            const double *row = coef + ((int64_t)(s * 9 + q) * 3) * nmax;
+            items[q] = tri_item{dir, ns->D[c], Nx, Ny, Nz, row, row + nmax, row + 2 * nmax, nullptr,
+                                cfg->P_adi[dir], dir == 2 ? 1 : 0, TRI_PDD};
+        }
+        st = tri_plan_create(ctx, items, 9, TRI_F64, &ns->plans[s]);
+        if (st) {
+            const std::string why = ctx->last_error;
+            ns_release(ns);
+            return fail(ctx, st, "ns_create: sweep plan: %s", why.c_str());
+        }
+    }
+    *out = ns;
+    return TRI_OK;
+}
+
+tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
+{
+    if (!ns) return TRI_E_ARG;
+    tri_ctx ctx = ns->ctx;
+    const int64_t Nx = ns->Nx, Ny = ns->Ny, Nz = ns->Nz, cells = Nx * Ny * Nz;
+    if (!u || !v || !w || !p) return fail(ctx, TRI_E_ARG, "ns_step: null field");
+    if (misaligned(u) || misaligned(v) || misaligned(w) || misaligned(p))
+        return fail(ctx, TRI_E_ARG, "ns_step: misaligned field");
+    const size_t bu = sizeof(double) * (size_t)(Nz * Ny * (Nx + 1)), bv = sizeof(double) * (size_t)(Nz * (Ny + 1) * Nx);
+    const size_t bc = sizeof(double) * (size_t)cells;
+    if (ns_overlap(u, bu, v, bv) || ns_overlap(u, bu, w, bc) || ns_overlap(u, bu, p, bc) ||
+        ns_overlap(v, bv, w, bc) || ns_overlap(v, bv, p, bc) || ns_overlap(w, bc, p, bc))
+        return fail(ctx, TRI_E_ARG, "ns_step: u, v, w and p must not overlap");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    for (int s = 0; s < 3; ++s) {
+        NsRhsArgs A;
+        A.u = u;
+        A.v = v;
+        A.w = w;
+        A.p = p;
+        A.dy = ns->dy;
+        A.Nx = Nx;
+        A.Ny = Ny;
+        A.Nz = Nz;
+        A.dx = ns->dx;
+        A.dz = ns->dz;
+        A.dt = ns->dt;
+        A.nu = ns->nu;
+        A.gamma = kRkGamma[s];
+        A.zeta = kRkZeta[s];
+        A.alpha = kRkGamma[s] + kRkZeta[s];
+        A.Nu = ns->N[0];
+        A.Nv = ns->N[1];
+        A.Nw = ns->N[2];
+        A.du = ns->D[0];
+        A.dv = ns->D[1];
+        A.dw = ns->D[2];
+        HIP_TRY(ctx, launch_ns_rhs(A, ctx->stream));
+        tri_status st = tri_plan_execute(ns->plans[s]);
+        if (st) return st;
+        HIP_TRY(ctx, launch_ns_update(u, v, w, ns->D[0], ns->D[1], ns->D[2], Nx, Ny, Nz, ctx->stream));
+        st = projection3d_step(ctx, u, v, w, ns->dx, ns->dy, ns->dz, ns->ay, ns->cy, ns->lamz, ns->lamx, ns->phihat,
+                               ns->phi, Nx, Ny, Nz, ns->P_poisson);
+        if (st) return st;
+        HIP_TRY(ctx, launch_ns_pressure(p, ns->phi, 1.0 / (A.alpha * ns->dt), cells, ctx->stream));
+    }
+    return TRI_OK;
+}
+
+tri_status ns_destroy(tri_ns ns)
+{
+    if (!ns) return TRI_E_ARG;
+    (void)hipSetDevice(ns->ctx->device);
+    (void)hipStreamSynchronize(ns->ctx->stream);
+    ns_release(ns);
+    return TRI_OK;
+}
+
+}  // extern "C"

@@ -221,6 +221,43 @@ int main()
         CHECK(tri_plan_create(ctx, &bad, 1, TRI_F64, &plan) == TRI_E_ARG && !plan);
     }
 
+    // ---- the fractional-step time step: set-up validation, steps allocate nothing
+    {
+        const int64_t nx = 16, ny = 32, nz = 24;
+        std::vector<double> dyv(ny, 1.0 / ny);
+        tri_ns_config cfg{nx, ny, nz, 1.0 / nx, 1.0 / nz, dyv.data(), 1e-3, 1e-3, {2, 4, 4}, 4};
+        tri_ns ns = nullptr;
+        const int m0 = g_mallocs;
+        tri_ns_config bad = cfg;
+        bad.Nx = 15;
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_SHAPE && !ns);
+        bad = cfg;
+        bad.Nz = 22;                                      // Nz/2 = 11
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_UNSUPPORTED && !ns);
+        bad = cfg;
+        bad.P_poisson = 3;
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_SHAPE && !ns);
+        bad = cfg;
+        bad.dt = 0.0;
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_ARG && !ns);
+        bad = cfg;
+        bad.dy = nullptr;
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_ARG && !ns);
+        CHECK(g_mallocs == m0);
+        bad = cfg;
+        bad.P_adi[0] = 3;                                 // 16 % 3: refused by the sweep plan, nothing kept
+        CHECK(ns_create(ctx, &bad, &ns) == TRI_E_SHAPE && !ns);
+        CHECK(ns_create(ctx, &cfg, &ns) == TRI_OK && ns);
+        std::vector<double> uu(nz * ny * (nx + 1)), vv(nz * (ny + 1) * nx), ww(nz * ny * nx), pp(nz * ny * nx);
+        const int l0 = g_launches, m1 = g_mallocs, s0 = g_syncs;
+        CHECK(ns_step(ns, uu.data(), vv.data(), ww.data(), pp.data()) == TRI_OK);
+        CHECK(g_launches > l0 && g_mallocs == m1 && g_syncs == s0);
+        REFUSED(ns_step(ns, uu.data(), vv.data(), ww.data(), ww.data()), TRI_E_ARG, ww);   // p over w
+        REFUSED(ns_step(ns, uu.data(), nullptr, ww.data(), pp.data()), TRI_E_ARG, ww);
+        CHECK(ns_step(nullptr, uu.data(), vv.data(), ww.data(), pp.data()) == TRI_E_ARG);
+        CHECK(ns_destroy(ns) == TRI_OK);
+    }
+
     CHECK(tri_destroy(ctx) == TRI_OK);
     CHECK(g_mallocs == g_frees);      // everything the library allocated was released
     if (failures) {

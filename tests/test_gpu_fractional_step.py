@@ -1,0 +1,149 @@
+"""GPU parity of the fractional-step time step (ns_create / ns_step; Sec. 2.1-2.2)
+against the oracle's step (oracle/fractional_step.py), through the C ABI.
+
+* Two time steps (six Runge-Kutta sub-steps, the pressure carried between them)
+  from a divergence-free random state on grids with ragged workgroup tails:
+  u, v, w and p within 1e-12 per x-line of the oracle's (PDD sweeps at the
+  same partition counts, PPT shifted solves).
+* The benchmark grid 2048 x 256 x 288 (x, y, z sweeps at P = 8, 4, 16; shifted
+  solves at P = 8), where the oracle's whole step is out of reach: after one
+  step from a random, divergent state the velocity is divergence free to
+  1e-13 of the initial divergence, the wall faces hold zero, and a step from
+  rest with no pressure stays exactly at rest.
+* Set-up refusals: shapes the projection cannot take, partition counts the
+  sweeps cannot take, overlapping fields.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from gpu_helpers import TOL, dev, host, line_relerr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_1812_01178_amd as T
+    T.lib()
+    return T
+
+
+@pytest.fixture(scope="module")
+def ctx(T):
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    h = T.tri_create(0, torch.cuda.current_stream().cuda_stream)
+    yield h
+    T.tri_destroy(h)
+
+
+def _state(Nx, Ny, Nz, seed, amp=0.3):
+    rng = np.random.default_rng(seed)
+    u = amp * rng.standard_normal((Nz, Ny, Nx + 1))
+    u[:, :, 0] = u[:, :, Nx] = 0.0
+    v = amp * rng.standard_normal((Nz, Ny + 1, Nx))
+    v[:, 0, :] = v[:, Ny, :] = 0.0
+    w = amp * rng.standard_normal((Nz, Ny, Nx))
+    return u, v, w
+
+
+@pytest.mark.parametrize("Nx,Ny,Nz,P_adi,P_poi", [(64, 32, 24, (8, 4, 4), 4), (200, 48, 30, (8, 4, 2), 2),
+                                                   (256, 64, 48, (8, 4, 4), 4)])
+def test_time_steps_match_the_oracle(T, ctx, orc, Nx, Ny, Nz, P_adi, P_poi):
+    from oracle import fractional_step as fs
+    from oracle.projection import project3d
+    dx, dz = 1.0 / Nx, 1.0 / Nz
+    dy = np.diff(W.tanh_faces(Ny))
+    dt, nu = 2e-3, 1e-2
+    u0, v0, w0, _ = project3d(*_state(Nx, Ny, Nz, 11), dx, dy, dz, P=P_poi)
+    ref = (u0, v0, w0)
+    p_ref = None
+    for _ in range(2):
+        *ref, p_ref = fs.time_step(*ref, dt, nu, dx, dy, dz, P=P_adi, P_poisson=P_poi, method=orc.PDD, p=p_ref)
+    u, v, w = dev(u0), dev(v0), dev(w0)
+    p = torch.zeros((Nz, Ny, Nx), dtype=torch.float64, device="cuda")
+    print(f"ns_step grid {Nx}x{Ny}x{Nz} P_adi={P_adi} P_poisson={P_poi}", flush=True)
+    ns = T.ns_create(ctx, Nx, Ny, Nz, dx, dz, dy, dt, nu, P_adi, P_poi)
+    try:
+        for _ in range(2):
+            T.ns_step(ns, u, v, w, p, ctx)
+        T.tri_sync_status(ctx)
+    finally:
+        T.ns_destroy(ns)
+    for name, got, want in (("u", u, ref[0]), ("v", v, ref[1]), ("w", w, ref[2]), ("p", p, p_ref)):
+        err = line_relerr(host(got), want, axis=2)
+        print(f"  {name}: worst x-line relative error {err:.2e}", flush=True)
+        assert err <= TOL, (name, err)
+
+
+def test_benchmark_grid_step_is_divergence_free(T, ctx):
+    Nx, Ny, Nz = 2048, 256, 288
+    dx, dz = 1.0 / Nx, 1.0 / Nz
+    dy = np.diff(W.tanh_faces(Ny))
+    g = torch.Generator(device="cuda").manual_seed(3)
+    u = 0.1 * torch.randn((Nz, Ny, Nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u[:, :, 0] = 0.0
+    u[:, :, Nx] = 0.0
+    v = 0.1 * torch.randn((Nz, Ny + 1, Nx), dtype=torch.float64, device="cuda", generator=g)
+    v[:, 0, :] = 0.0
+    v[:, Ny, :] = 0.0
+    w = 0.1 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    p = torch.zeros((Nz, Ny, Nx), dtype=torch.float64, device="cuda")
+    ddy = dev(dy)
+
+    def div():
+        return ((u[:, :, 1:] - u[:, :, :-1]) / dx + (v[:, 1:, :] - v[:, :-1, :]) / ddy[None, :, None]
+                + (torch.roll(w, -1, 0) - w) / dz).abs().max().item()
+    d0 = div()
+    print(f"ns_step grid {Nx}x{Ny}x{Nz}", flush=True)
+    ns = T.ns_create(ctx, Nx, Ny, Nz, dx, dz, dy, 1e-3, 1e-3, (8, 4, 16), 8)
+    try:
+        T.ns_step(ns, u, v, w, p, ctx)
+        T.tri_sync_status(ctx)
+        d1 = div()
+        assert d1 <= 1e-13 * d0, (d0, d1)
+        assert torch.count_nonzero(u[:, :, 0]) == 0 and torch.count_nonzero(u[:, :, Nx]) == 0
+        assert torch.count_nonzero(v[:, 0, :]) == 0 and torch.count_nonzero(v[:, Ny, :]) == 0
+        assert torch.isfinite(p).all()
+        # rest stays at rest (no forcing, no pressure)
+        for t in (u, v, w, p):
+            t.zero_()
+        T.ns_step(ns, u, v, w, p, ctx)
+        T.tri_sync_status(ctx)
+        assert all(torch.count_nonzero(t) == 0 for t in (u, v, w, p))
+    finally:
+        T.ns_destroy(ns)
+
+
+def test_set_up_and_step_refusals(T, ctx):
+    dy = np.full(32, 1.0 / 32)
+    bad = [
+        dict(Nx=15, Ny=32, Nz=24),          # odd Nx
+        dict(Nx=14, Ny=32, Nz=24),          # 14 = 2 * 7 is not a transform size
+        dict(Nx=16, Ny=32, Nz=22),          # Nz/2 = 11
+    ]
+    for g in bad:
+        with pytest.raises(T.TriError) as e:
+            T.ns_create(ctx, g["Nx"], g["Ny"], g["Nz"], 1.0 / g["Nx"], 1.0 / g["Nz"], dy, 1e-3, 1e-3, (2, 4, 4), 4)
+        assert e.value.status in (T.TRI_E_SHAPE, T.TRI_E_UNSUPPORTED)
+    with pytest.raises(T.TriError) as e:        # P_poisson = 3 does not divide Ny
+        T.ns_create(ctx, 16, 32, 24, 1 / 16, 1 / 24, dy, 1e-3, 1e-3, (2, 4, 4), 3)
+    assert e.value.status == T.TRI_E_SHAPE
+    with pytest.raises(T.TriError) as e:        # a sweep partition count that does not divide Nx
+        T.ns_create(ctx, 16, 32, 24, 1 / 16, 1 / 24, dy, 1e-3, 1e-3, (3, 4, 4), 4)
+    assert e.value.status == T.TRI_E_SHAPE
+    with pytest.raises(T.TriError) as e:
+        T.ns_create(ctx, 16, 32, 24, 1 / 16, 1 / 24, dy, -1e-3, 1e-3, (2, 4, 4), 4)
+    assert e.value.status == T.TRI_E_ARG
+    ns = T.ns_create(ctx, 16, 32, 24, 1 / 16, 1 / 24, dy, 1e-3, 1e-3, (2, 4, 4), 4)
+    try:
+        u = torch.zeros((24, 32, 17), dtype=torch.float64, device="cuda")
+        v = torch.zeros((24, 33, 16), dtype=torch.float64, device="cuda")
+        w = torch.zeros((24, 32, 16), dtype=torch.float64, device="cuda")
+        with pytest.raises(T.TriError) as e:    # p over w
+            T.ns_step(ns, u, v, w, w, ctx)
+        assert e.value.status == T.TRI_E_ARG
+    finally:
+        T.ns_destroy(ns)

@@ -175,3 +175,16 @@ def test_bench_cpu_baseline_leaves_its_inputs_untouched(orc):
     ay, cy = W.poisson_metric(ny)
     bench.cpu_baseline(orc, u0, phi0, coef, ay, cy, W.modified_wavenumbers(nz), 0.01)
     assert np.array_equal(u0, keep_u) and np.array_equal(phi0, keep_p)
+
+
+def test_tune_table_lists_the_ragged_partition_choices():
+    """The shipped tuning table fixes the partition count of every item of the
+    ragged eight-sub-grid batch (x, y, z sweeps and Poisson, FP64 and FP32+refine),
+    so every run of the benchmark measures the same configuration."""
+    table = open(os.path.join(ROOT, "paper_1812_01178_amd", "tune_gfx950.txt")).read().splitlines()
+    keys = {ln.rsplit("|", 1)[0]: int(ln.rsplit("|", 1)[1]) for ln in table if "|" in ln and not ln.startswith("#")}
+    for prec in (0, 1):
+        for nx, ny, nz in W.RAGGED_SUBGRIDS:
+            for kind, per, method, n3 in ((0, 0, 0, nz), (1, 0, 0, nz), (2, 1, 0, nz), (3, 0, 1, nz // 2 + 1)):
+                key = f"partitions k{kind} m{method} per{per} prec{prec} Nx{nx} Ny{ny} Nz{n3}"
+                assert keys.get(key, 0) in (1, 2, 4, 8, 16), key
