@@ -531,7 +531,7 @@ def measured_traffic(item, launch):
     return None
 
 
-REFINE_P = {"adi_z": 4}
+REFINE_P = {"adi_y": 8, "adi_z": 8}
 
 
 def refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, coef, u0, phi0,
@@ -543,7 +543,8 @@ def refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, co
     import torch
     # the refined result is the exact solution whatever the inner solver's
     # partition count; the refinement kernel takes at most 8 wavefronts of
-    # more than 8 rows, so the spanwise lines use P = 4 here
+    # more than 8 rows, and at P = 8 (one row per lane group) its strided
+    # form runs fastest, so the wall-normal and spanwise lines use P = 8 here
     items = [(nm, d, REFINE_P.get(nm, P), per, meth) for nm, d, P, per, meth in ITEMS]
     plans, descr = {}, {}
     for name, direction, P, per, meth in items:

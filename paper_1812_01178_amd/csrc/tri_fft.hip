@@ -308,7 +308,21 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
     cplx *twM = buf + (size_t)M * L;                 // [M]
     cplx *twN = twM + M;                             // [M/2 + 1]
     const int ln = threadIdx.x % L, tr = threadIdx.x / L;
-    const int64_t g = (int64_t)blockIdx.x * L + ln;
+    int64_t blk = blockIdx.x;
+    if (DIV == 2) {
+        // The x-face rows of u hold Nx+1 values, so a chunk of L stations
+        // reads L+1 faces spanning two cache lines, the second shared with the
+        // next chunk of the row.  Workgroups are dealt to the 8 XCDs in turn:
+        // each XCD takes a contiguous run of chunks of every row, walking the
+        // rows in order, so that both readers of such a line, and of the v
+        // faces shared with the next row, are resident in one L2 together.
+        const int cpr = A.Nx / L;
+        if (A.Nx % L == 0 && cpr % 8 == 0) {
+            const int64_t wr = cpr / 8, x = blk % 8, s = blk / 8;
+            blk = (s / wr) * cpr + x * wr + s % wr;
+        }
+    }
+    const int64_t g = blk * L + ln;
     const bool act = g < A.lines;
     const int Nz = 2 * M;
     make_twiddles(twM, twN, M);

@@ -19,10 +19,11 @@
 // R = 0) and N_q over N_q,prev.  Interpolations to a face: the mean of the two
 // neighbours on the uniform directions, the distance-weighted mean on the
 // stretched y mesh, (dy_j q_{j-1} + dy_{j-1} q_j) / (dy_{j-1} + dy_j).
-// One thread per cell (i, j, k) computes the three unknowns of that index;
-// every array is HBM-resident and read through the caches (stencil reuse of
-// neighbouring rows), so the kernel is bound by HBM.
+// One thread per column (i, j) marches in z and computes the three unknowns
+// of every cell of the column; the kernel is bound by HBM.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "tri_internal.h"
 
@@ -30,14 +31,50 @@ namespace tri {
 
 namespace {
 
-struct NsView {
+// The stencil of one cell (i, j) in one z-plane: every value of u, v, w, p at
+// that plane the three unknowns of the cell need (_xm/_xp: i -/+ 1, _ym/_yp:
+// j -/+ 1; values outside the grid read as 0 and are never used).
+struct Plane {
+    double u_xm, u0, u_xp, u_ym, u_yp, u_ymxp;
+    double v_xm, v0, v_xp, v_ypxm, v_yp, v_ym;
+    double w_xm, w0, w_xp, w_ym, w_yp;
+    double p0, p_xm, p_ym;
+};
+
+struct NsColumn {
     const double *u, *v, *w, *p;
-    const double *dy;
-    int64_t Nx, Ny, Nz;
-    __device__ __forceinline__ double U(int64_t k, int64_t j, int64_t i) const { return u[(k * Ny + j) * (Nx + 1) + i]; }
-    __device__ __forceinline__ double V(int64_t k, int64_t j, int64_t i) const { return v[(k * (Ny + 1) + j) * Nx + i]; }
-    __device__ __forceinline__ double W(int64_t k, int64_t j, int64_t i) const { return w[(k * Ny + j) * Nx + i]; }
-    __device__ __forceinline__ double Pc(int64_t k, int64_t j, int64_t i) const { return p[(k * Ny + j) * Nx + i]; }
+    int64_t Nx, Ny;
+    int64_t i, j;
+    // the plane-k stencil of cell (i, j)
+    __device__ __forceinline__ void load(int64_t k, Plane &q) const
+    {
+        const double *U = u + (k * Ny + j) * (Nx + 1) + i;       // u[k][j][i]
+        const double *V = v + (k * (Ny + 1) + j) * Nx + i;      // v[k][j][i]
+        const double *Wp = w + (k * Ny + j) * Nx + i;
+        const double *Pp = p + (k * Ny + j) * Nx + i;
+        const bool xm = i >= 1, xp = i <= Nx - 2, ym = j >= 1, yp = j <= Ny - 2;
+        const int64_t su = Nx + 1, sv = Nx;
+        q.u_xm = xm ? U[-1] : 0.0;
+        q.u0 = U[0];
+        q.u_xp = U[1];                                            // face i + 1 <= Nx exists
+        q.u_ym = ym ? U[-su] : 0.0;
+        q.u_yp = yp ? U[su] : 0.0;
+        q.u_ymxp = ym ? U[1 - su] : 0.0;
+        q.v_xm = xm ? V[-1] : 0.0;
+        q.v0 = V[0];
+        q.v_xp = xp ? V[1] : 0.0;
+        q.v_ypxm = xm ? V[sv - 1] : 0.0;                          // face j + 1 <= Ny exists
+        q.v_yp = V[sv];
+        q.v_ym = ym ? V[-sv] : 0.0;
+        q.w_xm = xm ? Wp[-1] : 0.0;
+        q.w0 = Wp[0];
+        q.w_xp = xp ? Wp[1] : 0.0;
+        q.w_ym = ym ? Wp[-sv] : 0.0;
+        q.w_yp = yp ? Wp[sv] : 0.0;
+        q.p0 = Pp[0];
+        q.p_xm = xm ? Pp[-1] : 0.0;
+        q.p_ym = ym ? Pp[-sv] : 0.0;
+    }
 };
 
 // cell-centred quantity q(j) interpolated to the interior y-face j (1..Ny-1)
@@ -46,125 +83,134 @@ __device__ __forceinline__ double to_yface(double qm, double q, double dym, doub
     return (dyj * qm + dym * q) / (dym + dyj);
 }
 
-__global__ void __launch_bounds__(256) k_ns_rhs(const NsView G, const NsRhsArgs A)
+// One thread per column (i, j), marching in z over the planes of its segment
+// (blockIdx.z; the segments split the periodic z range evenly) with the
+// stencils of planes k - 1 (the values still needed), k (C) and k + 1 (Nn,
+// loaded while plane k is computed) in registers: every plane of u, v, w, p
+// is read once per column and segment (the x- and y-neighbours of a row come
+// from the same cache lines as the neighbouring columns'), and no address is
+// recomputed from (i, j, k) inside the march.
+__global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
 {
-    const int64_t Nx = G.Nx, Ny = G.Ny, Nz = G.Nz;
+    const int64_t Nx = A.Nx, Ny = A.Ny, Nz = A.Nz;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t j = blockIdx.y, k = blockIdx.z;
+    const int64_t j = blockIdx.y;
     if (i >= Nx) return;
-    const int64_t km = (k == 0) ? Nz - 1 : k - 1, kp = (k == Nz - 1) ? 0 : k + 1;
+    const NsColumn G{A.u, A.v, A.w, A.p, Nx, Ny, i, j};
     const double dx = A.dx, dz = A.dz, idx2 = 1.0 / (dx * dx), idz2 = 1.0 / (dz * dz);
-    const double dyj = G.dy[j];
-    const double dym = (j > 0) ? G.dy[j - 1] : 0.0;          // dy_{j-1}
-    const double dyp = (j < Ny - 1) ? G.dy[j + 1] : 0.0;     // dy_{j+1}
-    const int64_t o = (k * Ny + j) * Nx + i;
+    const double dyj = A.dy[j];
+    const double dym = (j > 0) ? A.dy[j - 1] : 0.0;          // dy_{j-1}
+    const double dyp = (j < Ny - 1) ? A.dy[j + 1] : 0.0;     // dy_{j+1}
+    const double hj = 0.5 * (dym + dyj);
     const double cg = A.gamma, cz = A.zeta, ca = A.alpha, nu = A.nu, dt = A.dt;
+    const bool xm = i >= 1, xp = i <= Nx - 2, ym = j >= 1, yp = j <= Ny - 2;
 
     // y second difference of a cell-centred component (no-slip wall below cell
     // 0, zero flux through the top): lo q_{j-1} + diag q_j + up q_{j+1}
-    auto lap_y_cell = [&](double qm, double q, double qp) {
-        const double lo = (j >= 1) ? 1.0 / (dyj * (0.5 * (dym + dyj))) : 0.0;
-        const double up = (j <= Ny - 2) ? 1.0 / (dyj * (0.5 * (dyj + dyp))) : 0.0;
-        double diag = -(lo + up);
-        if (j == 0) diag -= 2.0 / (dyj * dyj);
-        return lo * qm + diag * q + up * qp;
-    };
+    const double ly_lo = ym ? 1.0 / (dyj * (0.5 * (dym + dyj))) : 0.0;
+    const double ly_up = yp ? 1.0 / (dyj * (0.5 * (dyj + dyp))) : 0.0;
+    const double ly_dg = -(ly_lo + ly_up) - ((j == 0) ? 2.0 / (dyj * dyj) : 0.0);
+    auto lap_y_cell = [&](double qm, double q, double qp) { return ly_lo * qm + ly_dg * q + ly_up * qp; };
     // x second difference of a cell-centred component (slip walls at both ends)
-    auto lap_x_cell = [&](double qm, double q, double qp) {
-        const double lo = (i >= 1) ? idx2 : 0.0, up = (i <= Nx - 2) ? idx2 : 0.0;
-        return lo * qm + (-(lo + up)) * q + up * qp;
-    };
+    const double lx_lo = xm ? idx2 : 0.0, lx_up = xp ? idx2 : 0.0, lx_dg = -(lx_lo + lx_up);
+    auto lap_x_cell = [&](double qm, double q, double qp) { return lx_lo * qm + lx_dg * q + lx_up * qp; };
     auto lap_z = [&](double qm, double q, double qp) { return idz2 * qm + (-2.0 * idz2) * q + idz2 * qp; };
+    // y second difference of v on the faces (walls at faces 0 and Ny, held 0)
+    const double lv_lo = ym ? 1.0 / (hj * dym) : 0.0, lv_upf = ym ? 1.0 / (hj * dyj) : 0.0;
+    const double lv_up = yp ? lv_upf : 0.0;
 
-    // ---------------- u at x-face i (interior faces 1..Nx-1) ----------------
-    {
-        double R = 0.0, Nq = 0.0;
-        if (i >= 1) {
-            const double u0 = G.U(k, j, i);
-            const double uxm = G.U(k, j, i - 1), uxp = G.U(k, j, i + 1);
-            const double ucp = 0.5 * (u0 + uxp), ucm = 0.5 * (uxm + u0);
-            const double duu = (ucp * ucp - ucm * ucm) / dx;
-            // flux u v through the y-faces j (bottom) and j+1 (top) of the cell
-            double Fb = 0.0, Ft = 0.0;
-            const double uym = (j >= 1) ? G.U(k, j - 1, i) : 0.0;
-            const double uyp = (j <= Ny - 2) ? G.U(k, j + 1, i) : 0.0;
-            if (j >= 1) Fb = to_yface(uym, u0, dym, dyj) * (0.5 * (G.V(k, j, i - 1) + G.V(k, j, i)));
-            if (j <= Ny - 2) Ft = to_yface(u0, uyp, dyj, dyp) * (0.5 * (G.V(k, j + 1, i - 1) + G.V(k, j + 1, i)));
-            const double duv = (Ft - Fb) / dyj;
-            // flux u w through the z-faces k and k+1
-            const double uzm = G.U(km, j, i), uzp = G.U(kp, j, i);
-            const double Gk = (0.5 * (uzm + u0)) * (0.5 * (G.W(k, j, i - 1) + G.W(k, j, i)));
-            const double Gk1 = (0.5 * (u0 + uzp)) * (0.5 * (G.W(kp, j, i - 1) + G.W(kp, j, i)));
-            const double duw = (Gk1 - Gk) / dz;
-            Nq = -(duu + duv + duw);
-            // u_Nx (the far wall) is stored as 0, so the x row needs no special case
-            const double Lq = (idx2 * uxm + (-2.0 * idx2) * u0 + idx2 * ((i <= Nx - 2) ? uxp : 0.0)) +
-                              lap_y_cell(uym, u0, uyp) + lap_z(uzm, u0, uzp);
-            const double Gp = (G.Pc(k, j, i) - G.Pc(k, j, i - 1)) / dx;
-            R = dt * (cg * Nq + (cz != 0.0 ? cz * A.Nu[o] : 0.0) + ca * (nu * Lq - Gp));
+    // planes k0 .. k1-1 of this segment; plane k0 - 1 (periodic) values still
+    // needed: u, u_xp, v, v_yp, w, p
+    const int64_t k0 = Nz * blockIdx.z / gridDim.z, k1 = Nz * (blockIdx.z + 1) / gridDim.z;
+    Plane C, Nn;
+    double b_u0, b_uxp, b_v0, b_vyp, b_w0, b_p0;
+    G.load(k0 > 0 ? k0 - 1 : Nz - 1, C);
+    b_u0 = C.u0, b_uxp = C.u_xp, b_v0 = C.v0, b_vyp = C.v_yp, b_w0 = C.w0, b_p0 = C.p0;
+    G.load(k0, C);
+    const int64_t plane = Ny * Nx;
+    int64_t o = (k0 * Ny + j) * Nx + i;
+    for (int64_t k = k0; k < k1; ++k, o += plane) {
+        G.load(k + 1 < Nz ? k + 1 : 0, Nn);
+        const double Nu_prev = cz != 0.0 ? A.Nu[o] : 0.0;
+        const double Nv_prev = cz != 0.0 ? A.Nv[o] : 0.0;
+        const double Nw_prev = cz != 0.0 ? A.Nw[o] : 0.0;
+        // ---------------- u at x-face i (interior faces 1..Nx-1) ----------------
+        {
+            double R = 0.0, Nq = 0.0;
+            if (xm) {
+                const double u0 = C.u0, uxm = C.u_xm, uxp = C.u_xp;
+                const double ucp = 0.5 * (u0 + uxp), ucm = 0.5 * (uxm + u0);
+                const double duu = (ucp * ucp - ucm * ucm) / dx;
+                // flux u v through the y-faces j (bottom) and j+1 (top) of the cell
+                const double uym = C.u_ym, uyp = C.u_yp;
+                const double Fb = ym ? to_yface(uym, u0, dym, dyj) * (0.5 * (C.v_xm + C.v0)) : 0.0;
+                const double Ft = yp ? to_yface(u0, uyp, dyj, dyp) * (0.5 * (C.v_ypxm + C.v_yp)) : 0.0;
+                const double duv = (Ft - Fb) / dyj;
+                // flux u w through the z-faces k and k+1
+                const double uzm = b_u0, uzp = Nn.u0;
+                const double Gk = (0.5 * (uzm + u0)) * (0.5 * (C.w_xm + C.w0));
+                const double Gk1 = (0.5 * (u0 + uzp)) * (0.5 * (Nn.w_xm + Nn.w0));
+                const double duw = (Gk1 - Gk) / dz;
+                Nq = -(duu + duv + duw);
+                // u_Nx (the far wall) is 0, so the x row needs no special case
+                const double Lq = (idx2 * uxm + (-2.0 * idx2) * u0 + idx2 * (xp ? uxp : 0.0)) +
+                                  lap_y_cell(uym, u0, uyp) + lap_z(uzm, u0, uzp);
+                const double Gp = (C.p0 - C.p_xm) / dx;
+                R = dt * (cg * Nq + cz * Nu_prev + ca * (nu * Lq - Gp));
+            }
+            A.Nu[o] = Nq;
+            A.du[o] = R;
         }
-        A.Nu[o] = Nq;
-        A.du[o] = R;
-    }
-    // ---------------- v at y-face j (interior faces 1..Ny-1) ----------------
-    {
-        double R = 0.0, Nq = 0.0;
-        if (j >= 1) {
-            const double v0 = G.V(k, j, i);
-            // flux v u through the x-faces i and i+1 (u = 0 on the x-walls)
-            double Hl = 0.0, Hr = 0.0;
-            const double vxm = (i >= 1) ? G.V(k, j, i - 1) : 0.0;
-            const double vxp = (i <= Nx - 2) ? G.V(k, j, i + 1) : 0.0;
-            if (i >= 1) Hl = (0.5 * (vxm + v0)) * to_yface(G.U(k, j - 1, i), G.U(k, j, i), dym, dyj);
-            if (i <= Nx - 2) Hr = (0.5 * (v0 + vxp)) * to_yface(G.U(k, j - 1, i + 1), G.U(k, j, i + 1), dym, dyj);
-            const double dvu = (Hr - Hl) / dx;
-            const double vym = G.V(k, j - 1, i), vyp = G.V(k, j + 1, i);
-            const double vcp = 0.5 * (v0 + vyp), vcm = 0.5 * (vym + v0);
-            const double hj = 0.5 * (dym + dyj);
-            const double dvv = (vcp * vcp - vcm * vcm) / hj;
-            // flux v w through the z-faces k and k+1
-            const double vzm = G.V(km, j, i), vzp = G.V(kp, j, i);
-            const double Gk = (0.5 * (vzm + v0)) * to_yface(G.W(k, j - 1, i), G.W(k, j, i), dym, dyj);
-            const double Gk1 = (0.5 * (v0 + vzp)) * to_yface(G.W(kp, j - 1, i), G.W(kp, j, i), dym, dyj);
-            const double dvw = (Gk1 - Gk) / dz;
-            Nq = -(dvu + dvv + dvw);
-            // y second difference on the faces (walls at faces 0 and Ny, held 0)
-            const double lo = 1.0 / (hj * dym), upf = 1.0 / (hj * dyj);
-            const double up = (j <= Ny - 2) ? upf : 0.0;
-            const double Ly = lo * vym + (-(lo + upf)) * v0 + up * vyp;
-            const double Lq = lap_x_cell(vxm, v0, vxp) + Ly + lap_z(vzm, v0, vzp);
-            const double Gp = (G.Pc(k, j, i) - G.Pc(k, j - 1, i)) / hj;
-            R = dt * (cg * Nq + (cz != 0.0 ? cz * A.Nv[o] : 0.0) + ca * (nu * Lq - Gp));
+        // ---------------- v at y-face j (interior faces 1..Ny-1) ----------------
+        {
+            double R = 0.0, Nq = 0.0;
+            if (ym) {
+                const double v0 = C.v0, vxm = C.v_xm, vxp = C.v_xp;
+                // flux v u through the x-faces i and i+1 (u = 0 on the x-walls)
+                const double Hl = xm ? (0.5 * (vxm + v0)) * to_yface(C.u_ym, C.u0, dym, dyj) : 0.0;
+                const double Hr = xp ? (0.5 * (v0 + vxp)) * to_yface(C.u_ymxp, C.u_xp, dym, dyj) : 0.0;
+                const double dvu = (Hr - Hl) / dx;
+                const double vym = C.v_ym, vyp = C.v_yp;
+                const double vcp = 0.5 * (v0 + vyp), vcm = 0.5 * (vym + v0);
+                const double dvv = (vcp * vcp - vcm * vcm) / hj;
+                // flux v w through the z-faces k and k+1
+                const double vzm = b_v0, vzp = Nn.v0;
+                const double Gk = (0.5 * (vzm + v0)) * to_yface(C.w_ym, C.w0, dym, dyj);
+                const double Gk1 = (0.5 * (v0 + vzp)) * to_yface(Nn.w_ym, Nn.w0, dym, dyj);
+                const double dvw = (Gk1 - Gk) / dz;
+                Nq = -(dvu + dvv + dvw);
+                const double Ly = lv_lo * vym + (-(lv_lo + lv_upf)) * v0 + lv_up * vyp;
+                const double Lq = lap_x_cell(vxm, v0, vxp) + Ly + lap_z(vzm, v0, vzp);
+                const double Gp = (C.p0 - C.p_ym) / hj;
+                R = dt * (cg * Nq + cz * Nv_prev + ca * (nu * Lq - Gp));
+            }
+            A.Nv[o] = Nq;
+            A.dv[o] = R;
         }
-        A.Nv[o] = Nq;
-        A.dv[o] = R;
-    }
-    // ---------------- w at z-face k ----------------------------------------
-    {
-        const double w0 = G.W(k, j, i);
-        // flux w u through the x-faces i and i+1 (u = 0 on the x-walls)
-        double Hl = 0.0, Hr = 0.0;
-        const double wxm = (i >= 1) ? G.W(k, j, i - 1) : 0.0;
-        const double wxp = (i <= Nx - 2) ? G.W(k, j, i + 1) : 0.0;
-        if (i >= 1) Hl = (0.5 * (wxm + w0)) * (0.5 * (G.U(km, j, i) + G.U(k, j, i)));
-        if (i <= Nx - 2) Hr = (0.5 * (w0 + wxp)) * (0.5 * (G.U(km, j, i + 1) + G.U(k, j, i + 1)));
-        const double dwu = (Hr - Hl) / dx;
-        // flux w v through the y-faces j and j+1 (v = 0 on the y-walls)
-        double Fb = 0.0, Ft = 0.0;
-        const double wym = (j >= 1) ? G.W(k, j - 1, i) : 0.0;
-        const double wyp = (j <= Ny - 2) ? G.W(k, j + 1, i) : 0.0;
-        if (j >= 1) Fb = to_yface(wym, w0, dym, dyj) * (0.5 * (G.V(km, j, i) + G.V(k, j, i)));
-        if (j <= Ny - 2) Ft = to_yface(w0, wyp, dyj, dyp) * (0.5 * (G.V(km, j + 1, i) + G.V(k, j + 1, i)));
-        const double dwv = (Ft - Fb) / dyj;
-        const double wzm = G.W(km, j, i), wzp = G.W(kp, j, i);
-        const double wcp = 0.5 * (w0 + wzp), wcm = 0.5 * (wzm + w0);
-        const double dww = (wcp * wcp - wcm * wcm) / dz;
-        const double Nq = -(dwu + dwv + dww);
-        const double Lq = lap_x_cell(wxm, w0, wxp) + lap_y_cell(wym, w0, wyp) + lap_z(wzm, w0, wzp);
-        const double Gp = (G.Pc(k, j, i) - G.Pc(km, j, i)) / dz;
-        const double R = dt * (cg * Nq + (cz != 0.0 ? cz * A.Nw[o] : 0.0) + ca * (nu * Lq - Gp));
-        A.Nw[o] = Nq;
-        A.dw[o] = R;
+        // ---------------- w at z-face k ----------------------------------------
+        {
+            const double w0 = C.w0, wxm = C.w_xm, wxp = C.w_xp;
+            // flux w u through the x-faces i and i+1 (u = 0 on the x-walls)
+            const double Hl = xm ? (0.5 * (wxm + w0)) * (0.5 * (b_u0 + C.u0)) : 0.0;
+            const double Hr = xp ? (0.5 * (w0 + wxp)) * (0.5 * (b_uxp + C.u_xp)) : 0.0;
+            const double dwu = (Hr - Hl) / dx;
+            // flux w v through the y-faces j and j+1 (v = 0 on the y-walls)
+            const double wym = C.w_ym, wyp = C.w_yp;
+            const double Fb = ym ? to_yface(wym, w0, dym, dyj) * (0.5 * (b_v0 + C.v0)) : 0.0;
+            const double Ft = yp ? to_yface(w0, wyp, dyj, dyp) * (0.5 * (b_vyp + C.v_yp)) : 0.0;
+            const double dwv = (Ft - Fb) / dyj;
+            const double wzm = b_w0, wzp = Nn.w0;
+            const double wcp = 0.5 * (w0 + wzp), wcm = 0.5 * (wzm + w0);
+            const double dww = (wcp * wcp - wcm * wcm) / dz;
+            const double Nq = -(dwu + dwv + dww);
+            const double Lq = lap_x_cell(wxm, w0, wxp) + lap_y_cell(wym, w0, wyp) + lap_z(wzm, w0, wzp);
+            const double Gp = (C.p0 - b_p0) / dz;
+            const double R = dt * (cg * Nq + cz * Nw_prev + ca * (nu * Lq - Gp));
+            A.Nw[o] = Nq;
+            A.dw[o] = R;
+        }
+        b_u0 = C.u0, b_uxp = C.u_xp, b_v0 = C.v0, b_vyp = C.v_yp, b_w0 = C.w0, b_p0 = C.p0;
+        C = Nn;
     }
 }
 
@@ -193,9 +239,12 @@ __global__ void __launch_bounds__(256) k_ns_pressure(double *p, const double *ph
 
 hipError_t launch_ns_rhs(const NsRhsArgs &A, hipStream_t s)
 {
-    const NsView G{A.u, A.v, A.w, A.p, A.dy, A.Nx, A.Ny, A.Nz};
-    const dim3 grid((unsigned)((A.Nx + 255) / 256), (unsigned)A.Ny, (unsigned)A.Nz);
-    hipLaunchKernelGGL(k_ns_rhs, grid, dim3(256), 0, s, G, A);
+    // z segments of about 48 planes (at most 8): enough workgroups that the
+    // last round of a launch is a small part of it, few enough that the
+    // plane each segment re-reads below its first is a small part of the reads
+    const int64_t nseg = std::max<int64_t>(1, std::min<int64_t>(8, A.Nz / 48));
+    const dim3 grid((unsigned)((A.Nx + 255) / 256), (unsigned)A.Ny, (unsigned)nseg);
+    hipLaunchKernelGGL(k_ns_rhs, grid, dim3(256), 0, s, A);
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 against the oracle's step (oracle/fractional_step.py), through the C ABI.
 
 * Two time steps (six Runge-Kutta sub-steps, the pressure carried between them)
-  from a divergence-free random state on grids with ragged workgroup tails:
+  from a divergence-free random state on grids with ragged workgroup tails and
+  with the z march split into segments (Nz = 144: three):
   u, v, w and p within 1e-12 per x-line of the oracle's (PDD sweeps at the
   same partition counts, PPT shifted solves).
 * The benchmark grid 2048 x 256 x 288 (x, y, z sweeps at P = 8, 4, 16; shifted
@@ -50,7 +51,7 @@ def _state(Nx, Ny, Nz, seed, amp=0.3):
 
 
 @pytest.mark.parametrize("Nx,Ny,Nz,P_adi,P_poi", [(64, 32, 24, (8, 4, 4), 4), (200, 48, 30, (8, 4, 2), 2),
-                                                   (256, 64, 48, (8, 4, 4), 4)])
+                                                   (256, 64, 48, (8, 4, 4), 4), (48, 16, 144, (4, 4, 4), 4)])
 def test_time_steps_match_the_oracle(T, ctx, orc, Nx, Ny, Nz, P_adi, P_poi):
     from oracle import fractional_step as fs
     from oracle.projection import project3d
