@@ -1869,7 +1869,10 @@ struct tri_ns_s {
     double *dy = nullptr, *ay = nullptr, *cy = nullptr, *lamz = nullptr, *lamx = nullptr;
     double *N[3] = {}, *D[3] = {};        // convection of the last sub-step; sweep right-hand sides
     double *phihat = nullptr, *phi = nullptr;
-    tri_plan plans[3] = {};
+    tri_plan plans[3] = {};               // per sub-step: the x and y sweeps of du, dv, dw
+    tri_plan zplans[3] = {};              // per sub-step: the z sweeps of du, dv, dw
+    bool fused = false;                   // the z sweeps add their solutions to u, v, w ...
+    Launch zacc[3][3];                    // ... with these launches [sub-step][component]
 };
 
 namespace {
@@ -1931,13 +1934,32 @@ void ns_lap_rows(int kind, int64_t n, double h, const std::vector<double> &dy, s
 
 void ns_release(tri_ns ns)
 {
-    for (tri_plan &p : ns->plans)
-        if (p) {
-            (void)tri_plan_destroy(p);
-            p = nullptr;
-        }
+    for (tri_plan *set : {ns->plans, ns->zplans})
+        for (int s = 0; s < 3; ++s)
+            if (set[s]) {
+                (void)tri_plan_destroy(set[s]);
+                set[s] = nullptr;
+            }
     if (ns->mem) (void)hipFree(ns->mem);
     delete ns;
+}
+
+// The accumulating form of a z sweep's launch: the strided kernel with one
+// line per lane (the two-lines-per-lane kernel has no accumulating
+// instance), the same partitions and factor tables.
+bool ns_acc_launch(const Launch &base, Launch &out)
+{
+    if (base.kind != 0 || base.refine) return false;
+    out = base;
+    SolveArgs &a = out.args;
+    if (a.lpl == 2) {
+        a.lpl = 1;
+        a.kc = 1;
+        a.Cs = a.m;
+        a.ngroups0 = (a.nb0 + 63) / 64;
+        out.chunk_max = pick_chunk(a.m);
+    }
+    return strided_acc_supported(TRI_PDD, out.chunk_max);
 }
 
 bool ns_overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -2055,22 +2077,41 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
         ns_release(ns);
         return fail(ctx, TRI_E_HIP, "ns_create: upload");
     }
-    // one plan per sub-step: the nine sweeps (x sweeps of the three fields form
-    // one dependency level, then y, then z)
+    // two plans per sub-step: the x and y sweeps of the three fields (two
+    // dependency levels), then their z sweeps.  Where every z sweep runs a
+    // strided kernel with an accumulating instance (one line per lane), the
+    // step launches those with u, v, w as targets, so that the velocity
+    // update u += du is the z sweep's store.  TRI_NS_FUSE=0 keeps the separate update kernel; =1
+    // makes ns_create fail with TRI_E_UNSUPPORTED where the z sweeps cannot
+    // add into the velocity.
+    ns->fused = true;
     for (int s = 0; s < 3; ++s) {
-        tri_item items[9];
+        tri_item xy[6], z[3];
         for (int q = 0; q < 9; ++q) {
             const int dir = q % 3, c = q / 3;
             const double *row = coef + ((int64_t)(s * 9 + q) * 3) * nmax;
-            items[q] = tri_item{dir, ns->D[c], Nx, Ny, Nz, row, row + nmax, row + 2 * nmax, nullptr,
-                                cfg->P_adi[dir], dir == 2 ? 1 : 0, TRI_PDD};
+            const tri_item it{dir, ns->D[c], Nx, Ny, Nz, row, row + nmax, row + 2 * nmax, nullptr,
+                              cfg->P_adi[dir], dir == 2 ? 1 : 0, TRI_PDD};
+            if (dir == 2) z[c] = it;
+            else xy[2 * c + dir] = it;
         }
-        st = tri_plan_create(ctx, items, 9, TRI_F64, &ns->plans[s]);
+        st = tri_plan_create(ctx, xy, 6, TRI_F64, &ns->plans[s]);
+        if (!st) st = tri_plan_create(ctx, z, 3, TRI_F64, &ns->zplans[s]);
         if (st) {
             const std::string why = ctx->last_error;
             ns_release(ns);
             return fail(ctx, st, "ns_create: sweep plan: %s", why.c_str());
         }
+        for (int c = 0; c < 3; ++c) {
+            const auto &item = ns->zplans[s]->items[(size_t)c];
+            if (item.launches.size() != 1 || !ns_acc_launch(item.launches[0], ns->zacc[s][c])) ns->fused = false;
+        }
+    }
+    const char *e = getenv("TRI_NS_FUSE");
+    if (e && atoi(e) == 0) ns->fused = false;
+    if (e && atoi(e) == 1 && !ns->fused) {
+        ns_release(ns);
+        return fail(ctx, TRI_E_UNSUPPORTED, "ns_create: a z sweep has no accumulating kernel instance");
     }
     *out = ns;
     return TRI_OK;
@@ -2116,7 +2157,24 @@ tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
         HIP_TRY(ctx, launch_ns_rhs(A, ctx->stream));
         tri_status st = tri_plan_execute(ns->plans[s]);
         if (st) return st;
-        HIP_TRY(ctx, launch_ns_update(u, v, w, ns->D[0], ns->D[1], ns->D[2], Nx, Ny, Nz, ctx->stream));
+        if (ns->fused) {
+            // z sweeps of du, dv, dw adding into u (faces 0..Nx-1 of each row),
+            // v (faces 0..Ny-1 of each plane) and w
+            double *tgt[3] = {u, v, w};
+            const int64_t aj[3] = {Ny * (Nx + 1), (Ny + 1) * Nx, Ny * Nx}, ab1[3] = {Nx + 1, Nx, Nx};
+            for (int c = 0; c < 3; ++c) {
+                Launch l = ns->zacc[s][c];
+                l.args.acc = tgt[c];
+                l.args.a_j = aj[c];
+                l.args.a_b0 = 1;
+                l.args.a_b1 = ab1[c];
+                HIP_TRY(ctx, run_launch(l, TRI_PDD, ctx->stream));
+            }
+        } else {
+            st = tri_plan_execute(ns->zplans[s]);
+            if (st) return st;
+            HIP_TRY(ctx, launch_ns_update(u, v, w, ns->D[0], ns->D[1], ns->D[2], Nx, Ny, Nz, ctx->stream));
+        }
         st = projection3d_step(ctx, u, v, w, ns->dx, ns->dy, ns->dz, ns->ay, ns->cy, ns->lamz, ns->lamx, ns->phihat,
                                ns->phi, Nx, Ny, Nz, ns->P_poisson);
         if (st) return st;

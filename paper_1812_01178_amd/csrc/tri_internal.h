@@ -104,6 +104,11 @@ struct SolveArgs {
     // persistent LDS-staged contiguous kernel
     int stage_stride;      // doubles between staging planes
     int lines_linear;      // 1: line L starts at L * s_b0 (s_b1 == nb0 * s_b0)
+    // strided kernel (one line per lane), accumulating instances only: the
+    // solution is added to acc[j a_j + b0 a_b0 + b1 a_b1] instead of being
+    // stored over d
+    double *acc;
+    int64_t a_j, a_b0, a_b1;
     // (the register-factor contiguous kernel uses C, Lp, LL, stage_stride,
     // nlines and lines_linear, one line per workgroup)
 };
@@ -154,6 +159,8 @@ struct GeneralArgs {
 // Host launchers (tri_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_factor(const MatSrc &src, const Tables &T, int *status, hipStream_t s);
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s);
+// whether launch_strided has an accumulating instance (a.acc set, lpl = 1)
+bool strided_acc_supported(int method, int chunk_max);
 size_t strided_lds_bytes(const SolveArgs &a);
 // Two lines per lane (adjacent lines, s_b0 = 1, 16-byte aligned pairs), one
 // chunk per partition (kc = 1), m <= 24.

@@ -291,7 +291,7 @@ __device__ __forceinline__ void strided_block(const SolveArgs &A, int64_t blk, i
     }
 }
 
-template <int CMAX, int METHOD, bool CHUNKED>
+template <int CMAX, int METHOD, bool CHUNKED, bool ACC = false>
 __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, double *lds)
 {
     const int lane = threadIdx.x & 63;
@@ -413,18 +413,29 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
         if (t < Cs) x[t] = x[t] - yl * Fv[t] - yr * Fw[t];
-    if (active) {
+    if (active && ACC) {
+        // add the solution to the accumulation target (its own layout)
+        const int64_t aj = A.a_j;
+        gdouble *__restrict__ q = (gdouble *)(A.acc + b0 * A.a_b0 + b1 * A.a_b1 + row0 * aj);
+        double z[CMAX];
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) z[t] = __builtin_nontemporal_load(q + t * aj);
+#pragma unroll
+        for (int t = 0; t < CMAX; ++t)
+            if (t < Cs) __builtin_nontemporal_store(z[t] + x[t], q + t * aj);
+    } else if (active) {
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) __builtin_nontemporal_store(x[t], p + t * sj);
     }
 }
 
-template <int CMAX, int METHOD, bool CHUNKED>
+template <int CMAX, int METHOD, bool CHUNKED, bool ACC = false>
 __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveArgs A)
 {
     extern __shared__ double lds[];
-    strided_solve<CMAX, METHOD, CHUNKED>(A, blockIdx.x, lds);
+    strided_solve<CMAX, METHOD, CHUNKED, ACC>(A, blockIdx.x, lds);
 }
 
 // ===========================================================================
@@ -534,6 +545,7 @@ hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStr
     const size_t lds = sizeof(double) * 2 * (size_t)a.P * 128;
     const dim3 grid((unsigned)blocks), block(64 * a.P);
     const bool pdd = method == TRI_PDD;
+    if (a.acc) return hipErrorInvalidValue;   // no accumulating instance (it would spill)
     switch (chunk_max) {
     case 8:
         if (pdd) hipLaunchKernelGGL((k_strided2<8, TRI_PDD>), grid, block, lds, s, a);
@@ -645,8 +657,37 @@ static hipError_t launch_strided_m(const SolveArgs &a, int cmax, hipStream_t s)
     }
 }
 
+// Accumulating instances (PDD, one line per lane, at most 24 rows a chunk):
+// x is added to a.acc in its own layout instead of being stored over a.d.
+// (With two lines per lane the added rows would not fit in registers.)
+template <int CMAX>
+static hipError_t launch_strided_acc_t(const SolveArgs &a, hipStream_t s)
+{
+    const int64_t blocks = a.ngroups0 * a.nb1;
+    if (a.kc > 1)
+        hipLaunchKernelGGL((k_strided<CMAX, TRI_PDD, true, true>), dim3((unsigned)blocks), dim3(64 * a.P * a.kc),
+                           strided_lds_bytes(a), s, a);
+    else
+        hipLaunchKernelGGL((k_strided<CMAX, TRI_PDD, false, true>), dim3((unsigned)blocks), dim3(64 * a.P),
+                           strided_lds_bytes(a), s, a);
+    return hipGetLastError();
+}
+
+bool strided_acc_supported(int method, int chunk_max)
+{
+    return method == TRI_PDD && (chunk_max == 8 || chunk_max == 16 || chunk_max == 24);
+}
+
 hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStream_t s)
 {
+    if (a.acc) {
+        if (!strided_acc_supported(method, chunk_max)) return hipErrorInvalidValue;
+        switch (chunk_max) {
+        case 8: return launch_strided_acc_t<8>(a, s);
+        case 16: return launch_strided_acc_t<16>(a, s);
+        default: return launch_strided_acc_t<24>(a, s);
+        }
+    }
     return method == TRI_PDD ? launch_strided_m<TRI_PDD>(a, chunk_max, s)
                              : launch_strided_m<TRI_PPT>(a, chunk_max, s);
 }

@@ -11,6 +11,8 @@ against the oracle's step (oracle/fractional_step.py), through the C ABI.
   step from a random, divergent state the velocity is divergence free to
   1e-13 of the initial divergence, the wall faces hold zero, and a step from
   rest with no pressure stays exactly at rest.
+* The velocity update fused into the z sweeps' stores gives the same bits as
+  the separate update kernel, on the small grids and the benchmark grid.
 * Set-up refusals: shapes the projection cannot take, partition counts the
   sweeps cannot take, overlapping fields.
 """
@@ -116,6 +118,40 @@ def test_benchmark_grid_step_is_divergence_free(T, ctx):
         assert all(torch.count_nonzero(t) == 0 for t in (u, v, w, p))
     finally:
         T.ns_destroy(ns)
+
+
+@pytest.mark.parametrize("Nx,Ny,Nz,P_adi,P_poi", [(64, 32, 24, (8, 4, 4), 4), (48, 16, 144, (4, 4, 4), 4),
+                                                   (2048, 256, 288, (8, 4, 16), 8)])
+def test_fused_update_matches_the_separate_update(T, ctx, monkeypatch, Nx, Ny, Nz, P_adi, P_poi):
+    """The z sweeps adding their solutions into u, v, w (TRI_NS_FUSE=1: required,
+    so ns_create fails if the fused form is not taken) give the same bits as
+    the z sweeps followed by the separate update kernel (TRI_NS_FUSE=0)."""
+    dx, dz = 1.0 / Nx, 1.0 / Nz
+    dy = np.diff(W.tanh_faces(Ny))
+    g = torch.Generator(device="cuda").manual_seed(5)
+    u0 = 0.1 * torch.randn((Nz, Ny, Nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u0[:, :, 0] = 0.0
+    u0[:, :, Nx] = 0.0
+    v0 = 0.1 * torch.randn((Nz, Ny + 1, Nx), dtype=torch.float64, device="cuda", generator=g)
+    v0[:, 0, :] = 0.0
+    v0[:, Ny, :] = 0.0
+    w0 = 0.1 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    p0 = 0.01 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    out = {}
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("TRI_NS_FUSE", fuse)
+        print(f"ns_step grid {Nx}x{Ny}x{Nz} TRI_NS_FUSE={fuse}", flush=True)
+        ns = T.ns_create(ctx, Nx, Ny, Nz, dx, dz, dy, 1e-3, 1e-3, P_adi, P_poi)
+        try:
+            f = [t.clone() for t in (u0, v0, w0, p0)]
+            for _ in range(2):
+                T.ns_step(ns, *f, ctx)
+            T.tri_sync_status(ctx)
+        finally:
+            T.ns_destroy(ns)
+        out[fuse] = f
+    for name, a, b in zip("uvwp", out["0"], out["1"]):
+        assert torch.equal(a, b), name
 
 
 def test_set_up_and_step_refusals(T, ctx):
