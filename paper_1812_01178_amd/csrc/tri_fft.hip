@@ -195,11 +195,21 @@ struct TwSplit {
     __device__ cplx operator()(int q) const { return cmul(hi[q >> 6], lo[q & 63]); }
 };
 
+// Element i of a line sits at slot i of buf[][L], or, with PAD, at slot
+// i + i/16: with few lines a workgroup (the streamwise rows) the first passes
+// write with lane strides of R elements, which without the padding fall on the
+// same LDS banks.
+template <bool PAD>
+__device__ __forceinline__ int fft_slot(int i)
+{
+    return PAD ? i + (i >> 4) : i;
+}
+
 // One Stockham pass of radix R over the M-point transforms of the L lines in
 // buf[M][L].  Butterfly j reads elements j + r M/R, twiddles element r by
 // W_{Ns R}^{(j mod Ns) r} = twM((j mod Ns) r M/(Ns R)), and writes output r to
 // (j/Ns) Ns R + (j mod Ns) + r Ns.
-template <int R, int IT, class TW>
+template <int R, int IT, class TW, bool PAD = false>
 __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, int ln, int tr, int T)
 {
     const int nb = M / R;
@@ -210,7 +220,7 @@ __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, 
         const int j = tr + it * T;
         if (j < nb) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[it][r] = buf[(j + r * nb) * L + ln];
+            for (int r = 0; r < R; ++r) v[it][r] = buf[fft_slot<PAD>(j + r * nb) * L + ln];
         }
     }
     __syncthreads();
@@ -234,7 +244,7 @@ __device__ inline void fft_pass(cplx *buf, const TW &twM, int M, int Ns, int L, 
             dft<R>(v[it]);
             const int d = (j / Ns) * Ns * R + jn;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[(d + r * Ns) * L + ln] = v[it][r];
+            for (int r = 0; r < R; ++r) buf[fft_slot<PAD>(d + r * Ns) * L + ln] = v[it][r];
         }
     }
     __syncthreads();
@@ -245,7 +255,7 @@ constexpr int kRadix8 = 1, kRadix16 = 2;
 // RSET: which long radices are compiled in (kRadix8, kRadix16 for 16 and 9),
 // only where the plan uses them: their registers would otherwise lower the
 // occupancy of every transform kernel.
-template <int L, int MMAX, int RSET, class TW>
+template <int L, int MMAX, int RSET, class TW, bool PAD = false>
 __device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, int ln, int tr)
 {
     constexpr int T = kFftThreads / L;
@@ -253,18 +263,21 @@ __device__ inline void fft_lines(cplx *buf, const TW &twM, const FftShape &S, in
     for (int s = 0; s < S.npass; ++s) {
         switch (S.radix[s]) {
         case 16:
-            if constexpr ((RSET & kRadix16) != 0) fft_pass<16, (MMAX / 16 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            if constexpr ((RSET & kRadix16) != 0)
+                fft_pass<16, (MMAX / 16 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T);
             break;
         case 9:
-            if constexpr ((RSET & kRadix16) != 0) fft_pass<9, (MMAX / 9 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            if constexpr ((RSET & kRadix16) != 0)
+                fft_pass<9, (MMAX / 9 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T);
             break;
         case 8:
-            if constexpr ((RSET & kRadix8) != 0) fft_pass<8, (MMAX / 8 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T);
+            if constexpr ((RSET & kRadix8) != 0)
+                fft_pass<8, (MMAX / 8 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T);
             break;
-        case 4: fft_pass<4, (MMAX / 4 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
-        case 2: fft_pass<2, (MMAX / 2 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
-        case 3: fft_pass<3, (MMAX / 3 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
-        default: fft_pass<5, (MMAX / 5 + T - 1) / T>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 4: fft_pass<4, (MMAX / 4 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 2: fft_pass<2, (MMAX / 2 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        case 3: fft_pass<3, (MMAX / 3 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T); break;
+        default: fft_pass<5, (MMAX / 5 + T - 1) / T, TW, PAD>(buf, twM, S.M, Ns, L, ln, tr, T); break;
         }
         Ns *= S.radix[s];
     }
@@ -560,8 +573,9 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
     constexpr int NPT = NMAX / T;
     extern __shared__ double lds_fft[];
     const int N = A.S.M;
-    cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [N][L]
-    cplx *lo = buf + (size_t)N * L;                  // W_N^t, t < 64
+    cplx *buf = reinterpret_cast<cplx *>(lds_fft);   // [N + N/16][L] (padded slots)
+    auto slot = [](int i) { return fft_slot<true>(i); };
+    cplx *lo = buf + (size_t)slot(N) * L;            // W_N^t, t < 64
     cplx *hi = lo + 64;                              // W_N^{64 s}
     const int nhi = (N + 63) / 64;
     cplx *q4 = hi + nhi;                             // W_{4N}^r, r < 4
@@ -591,7 +605,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
 #pragma unroll
         for (int u = 0; u < NPT; ++u) {
             const int n = tr + u * T;
-            if (n < N) buf[((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln] = {xv[u].x, xv[u].y};
+            if (n < N) buf[slot((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln] = {xv[u].x, xv[u].y};
         }
     } else {
         constexpr int KP = (NMAX / 2 + 1 + T - 1) / T;
@@ -612,23 +626,23 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
             const cplx wc = cconj(w4(k));                               // conj(W) = exp(+i pi k/(2N))
             const double P = xa[u].x, Q = xa[u].y, Pm = xb[u].x, Qm = xb[u].y;
             const cplx vk = cmul(wc, {P + Qm, Q - Pm});
-            buf[k * L + ln] = cconj(vk);                               // conjugated: inverse by forward passes
+            buf[slot(k) * L + ln] = cconj(vk);                         // conjugated: inverse by forward passes
             if (k > 0 && N - k != k) {
                 // V_{N-k} = conj(W^{N-k})... = i conj(wc) ((P_{N-k} + Q_k) + i (Q_{N-k} - P_k))
                 const cplx t = cmul(cconj(wc), {Pm + Q, Qm - P});
-                buf[(N - k) * L + ln] = cconj(cplx{-t.im, t.re});
+                buf[slot(N - k) * L + ln] = cconj(cplx{-t.im, t.re});
             }
         }
     }
     __syncthreads();
 
-    fft_lines<L, NMAX, kRadix8 | kRadix16>(buf, TwSplit{lo, hi}, A.S, ln, tr);
+    fft_lines<L, NMAX, kRadix8 | kRadix16, TwSplit, true>(buf, TwSplit{lo, hi}, A.S, ln, tr);
 
     if (!act) return;
     if (!INV) {
         for (int k = tr; k <= N / 2; k += T) {
-            const cplx vk = buf[k * L + ln];
-            const cplx vm = buf[(k == 0 ? 0 : N - k) * L + ln];
+            const cplx vk = buf[slot(k) * L + ln];
+            const cplx vm = buf[slot(k == 0 ? 0 : N - k) * L + ln];
             const cplx a = {0.5 * (vk.re + vm.re), 0.5 * (vk.im - vm.im)};
             const cplx b = {0.5 * (vk.im + vm.im), -0.5 * (vk.re - vm.re)};
             const cplx w = w4(k);
@@ -642,7 +656,7 @@ __global__ void __launch_bounds__(kFftThreads) k_dct_x(DctArgs A)
         for (int u = 0; u < NPT; ++u) {
             const int n = tr + u * T;
             if (n >= N) continue;
-            const cplx z = buf[((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln];
+            const cplx z = buf[slot((n & 1) ? N - 1 - (n >> 1) : (n >> 1)) * L + ln];
             __builtin_nontemporal_store(v2d{z.re * inv_n, -z.im * inv_n}, x + n);
         }
     }
@@ -732,7 +746,7 @@ static hipError_t launch_dct_t(const DctArgs &A, bool inverse, hipStream_t s)
 {
     const int64_t blocks = (A.rows + L - 1) / L;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-    const size_t lds = sizeof(cplx) * ((size_t)A.S.M * L + 64 + (A.S.M + 63) / 64 + 4);
+    const size_t lds = sizeof(cplx) * ((size_t)(A.S.M + A.S.M / 16) * L + 64 + (A.S.M + 63) / 64 + 4);
     if (inverse)
         hipLaunchKernelGGL((k_dct_x<L, NMAX, true>), dim3((unsigned)blocks), dim3(kFftThreads), lds, s, A);
     else

@@ -131,9 +131,11 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
     int64_t o = (k0 * Ny + j) * Nx + i;
     for (int64_t k = k0; k < k1; ++k, o += plane) {
         G.load(k + 1 < Nz ? k + 1 : 0, Nn);
-        const double Nu_prev = cz != 0.0 ? A.Nu[o] : 0.0;
-        const double Nv_prev = cz != 0.0 ? A.Nv[o] : 0.0;
-        const double Nw_prev = cz != 0.0 ? A.Nw[o] : 0.0;
+        // the previous convection terms are read once and the outputs written
+        // once (non-temporal); u, v, w, p are shared with the neighbour columns
+        const double Nu_prev = cz != 0.0 ? __builtin_nontemporal_load(A.Nu + o) : 0.0;
+        const double Nv_prev = cz != 0.0 ? __builtin_nontemporal_load(A.Nv + o) : 0.0;
+        const double Nw_prev = cz != 0.0 ? __builtin_nontemporal_load(A.Nw + o) : 0.0;
         // ---------------- u at x-face i (interior faces 1..Nx-1) ----------------
         {
             double R = 0.0, Nq = 0.0;
@@ -158,8 +160,8 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
                 const double Gp = (C.p0 - C.p_xm) / dx;
                 R = dt * (cg * Nq + cz * Nu_prev + ca * (nu * Lq - Gp));
             }
-            A.Nu[o] = Nq;
-            A.du[o] = R;
+            __builtin_nontemporal_store(Nq, A.Nu + o);
+            __builtin_nontemporal_store(R, A.du + o);
         }
         // ---------------- v at y-face j (interior faces 1..Ny-1) ----------------
         {
@@ -184,8 +186,8 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
                 const double Gp = (C.p0 - C.p_ym) / hj;
                 R = dt * (cg * Nq + cz * Nv_prev + ca * (nu * Lq - Gp));
             }
-            A.Nv[o] = Nq;
-            A.dv[o] = R;
+            __builtin_nontemporal_store(Nq, A.Nv + o);
+            __builtin_nontemporal_store(R, A.dv + o);
         }
         // ---------------- w at z-face k ----------------------------------------
         {
@@ -206,8 +208,8 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
             const double Lq = lap_x_cell(wxm, w0, wxp) + lap_y_cell(wym, w0, wyp) + lap_z(wzm, w0, wzp);
             const double Gp = (C.p0 - b_p0) / dz;
             const double R = dt * (cg * Nq + cz * Nw_prev + ca * (nu * Lq - Gp));
-            A.Nw[o] = Nq;
-            A.dw[o] = R;
+            __builtin_nontemporal_store(Nq, A.Nw + o);
+            __builtin_nontemporal_store(R, A.dw + o);
         }
         b_u0 = C.u0, b_uxp = C.u_xp, b_v0 = C.v0, b_vyp = C.v_yp, b_w0 = C.w0, b_p0 = C.p0;
         C = Nn;
