@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "tri_internal.h"
+#include "tri_ns.h"
 
 using namespace tri;
 
@@ -1867,6 +1868,7 @@ struct tri_ns_s {
     int P_poisson = 8;
     void *mem = nullptr;                  // metric, sweep coefficients and work fields, one allocation
     double *dy = nullptr, *ay = nullptr, *cy = nullptr, *lamz = nullptr, *lamx = nullptr;
+    double *ycoef = nullptr;              // [Ny][NS_YCOEF] constants of the momentum right-hand side
     double *N[3] = {}, *D[3] = {};        // convection of the last sub-step; sweep right-hand sides
     double *phihat = nullptr, *phi = nullptr;
     tri_plan plans[3] = {};               // per sub-step: the x and y sweeps of du, dv, dw
@@ -1944,6 +1946,33 @@ void ns_release(tri_ns ns)
     delete ns;
 }
 
+}  // namespace
+
+void tri::ns_ycoef_row(const double *dy, int64_t Ny, int64_t j, double *out)
+{
+    const double dyj = dy[j], dym = j > 0 ? dy[j - 1] : 0.0, dyp = j < Ny - 1 ? dy[j + 1] : 0.0;
+    const bool ym = j >= 1, yp = j <= Ny - 2;
+    const double hj = 0.5 * (dym + dyj);
+    const double ifj = 1.0 / (dym + dyj), ifj1 = 1.0 / (dyj + dyp);
+    out[0] = 1.0 / dyj;
+    out[1] = 1.0 / hj;
+    out[2] = dyj * ifj;
+    out[3] = dym * ifj;
+    out[4] = dyp * ifj1;
+    out[5] = dyj * ifj1;
+    const double ly_lo = ym ? 1.0 / (dyj * (0.5 * (dym + dyj))) : 0.0;
+    const double ly_up = yp ? 1.0 / (dyj * (0.5 * (dyj + dyp))) : 0.0;
+    out[6] = ly_lo;
+    out[7] = -(ly_lo + ly_up) - (j == 0 ? 2.0 / (dyj * dyj) : 0.0);
+    out[8] = ly_up;
+    const double lv_lo = ym ? 1.0 / (hj * dym) : 0.0, lv_upf = ym ? 1.0 / (hj * dyj) : 0.0;
+    out[9] = lv_lo;
+    out[10] = -(lv_lo + lv_upf);
+    out[11] = yp ? lv_upf : 0.0;
+}
+
+namespace {
+
 // The accumulating form of a z sweep's launch: the strided kernel with one
 // line per lane (the two-lines-per-lane kernel has no accumulating
 // instance), the same partitions and factor tables.
@@ -2011,9 +2040,9 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
     const int64_t cells = Nx * Ny * Nz, Nk = Nz / 2 + 1;
     const int64_t nmax = std::max(Nx, std::max(Ny, Nz));
     // layout (doubles): dy ay cy [Ny each], lamz [Nk], lamx [Nx], coefficients
-    // [3 sub-steps][9 sweeps][3][nmax], then 16-byte aligned: N[3], D[3], phi
-    // [cells each], phihat [2 Nk Ny Nx]
-    const int64_t head = 3 * Ny + Nk + Nx + 3 * 9 * 3 * nmax;
+    // [3 sub-steps][9 sweeps][3][nmax], ycoef [Ny][NS_YCOEF], then 16-byte
+    // aligned: N[3], D[3], phi [cells each], phihat [2 Nk Ny Nx]
+    const int64_t head = 3 * Ny + Nk + Nx + 3 * 9 * 3 * nmax + NS_YCOEF * Ny;
     const int64_t head_al = (head + 31) / 32 * 32;
     const size_t bytes = sizeof(double) * (size_t)(head_al + 7 * cells + 2 * Nk * Ny * Nx);
     if (hipMalloc(&ns->mem, bytes) != hipSuccess) {
@@ -2028,6 +2057,7 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
     ns->lamz = base + 3 * Ny;
     ns->lamx = ns->lamz + Nk;
     double *coef = ns->lamx + Nx;
+    ns->ycoef = coef + 3 * 9 * 3 * nmax;
     double *fields = base + head_al;
     for (int c = 0; c < 3; ++c) {
         ns->N[c] = fields + (int64_t)c * cells;
@@ -2073,6 +2103,8 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
             }
         }
     }
+    for (int64_t j = 0; j < Ny; ++j)
+        ns_ycoef_row(dy.data(), Ny, j, host.data() + coef_off + 3 * 9 * 3 * nmax + NS_YCOEF * j);
     if (hipMemcpy(base, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
         ns_release(ns);
         return fail(ctx, TRI_E_HIP, "ns_create: upload");
@@ -2137,12 +2169,14 @@ tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
         A.v = v;
         A.w = w;
         A.p = p;
-        A.dy = ns->dy;
+        A.ycoef = ns->ycoef;
         A.Nx = Nx;
         A.Ny = Ny;
         A.Nz = Nz;
-        A.dx = ns->dx;
-        A.dz = ns->dz;
+        A.idx = 1.0 / ns->dx;
+        A.idz = 1.0 / ns->dz;
+        A.idx2 = 1.0 / (ns->dx * ns->dx);
+        A.idz2 = 1.0 / (ns->dz * ns->dz);
         A.dt = ns->dt;
         A.nu = ns->nu;
         A.gamma = kRkGamma[s];

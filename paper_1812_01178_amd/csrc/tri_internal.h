@@ -224,22 +224,6 @@ hipError_t launch_fft(const FftArgs &A, int kind, hipStream_t s);
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,
                          hipStream_t s);
 
-// ---------------------------------------------------------------------------
-// Fractional-step time step (tri_ns.hip): the momentum right-hand side of one
-// Runge-Kutta sub-step, the velocity update and the pressure update.
-struct NsRhsArgs {
-    const double *u = nullptr, *v = nullptr, *w = nullptr, *p = nullptr, *dy = nullptr;
-    int64_t Nx = 0, Ny = 0, Nz = 0;
-    double dx = 0.0, dz = 0.0, dt = 0.0, nu = 0.0;
-    double gamma = 0.0, zeta = 0.0, alpha = 0.0;     // the sub-step's coefficients
-    double *Nu = nullptr, *Nv = nullptr, *Nw = nullptr;   // convection: previous in, this sub-step's out
-    double *du = nullptr, *dv = nullptr, *dw = nullptr;   // right-hand sides of the ADI sweeps
-};
-hipError_t launch_ns_rhs(const NsRhsArgs &A, hipStream_t s);
-hipError_t launch_ns_update(double *u, double *v, double *w, const double *du, const double *dv, const double *dw,
-                            int64_t Nx, int64_t Ny, int64_t Nz, hipStream_t s);
-hipError_t launch_ns_pressure(double *p, const double *phi, double scale, int64_t n, hipStream_t s);
-
 // Reference copy of n doubles (16-byte aligned, disjoint or equal ranges).
 hipError_t launch_stream_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 size_t contig_reg_lds_bytes(const SolveArgs &a);

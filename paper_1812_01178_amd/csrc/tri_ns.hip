@@ -25,7 +25,7 @@
 
 #include <algorithm>
 
-#include "tri_internal.h"
+#include "tri_ns.h"
 
 namespace tri {
 
@@ -77,11 +77,6 @@ struct NsColumn {
     }
 };
 
-// cell-centred quantity q(j) interpolated to the interior y-face j (1..Ny-1)
-__device__ __forceinline__ double to_yface(double qm, double q, double dym, double dyj)
-{
-    return (dyj * qm + dym * q) / (dym + dyj);
-}
 
 // One thread per column (i, j), marching in z over the planes of its segment
 // (blockIdx.z; the segments split the periodic z range evenly) with the
@@ -97,27 +92,21 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
     const int64_t j = blockIdx.y;
     if (i >= Nx) return;
     const NsColumn G{A.u, A.v, A.w, A.p, Nx, Ny, i, j};
-    const double dx = A.dx, dz = A.dz, idx2 = 1.0 / (dx * dx), idz2 = 1.0 / (dz * dz);
-    const double dyj = A.dy[j];
-    const double dym = (j > 0) ? A.dy[j - 1] : 0.0;          // dy_{j-1}
-    const double dyp = (j < Ny - 1) ? A.dy[j + 1] : 0.0;     // dy_{j+1}
-    const double hj = 0.5 * (dym + dyj);
     const double cg = A.gamma, cz = A.zeta, ca = A.alpha, nu = A.nu, dt = A.dt;
+    const double idx = A.idx, idz = A.idz, idx2 = A.idx2, idz2 = A.idz2;
     const bool xm = i >= 1, xp = i <= Nx - 2, ym = j >= 1, yp = j <= Ny - 2;
-
-    // y second difference of a cell-centred component (no-slip wall below cell
-    // 0, zero flux through the top): lo q_{j-1} + diag q_j + up q_{j+1}
-    const double ly_lo = ym ? 1.0 / (dyj * (0.5 * (dym + dyj))) : 0.0;
-    const double ly_up = yp ? 1.0 / (dyj * (0.5 * (dyj + dyp))) : 0.0;
-    const double ly_dg = -(ly_lo + ly_up) - ((j == 0) ? 2.0 / (dyj * dyj) : 0.0);
+    // this row's constants of the y mesh (uniform: scalar loads), so that the
+    // march multiplies where the definitions divide
+    const double *__restrict__ yc = A.ycoef + j * NS_YCOEF;
+    const double idyj = yc[0], ihj = yc[1], fm = yc[2], fp = yc[3], gm = yc[4], gp = yc[5];
+    const double ly_lo = yc[6], ly_dg = yc[7], ly_up = yc[8], lv_lo = yc[9], lv_dg = yc[10], lv_up = yc[11];
+    auto face_j = [&](double qm, double q) { return fm * qm + fp * q; };      // q at y-face j
+    auto face_j1 = [&](double q, double qp) { return gm * q + gp * qp; };     // q at y-face j+1
     auto lap_y_cell = [&](double qm, double q, double qp) { return ly_lo * qm + ly_dg * q + ly_up * qp; };
     // x second difference of a cell-centred component (slip walls at both ends)
     const double lx_lo = xm ? idx2 : 0.0, lx_up = xp ? idx2 : 0.0, lx_dg = -(lx_lo + lx_up);
     auto lap_x_cell = [&](double qm, double q, double qp) { return lx_lo * qm + lx_dg * q + lx_up * qp; };
     auto lap_z = [&](double qm, double q, double qp) { return idz2 * qm + (-2.0 * idz2) * q + idz2 * qp; };
-    // y second difference of v on the faces (walls at faces 0 and Ny, held 0)
-    const double lv_lo = ym ? 1.0 / (hj * dym) : 0.0, lv_upf = ym ? 1.0 / (hj * dyj) : 0.0;
-    const double lv_up = yp ? lv_upf : 0.0;
 
     // planes k0 .. k1-1 of this segment; plane k0 - 1 (periodic) values still
     // needed: u, u_xp, v, v_yp, w, p
@@ -142,22 +131,22 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
             if (xm) {
                 const double u0 = C.u0, uxm = C.u_xm, uxp = C.u_xp;
                 const double ucp = 0.5 * (u0 + uxp), ucm = 0.5 * (uxm + u0);
-                const double duu = (ucp * ucp - ucm * ucm) / dx;
+                const double duu = (ucp * ucp - ucm * ucm) * idx;
                 // flux u v through the y-faces j (bottom) and j+1 (top) of the cell
                 const double uym = C.u_ym, uyp = C.u_yp;
-                const double Fb = ym ? to_yface(uym, u0, dym, dyj) * (0.5 * (C.v_xm + C.v0)) : 0.0;
-                const double Ft = yp ? to_yface(u0, uyp, dyj, dyp) * (0.5 * (C.v_ypxm + C.v_yp)) : 0.0;
-                const double duv = (Ft - Fb) / dyj;
+                const double Fb = ym ? face_j(uym, u0) * (0.5 * (C.v_xm + C.v0)) : 0.0;
+                const double Ft = yp ? face_j1(u0, uyp) * (0.5 * (C.v_ypxm + C.v_yp)) : 0.0;
+                const double duv = (Ft - Fb) * idyj;
                 // flux u w through the z-faces k and k+1
                 const double uzm = b_u0, uzp = Nn.u0;
                 const double Gk = (0.5 * (uzm + u0)) * (0.5 * (C.w_xm + C.w0));
                 const double Gk1 = (0.5 * (u0 + uzp)) * (0.5 * (Nn.w_xm + Nn.w0));
-                const double duw = (Gk1 - Gk) / dz;
+                const double duw = (Gk1 - Gk) * idz;
                 Nq = -(duu + duv + duw);
                 // u_Nx (the far wall) is 0, so the x row needs no special case
                 const double Lq = (idx2 * uxm + (-2.0 * idx2) * u0 + idx2 * (xp ? uxp : 0.0)) +
                                   lap_y_cell(uym, u0, uyp) + lap_z(uzm, u0, uzp);
-                const double Gp = (C.p0 - C.p_xm) / dx;
+                const double Gp = (C.p0 - C.p_xm) * idx;
                 R = dt * (cg * Nq + cz * Nu_prev + ca * (nu * Lq - Gp));
             }
             __builtin_nontemporal_store(Nq, A.Nu + o);
@@ -169,21 +158,21 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
             if (ym) {
                 const double v0 = C.v0, vxm = C.v_xm, vxp = C.v_xp;
                 // flux v u through the x-faces i and i+1 (u = 0 on the x-walls)
-                const double Hl = xm ? (0.5 * (vxm + v0)) * to_yface(C.u_ym, C.u0, dym, dyj) : 0.0;
-                const double Hr = xp ? (0.5 * (v0 + vxp)) * to_yface(C.u_ymxp, C.u_xp, dym, dyj) : 0.0;
-                const double dvu = (Hr - Hl) / dx;
+                const double Hl = xm ? (0.5 * (vxm + v0)) * face_j(C.u_ym, C.u0) : 0.0;
+                const double Hr = xp ? (0.5 * (v0 + vxp)) * face_j(C.u_ymxp, C.u_xp) : 0.0;
+                const double dvu = (Hr - Hl) * idx;
                 const double vym = C.v_ym, vyp = C.v_yp;
                 const double vcp = 0.5 * (v0 + vyp), vcm = 0.5 * (vym + v0);
-                const double dvv = (vcp * vcp - vcm * vcm) / hj;
+                const double dvv = (vcp * vcp - vcm * vcm) * ihj;
                 // flux v w through the z-faces k and k+1
                 const double vzm = b_v0, vzp = Nn.v0;
-                const double Gk = (0.5 * (vzm + v0)) * to_yface(C.w_ym, C.w0, dym, dyj);
-                const double Gk1 = (0.5 * (v0 + vzp)) * to_yface(Nn.w_ym, Nn.w0, dym, dyj);
-                const double dvw = (Gk1 - Gk) / dz;
+                const double Gk = (0.5 * (vzm + v0)) * face_j(C.w_ym, C.w0);
+                const double Gk1 = (0.5 * (v0 + vzp)) * face_j(Nn.w_ym, Nn.w0);
+                const double dvw = (Gk1 - Gk) * idz;
                 Nq = -(dvu + dvv + dvw);
-                const double Ly = lv_lo * vym + (-(lv_lo + lv_upf)) * v0 + lv_up * vyp;
+                const double Ly = lv_lo * vym + lv_dg * v0 + lv_up * vyp;
                 const double Lq = lap_x_cell(vxm, v0, vxp) + Ly + lap_z(vzm, v0, vzp);
-                const double Gp = (C.p0 - C.p_ym) / hj;
+                const double Gp = (C.p0 - C.p_ym) * ihj;
                 R = dt * (cg * Nq + cz * Nv_prev + ca * (nu * Lq - Gp));
             }
             __builtin_nontemporal_store(Nq, A.Nv + o);
@@ -195,18 +184,18 @@ __global__ void __launch_bounds__(256) k_ns_rhs(const NsRhsArgs A)
             // flux w u through the x-faces i and i+1 (u = 0 on the x-walls)
             const double Hl = xm ? (0.5 * (wxm + w0)) * (0.5 * (b_u0 + C.u0)) : 0.0;
             const double Hr = xp ? (0.5 * (w0 + wxp)) * (0.5 * (b_uxp + C.u_xp)) : 0.0;
-            const double dwu = (Hr - Hl) / dx;
+            const double dwu = (Hr - Hl) * idx;
             // flux w v through the y-faces j and j+1 (v = 0 on the y-walls)
             const double wym = C.w_ym, wyp = C.w_yp;
-            const double Fb = ym ? to_yface(wym, w0, dym, dyj) * (0.5 * (b_v0 + C.v0)) : 0.0;
-            const double Ft = yp ? to_yface(w0, wyp, dyj, dyp) * (0.5 * (b_vyp + C.v_yp)) : 0.0;
-            const double dwv = (Ft - Fb) / dyj;
+            const double Fb = ym ? face_j(wym, w0) * (0.5 * (b_v0 + C.v0)) : 0.0;
+            const double Ft = yp ? face_j1(w0, wyp) * (0.5 * (b_vyp + C.v_yp)) : 0.0;
+            const double dwv = (Ft - Fb) * idyj;
             const double wzm = b_w0, wzp = Nn.w0;
             const double wcp = 0.5 * (w0 + wzp), wcm = 0.5 * (wzm + w0);
-            const double dww = (wcp * wcp - wcm * wcm) / dz;
+            const double dww = (wcp * wcp - wcm * wcm) * idz;
             const double Nq = -(dwu + dwv + dww);
             const double Lq = lap_x_cell(wxm, w0, wxp) + lap_y_cell(wym, w0, wyp) + lap_z(wzm, w0, wzp);
-            const double Gp = (C.p0 - b_p0) / dz;
+            const double Gp = (C.p0 - b_p0) * idz;
             const double R = dt * (cg * Nq + cz * Nw_prev + ca * (nu * Lq - Gp));
             __builtin_nontemporal_store(Nq, A.Nw + o);
             __builtin_nontemporal_store(R, A.dw + o);

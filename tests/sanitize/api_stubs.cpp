@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "tri_internal.h"
+#include "tri_ns.h"
 
 int g_launches = 0;      // kernel launches since start
 int g_mallocs = 0;       // hipMalloc calls since start
