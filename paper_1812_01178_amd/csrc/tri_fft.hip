@@ -347,10 +347,12 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
         // by two cells (plain loads, so that the second read finds it cached).
         const int64_t sv = A.lines + A.Nx;          // (Ny+1) Nx
         const int64_t jg = act ? g / A.Nx : 0;
-        const double dyj = act ? A.dy[jg] : 1.0;
+        // reciprocals once a thread (the rows then multiply; FP64 division is
+        // a long instruction sequence)
         // u[Nz][Ny][Nx+1] on the x-faces (3-D projection only): face i of cell
         // (j, i) at j (Nx+1) + i in its plane
         constexpr bool has_u = DIV == 2;
+        const double idyj = 1.0 / (act ? A.dy[jg] : 1.0), idz = 1.0 / A.dz, idx = has_u ? 1.0 / A.dx : 0.0;
         const int64_t su = A.lines + (A.lines / A.Nx), ug = g + jg;
 #pragma unroll
         for (int b0 = 0; b0 < NPT; b0 += NB) {
@@ -380,8 +382,8 @@ __global__ void __launch_bounds__(kFftThreads) k_rfft_z(FftArgs A)
                 if (b0 + u < NPT && k < Nz) {
                     double x = 0.0;
                     if (act) {
-                        x = (v1[u] - v0[u]) / dyj + (w1[u] - w0[u]) / A.dz;
-                        if (has_u) x = (u1[u] - u0[u]) / A.dx + x;
+                        x = (v1[u] - v0[u]) * idyj + (w1[u] - w0[u]) * idz;
+                        if (has_u) x = (u1[u] - u0[u]) * idx + x;
                     }
                     bd[((k >> 1) * L + ln) * 2 + (k & 1)] = x;
                 }
@@ -491,7 +493,7 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
     fft_lines<L, MMAX, RSET>(buf, TwFull{twM}, A.S, ln, tr);
 
     if (!act) return;
-    const double inv_m = 1.0 / M;
+    const double inv_m = 1.0 / M, idz = CORR ? 1.0 / A.dz : 0.0;
     const double *bd = lds_fft;
     // x_{2n} = Re z_n, x_{2n+1} = Im z_n, z = conj(buf)/M
     auto xval = [&](int k) {
@@ -506,7 +508,7 @@ __global__ void __launch_bounds__(kFftThreads) k_irfft_z(FftArgs A)
         __builtin_nontemporal_store(x, A.x_out + k * A.lines + g);
         if (CORR) {
             const double xm = xval(k == 0 ? Nz - 1 : k - 1);
-            __builtin_nontemporal_store(wpre[u] - (x - xm) / A.dz, A.w_io + k * A.lines + g);
+            __builtin_nontemporal_store(wpre[u] - (x - xm) * idz, A.w_io + k * A.lines + g);
         }
     }
 }
