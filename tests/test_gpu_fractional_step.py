@@ -14,6 +14,8 @@ against the oracle's step (oracle/fractional_step.py), through the C ABI.
   rest with no pressure stays exactly at rest.
 * The velocity update fused into the z sweeps' stores gives the same bits as
   the separate update kernel, on the small grids and the benchmark grid.
+* A whole time step records into a HIP graph and its replays give the eager
+  step's bits.
 * Set-up refusals: shapes the projection cannot take, partition counts the
   sweeps cannot take, overlapping fields.
 """
@@ -164,6 +166,51 @@ def test_fused_update_matches_the_separate_update(T, ctx, monkeypatch, Nx, Ny, N
         out[fuse] = f
     for name, a, b in zip("uvwp", out["0"], out["1"]):
         assert torch.equal(a, b), name
+
+
+def test_time_step_replays_from_a_hip_graph(T, ctx):
+    """ns_step allocates nothing and never synchronises, so a whole time step (three
+    sub-steps: kernels, sweep plans, the projection) records into a HIP graph; three
+    replays, with eager restores and synchronisations between them, give the eager
+    step's bits."""
+    Nx, Ny, Nz = 96, 32, 48
+    dy = np.diff(W.tanh_faces(Ny))
+    g = torch.Generator(device="cuda").manual_seed(9)
+    u0 = 0.1 * torch.randn((Nz, Ny, Nx + 1), dtype=torch.float64, device="cuda", generator=g)
+    u0[:, :, 0] = 0.0
+    u0[:, :, Nx] = 0.0
+    v0 = 0.1 * torch.randn((Nz, Ny + 1, Nx), dtype=torch.float64, device="cuda", generator=g)
+    v0[:, 0, :] = 0.0
+    v0[:, Ny, :] = 0.0
+    w0 = 0.1 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    p0 = 0.01 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    init = (u0, v0, w0, p0)
+    ns = T.ns_create(ctx, Nx, Ny, Nz, 1.0 / Nx, 1.0 / Nz, dy, 1e-3, 1e-3, (8, 4, 4), 4)
+    f = [t.clone() for t in init]
+    try:
+        T.ns_step(ns, *f, ctx)
+        T.tri_sync_status(ctx)
+        ref = [t.clone() for t in f]
+        for t, t0 in zip(f, init):
+            t.copy_(t0)
+        side = torch.cuda.Stream()
+        graph = torch.cuda.CUDAGraph()
+        T.tri_set_stream(ctx, side.cuda_stream)
+        with torch.cuda.graph(graph, stream=side):
+            T.ns_step(ns, *f, ctx)
+        T.tri_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+        for rep in range(3):
+            for t, t0 in zip(f, init):
+                t.copy_(t0)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            for name, got, want in zip("uvwp", f, ref):
+                assert torch.equal(got, want), (rep, name)
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+        T.ns_destroy(ns)
 
 
 def test_set_up_and_step_refusals(T, ctx):
