@@ -542,9 +542,9 @@ def refine_section(T, ctx, stream, u, phi, du0, dphi0, dcoef, day, dcy, dlam, co
     solution, so it is ~1e-16 like an FP64 solve)."""
     import torch
     # the refined result is the exact solution whatever the inner solver's
-    # partition count; the refinement kernel takes at most 8 wavefronts of
-    # more than 8 rows, and at P = 8 (one row per lane group) its strided
-    # form runs fastest, so the wall-normal and spanwise lines use P = 8 here
+    # partition count; the refinement kernel takes up to 16 wavefronts of up
+    # to 16 rows or up to 8 wavefronts of up to 40 rows, and the wall-normal
+    # and spanwise lines run fastest at P = 8 (16-row and 36-row chunks)
     items = [(nm, d, REFINE_P.get(nm, P), per, meth) for nm, d, P, per, meth in ITEMS]
     plans, descr = {}, {}
     for name, direction, P, per, meth in items:

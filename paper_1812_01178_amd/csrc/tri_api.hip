@@ -128,13 +128,15 @@ int env_int(const char *name, int dflt)
 
 // Chunks per partition for the refinement kernel, which keeps d and x in
 // FP64 and the work vector in FP32 (5 VGPRs per row): chunks of at most 16
-// rows when possible, at most 40; more than 8 rows need P*kc <= 8.
+// rows when possible, at most 40; more than 16 rows need P*kc <= 8.
 int pick_kc_refine(int m, int P, int want_kc)
 {
     auto valid = [&](int kc) {
         if (kc < 1 || m % kc != 0 || P * kc > 16) return false;
         const int c = m / kc;
-        return c <= 40 && (c <= 8 || P * kc <= 8);
+        // up to 16 wavefronts of up to 16 rows (128 VGPRs a lane), else up to
+        // 8 wavefronts of up to 40 rows
+        return c <= 40 && (c <= 16 || P * kc <= 8);
     };
     if (want_kc > 0) return valid(want_kc) ? want_kc : 0;
     for (int kc = 1; kc <= 16; ++kc)

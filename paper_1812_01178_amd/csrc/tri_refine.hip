@@ -283,7 +283,7 @@ __device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const R
 }
 
 template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
+__global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
 {
     extern __shared__ double lds[];
     strided_refine_solve<CMAX, METHOD>(A, R, blockIdx.x, lds);
@@ -292,7 +292,7 @@ __global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine(const 
 // Ragged batch of refinement solves in one launch (see k_strided_batch):
 // every entry runs with this instance's CMAX, method and P * kc.
 template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(CMAX > 8 ? 512 : 1024) k_strided_refine_batch(const BatchEntry *__restrict__ E,
+__global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine_batch(const BatchEntry *__restrict__ E,
                                                                                   int count)
 {
     extern __shared__ double lds[];

@@ -66,7 +66,7 @@ def test_fullsize_adi_sweep(T, ctx, orc, field, direction, P, prec):
     item = dict(kind=direction, field=u, Nx=NX, Ny=NY, Nz=NZ, a=dev(a), b=dev(b), c=dev(c), P=P,
                 periodic=int(per), method=T.TRI_PDD)
     if prec == "refine" and P == 16:
-        # the refinement kernel takes at most 8 wavefronts of more than 8 rows
+        # the refinement kernel takes at most 8 wavefronts of more than 16 rows
         with pytest.raises(T.TriError) as e:
             T.tri_plan_create(ctx, [item], prec=T.TRI_F32_REFINE)
         assert e.value.status == T.TRI_E_UNSUPPORTED
