@@ -60,7 +60,13 @@ def _poisson_exact(orc, phihat, ay, cy, lam):
     (1, 256, 4, False, "stretched"), (2, 288, 4, True, "periodic"), (1, 64, 4, False, "random"),
     (2, 96, 2, True, "random"), (1, 200, 8, False, "random"),
     (0, 2048, 8, False, "uniform"), (0, 512, 4, False, "random"), (0, 1024, 16, True, "random"),
-    (0, 256, 8, False, "random")])
+    (0, 256, 8, False, "random"),
+    # sixteen wavefronts of 16-row chunks in one workgroup: P = 16, one chunk a
+    # partition; P = 8, two chunks; periodic (dominant rows: with PDD as the
+    # inner solver the iteration contracts by about the dropped entries, which
+    # at 16 rows a partition of the stretched momentum rows are too large for
+    # three refinements; the status says so)
+    (1, 256, 16, False, "random"), (1, 256, 8, False, "random"), (2, 256, 16, True, "random")])
 def test_refine_sweeps_match_exact(T, ctx, orc, method, direction, n, P, per, coef):
     shape = {0: (5, 7, n), 1: (3, n, 130), 2: (n, 4, 70)}[direction]
     Nz, Ny, Nx = shape
