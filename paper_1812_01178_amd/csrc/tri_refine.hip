@@ -44,13 +44,14 @@ __device__ __forceinline__ int line_exponent(double v)
     return min(1000, max(-1000, ilogb(v)));
 }
 
-template <int CMAX, int METHOD>
+// EXACT: the chunk has exactly CMAX rows (no row guards).
+template <int CMAX, int METHOD, bool EXACT = false>
 __device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const RefineArgs &R, int64_t blk,
                                                      double *lds)
 {
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int kc = A.kc, Cs = A.Cs;
+    const int kc = A.kc, Cs = EXACT ? CMAX : A.Cs;
     const int r = w / kc, s = w - r * kc;
     const int P = A.P, m = A.m;
     const int nw = P * kc;
@@ -227,15 +228,18 @@ __device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const R
         double yl, yr;
         interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
         double dmax = 0.0, xmax = 0.0;
+        bool nan = false;                       // (fmax drops NaNs: they are counted apart)
         const double unscale = ldexp(1.0, E);
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) {
                 const double delta = ((double)e[t] - yl * (double)Fv[t] - yr * (double)Fw[t]) * unscale;
                 xv[t] += delta;
-                dmax = nanmax(dmax, fabs(delta));
-                xmax = nanmax(xmax, fabs(xv[t]));
+                nan |= !(delta == delta) || !(xv[t] == xv[t]);
+                dmax = fmax(dmax, fabs(delta));
+                xmax = fmax(xmax, fabs(xv[t]));
             }
+        if (nan) dmax = xmax = __builtin_nan("");
         // ---- convergence of every line of the workgroup ------------------
         nrm[(w * 2 + 0) * 64 + lane] = dmax;
         nrm[(w * 2 + 1) * 64 + lane] = xmax;
@@ -282,11 +286,11 @@ __device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const R
     }
 }
 
-template <int CMAX, int METHOD>
+template <int CMAX, int METHOD, bool EXACT>
 __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine(const SolveArgs A, const RefineArgs R)
 {
     extern __shared__ double lds[];
-    strided_refine_solve<CMAX, METHOD>(A, R, blockIdx.x, lds);
+    strided_refine_solve<CMAX, METHOD, EXACT>(A, R, blockIdx.x, lds);
 }
 
 // Ragged batch of refinement solves in one launch (see k_strided_batch):
@@ -339,8 +343,12 @@ template <int CMAX, int METHOD>
 static hipError_t launch_refine_t(const SolveArgs &a, const RefineArgs &R, hipStream_t s)
 {
     const int64_t blocks = a.ngroups0 * a.nb1;
-    hipLaunchKernelGGL((k_strided_refine<CMAX, METHOD>), dim3((unsigned)blocks), dim3(64 * a.P * a.kc),
-                       strided_refine_lds_bytes(a), s, a, R);
+    if (a.Cs == CMAX)
+        hipLaunchKernelGGL((k_strided_refine<CMAX, METHOD, true>), dim3((unsigned)blocks), dim3(64 * a.P * a.kc),
+                           strided_refine_lds_bytes(a), s, a, R);
+    else
+        hipLaunchKernelGGL((k_strided_refine<CMAX, METHOD, false>), dim3((unsigned)blocks), dim3(64 * a.P * a.kc),
+                           strided_refine_lds_bytes(a), s, a, R);
     return hipGetLastError();
 }
 
