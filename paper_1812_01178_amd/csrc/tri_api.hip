@@ -358,7 +358,8 @@ tri_status plan_refine_launch(tri_ctx ctx, const Problem &pb, const Tables &T, L
     a.Cs = m / kc;
     a.ngroups0 = (pb.L.nb0 + 63) / 64;
     out.kind = 0;
-    out.chunk_max = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : 40)));
+    // (the instance for chunks of exactly 36 rows: the spanwise lines at P = 8)
+    out.chunk_max = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : (a.Cs == 36 ? 36 : 40))));
     out.refine = true;
     out.R = RefineArgs{T.F32, T.ORIG, kRefineMaxSweeps, kRefineTol, ctx->status_dev, ctx->sweeps_dev,
                        ctx->resid_dev};

@@ -315,6 +315,7 @@ static hipError_t launch_refine_batch_m(const BatchEntry *e, int count, dim3 gri
     case 16: hipLaunchKernelGGL((k_strided_refine_batch<16, METHOD>), grid, block, lds, s, e, count); break;
     case 24: hipLaunchKernelGGL((k_strided_refine_batch<24, METHOD>), grid, block, lds, s, e, count); break;
     case 32: hipLaunchKernelGGL((k_strided_refine_batch<32, METHOD>), grid, block, lds, s, e, count); break;
+    case 36: hipLaunchKernelGGL((k_strided_refine_batch<36, METHOD>), grid, block, lds, s, e, count); break;
     case 40: hipLaunchKernelGGL((k_strided_refine_batch<40, METHOD>), grid, block, lds, s, e, count); break;
     default: return hipErrorInvalidValue;
     }
@@ -333,7 +334,7 @@ hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int
 size_t strided_refine_lds_bytes(const SolveArgs &a)
 {
     const int nw = a.P * a.kc;
-    const int cmax = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : 40)));
+    const int cmax = a.Cs <= 8 ? 8 : (a.Cs <= 16 ? 16 : (a.Cs <= 24 ? 24 : (a.Cs <= 32 ? 32 : (a.Cs == 36 ? 36 : 40))));
     return sizeof(double) * ((size_t)2 * a.P * 64 + (size_t)nw * 4 * 64) +
            sizeof(float) * ((size_t)nw * 2 * 64 + 2 * (size_t)nw) + 16 + 64 * sizeof(int) +
            sizeof(double) * (size_t)nw * 3 * cmax + sizeof(float) * (size_t)nw * kNumFactors * cmax;
@@ -360,6 +361,7 @@ static hipError_t launch_refine_m(const SolveArgs &a, const RefineArgs &R, int c
     case 16: return launch_refine_t<16, METHOD>(a, R, s);
     case 24: return launch_refine_t<24, METHOD>(a, R, s);
     case 32: return launch_refine_t<32, METHOD>(a, R, s);
+    case 36: return launch_refine_t<36, METHOD>(a, R, s);
     case 40: return launch_refine_t<40, METHOD>(a, R, s);
     default: return hipErrorInvalidValue;
     }
