@@ -1459,6 +1459,7 @@ struct tri_plan_s {
         int item = -1, launch = -1;                 // a single launch ...
         std::vector<std::pair<int, int>> members;   // ... or a batch of (item, launch)
         bool refine = false;                        // batch of refinement solves
+        bool exact = false;                         // ... whose chunks all have cmax rows
         bool chunked = false;
         int method = 0;
         BatchEntry *dev = nullptr;
@@ -1596,13 +1597,17 @@ Span launch_span(const SolveArgs &a)
 }
 
 // Strided launches can join a batch of launches that run the same kernel
-// instance: the key holds refinement, chunk instance (CMAX), method,
-// chunking and wavefronts per workgroup.
+// instance: the key holds refinement (and, for it, whether every chunk has
+// exactly CMAX rows), chunk instance (CMAX), method, chunking and wavefronts
+// per workgroup.
 bool batchable(const Launch &l) { return l.kind == 0 && l.args.nlines > 0 && l.args.lpl <= 1; }
+
+bool refine_exact(const Launch &l) { return l.refine && l.args.Cs == l.chunk_max; }
 
 int64_t batch_key(const Launch &l, int method)
 {
-    return (((int64_t)(l.refine ? 1 : 0) * 128 + l.chunk_max) * 2 + method) * 2 * 64 +
+    return ((((int64_t)(l.refine ? 1 : 0) * 2 + (refine_exact(l) ? 1 : 0)) * 128 + l.chunk_max) * 2 + method) *
+               2 * 64 +
            (int64_t)(l.args.kc > 1 ? 64 : 0) + l.args.P * l.args.kc;
 }
 
@@ -1659,6 +1664,7 @@ tri_status build_schedule(tri_plan plan)
             std::vector<BatchEntry> host;
             const Launch &l0 = plan->items[(size_t)kv.second[0].item].launches[(size_t)kv.second[0].launch];
             st.refine = l0.refine;
+            st.exact = refine_exact(l0);
             st.cmax = l0.chunk_max;
             st.chunked = l0.args.kc > 1;
             st.method = plan->items[(size_t)kv.second[0].item].pb.method;
@@ -1693,7 +1699,8 @@ hipError_t run_step(const tri_plan_s &plan, const tri_plan_s::Step &st, hipStrea
         return run_launch(item.launches[(size_t)st.launch], item.pb.method, s);
     }
     if (st.refine)
-        return launch_strided_refine_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.lds, s);
+        return launch_strided_refine_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.exact,
+                                           st.lds, s);
     return launch_strided_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.chunked, st.lds,
                                 s);
 }

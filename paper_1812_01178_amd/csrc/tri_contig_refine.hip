@@ -238,13 +238,16 @@ __global__ void __launch_bounds__(512) k_contig_refine(const SolveArgs A, const 
             interface_unknowns<METHOD>(it_rows, r, P, A.periodic, [&](int q) { return tips[q]; }, yl, yr);
             const double unscale = ldexp(1.0, E);
             double dmax = 0.0, xmax = 0.0;
+            bool nan = false;                   // (fmax drops NaNs: they are counted apart)
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 const double delta = ((double)e[c] - yl * (double)fv[c] - yr * (double)fw[c]) * unscale;
                 xv[c] += delta;
-                dmax = rmax(dmax, fabs(delta));
-                xmax = rmax(xmax, fabs(xv[c]));
+                nan |= !(delta == delta) || !(xv[c] == xv[c]);
+                dmax = fmax(dmax, fabs(delta));
+                xmax = fmax(xmax, fabs(xv[c]));
             }
+            if (nan) dmax = xmax = __builtin_nan("");
             // convergence of the line (the workgroup): every thread takes the
             // same decision from the same reduced values
             block_max2(dmax, xmax, red);

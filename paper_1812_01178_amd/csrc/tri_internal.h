@@ -231,9 +231,10 @@ int contig_reg_grid(const SolveArgs &a, int method);
 hipError_t launch_general(const GeneralArgs &a, int method, hipStream_t s);
 hipError_t launch_strided_refine(const SolveArgs &a, const RefineArgs &R, int method, int chunk_max, hipStream_t s);
 size_t strided_refine_lds_bytes(const SolveArgs &a);
-// Ragged batch of refinement solves (same rule with the refinement kernel).
+// Ragged batch of refinement solves (same rule with the refinement kernel);
+// exact: every entry's chunks have exactly cmax rows.
 hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts,
-                                       int cmax, int method, size_t lds, hipStream_t s);
+                                       int cmax, int method, bool exact, size_t lds, hipStream_t s);
 // Refinement for contiguous rows (one shared matrix; register-factor layout).
 hipError_t launch_contig_refine(const SolveArgs &a, const RefineArgs &R, int method, int grid, hipStream_t s);
 size_t contig_refine_lds_bytes(const SolveArgs &a);

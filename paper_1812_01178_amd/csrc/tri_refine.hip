@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine(const
 
 // Ragged batch of refinement solves in one launch (see k_strided_batch):
 // every entry runs with this instance's CMAX, method and P * kc.
-template <int CMAX, int METHOD>
+template <int CMAX, int METHOD, bool EXACT>
 __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine_batch(const BatchEntry *__restrict__ E,
                                                                                   int count)
 {
@@ -303,32 +303,40 @@ __global__ void __launch_bounds__(CMAX > 16 ? 512 : 1024) k_strided_refine_batch
     const int64_t b = blockIdx.x;
     int i = 0;
     while (i + 1 < count && E[i + 1].begin <= b) ++i;
-    strided_refine_solve<CMAX, METHOD>(E[i].a, E[i].R, b - E[i].begin, lds);
+    strided_refine_solve<CMAX, METHOD, EXACT>(E[i].a, E[i].R, b - E[i].begin, lds);
+}
+
+template <int CMAX, int METHOD>
+static void launch_refine_batch_t(const BatchEntry *e, int count, dim3 grid, dim3 block, size_t lds, bool exact,
+                                  hipStream_t s)
+{
+    if (exact) hipLaunchKernelGGL((k_strided_refine_batch<CMAX, METHOD, true>), grid, block, lds, s, e, count);
+    else hipLaunchKernelGGL((k_strided_refine_batch<CMAX, METHOD, false>), grid, block, lds, s, e, count);
 }
 
 template <int METHOD>
 static hipError_t launch_refine_batch_m(const BatchEntry *e, int count, dim3 grid, dim3 block, size_t lds,
-                                        int cmax, hipStream_t s)
+                                        int cmax, bool exact, hipStream_t s)
 {
     switch (cmax) {
-    case 8: hipLaunchKernelGGL((k_strided_refine_batch<8, METHOD>), grid, block, lds, s, e, count); break;
-    case 16: hipLaunchKernelGGL((k_strided_refine_batch<16, METHOD>), grid, block, lds, s, e, count); break;
-    case 24: hipLaunchKernelGGL((k_strided_refine_batch<24, METHOD>), grid, block, lds, s, e, count); break;
-    case 32: hipLaunchKernelGGL((k_strided_refine_batch<32, METHOD>), grid, block, lds, s, e, count); break;
-    case 36: hipLaunchKernelGGL((k_strided_refine_batch<36, METHOD>), grid, block, lds, s, e, count); break;
-    case 40: hipLaunchKernelGGL((k_strided_refine_batch<40, METHOD>), grid, block, lds, s, e, count); break;
+    case 8: launch_refine_batch_t<8, METHOD>(e, count, grid, block, lds, exact, s); break;
+    case 16: launch_refine_batch_t<16, METHOD>(e, count, grid, block, lds, exact, s); break;
+    case 24: launch_refine_batch_t<24, METHOD>(e, count, grid, block, lds, exact, s); break;
+    case 32: launch_refine_batch_t<32, METHOD>(e, count, grid, block, lds, exact, s); break;
+    case 36: launch_refine_batch_t<36, METHOD>(e, count, grid, block, lds, exact, s); break;
+    case 40: launch_refine_batch_t<40, METHOD>(e, count, grid, block, lds, exact, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_strided_refine_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts,
-                                       int cmax, int method, size_t lds, hipStream_t s)
+                                       int cmax, int method, bool exact, size_t lds, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
     const dim3 grid((unsigned)blocks), block(64 * wavefronts);
-    return method == TRI_PDD ? launch_refine_batch_m<TRI_PDD>(entries, count, grid, block, lds, cmax, s)
-                             : launch_refine_batch_m<TRI_PPT>(entries, count, grid, block, lds, cmax, s);
+    return method == TRI_PDD ? launch_refine_batch_m<TRI_PDD>(entries, count, grid, block, lds, cmax, exact, s)
+                             : launch_refine_batch_m<TRI_PPT>(entries, count, grid, block, lds, cmax, exact, s);
 }
 
 size_t strided_refine_lds_bytes(const SolveArgs &a)

@@ -92,7 +92,7 @@ int contig_reg_grid(const SolveArgs &, int) { return 256; }
 hipError_t launch_general(const GeneralArgs &, int, hipStream_t) { return counted(); }
 hipError_t launch_strided_refine(const SolveArgs &, const RefineArgs &, int, int, hipStream_t) { return counted(); }
 size_t strided_refine_lds_bytes(const SolveArgs &) { return 4096; }
-hipError_t launch_strided_refine_batch(const BatchEntry *, int, int64_t, int, int, int, size_t, hipStream_t)
+hipError_t launch_strided_refine_batch(const BatchEntry *, int, int64_t, int, int, int, bool, size_t, hipStream_t)
 {
     return counted();
 }
