@@ -915,9 +915,11 @@ def ragged_section(T, ctx, stream, args, pristine=None):
     Nx in {256..2048}, Ny in {128, 256}, Nz in {96, 288}, each with an x, y and
     periodic-z momentum sweep (PDD) and its Poisson wavenumber solves (PPT),
     all in one plan with P = 0 (the plan times P in {1,2,4,8,16}; PDD only
-    where its dropped entries are <= 1e-15).  Strided solves of a dependency
-    level run as one batched launch; the step is also timed as a HIP graph,
-    without batching, and in FP32 + refinement.  Every sub-grid's result is
+    where its dropped entries are <= 1e-15).  FP64: every solve of a
+    dependency level in one launch of the level kernel (three launches a
+    step); the step is also timed as a HIP graph, with the strided solves of
+    one kernel instance batched instead, without batching, and in FP32 +
+    refinement (strided refinement solves of one instance batched).  Every sub-grid's result is
     checked by its backward error (the oracle parity of this batch is in the
     GPU tests)."""
     import torch
@@ -1009,7 +1011,10 @@ def ragged_section(T, ctx, stream, args, pristine=None):
         n_items = 4 * len(grids)
         Ps = [T.tri_plan_item_partitions(plan, i) for i in range(n_items)]
         descr = [T.tri_plan_item_describe(plan, i) for i in range(n_items)]
-        batches = sorted({d.split("batch=")[1].split()[0] for d in descr if "batch=" in d})
+        batches = sorted({d.split(k)[1].split()[0] for d in descr for k in ("batch=", "level=") if k in d})
+        n_launch = T.tri_plan_launch_count(plan)
+        mode = "one launch per dependency level" if any("level=" in d for d in descr) else \
+            "strided solves of one kernel instance batched"
         reset()
         T.tri_plan_execute(plan)
         T.tri_sync_status(ctx)
@@ -1042,15 +1047,43 @@ def ragged_section(T, ctx, stream, args, pristine=None):
                "residual": "per sub-grid: the step x -> y -> z solves A_z A_y A_x u = u0, so "
                            "max|A_x A_y A_z u - u0| / max(|A_x| |A_y| |A_z| |u|), and the largest "
                            "per-line backward error of the Poisson solves"}
+        res["launches_per_step"] = n_launch
+        res["launch_mode"] = mode
         os.environ["TRI_BATCH"] = "0"
         plan = T.tri_plan_create(ctx, items(), prec=prec)
         os.environ.pop("TRI_BATCH")
         reset()
         res["ms_per_step_unbatched"] = round(timed(lambda: T.tri_plan_execute(plan), args.steps), 4)
+        res["launches_per_step_unbatched"] = T.tri_plan_launch_count(plan)
         T.tri_plan_destroy(plan)
+        if prec == T.TRI_F64:
+            # the alternative grouping: strided solves of one kernel instance
+            # batched, every other solve in a launch of its own kernel (with
+            # that grouping's own partition-count and shape choices)
+            os.environ["TRI_BATCH"] = "1"
+            plan = T.tri_plan_create(ctx, items(), prec=prec)
+            os.environ.pop("TRI_BATCH")
+            reset()
+            T.tri_plan_execute(plan)
+            T.tri_sync_status(ctx)
+            pi_err = max(max(ragged_residual(g)) for g in grids)
+            reset()
+            pi_ms = timed(lambda: T.tri_plan_execute(plan), args.steps)
+            T.tri_plan_capture(plan)
+            reset()
+            pi_graph = timed(lambda: T.tri_plan_graph_launch(plan), args.steps)
+            res["per_instance_batches"] = {
+                "ms_per_step": round(pi_ms, 4), "ms_per_step_graph": round(pi_graph, 4),
+                "unknowns_per_s_graph": unknowns / (pi_graph * 1e-3),
+                "launches_per_step": T.tri_plan_launch_count(plan),
+                "P": [T.tri_plan_item_partitions(plan, i) for i in range(n_items)],
+                "residual_max": pi_err}
+            T.tri_plan_destroy(plan)
+            log(f"ragged {prec_name} per-instance batches: {pi_ms:.3f} ms/step ({pi_graph:.3f} ms as graph), "
+                f"{res['per_instance_batches']['launches_per_step']} launches, residual {pi_err:.2e}")
         out[prec_name] = res
         log(f"ragged {prec_name}: {ms:.3f} ms/step ({ms_graph:.3f} ms as graph), "
-            f"{unknowns / (ms_graph * 1e-3) / 1e9:.1f} G unknowns/s, {len(batches)} batched launches, "
+            f"{unknowns / (ms_graph * 1e-3) / 1e9:.1f} G unknowns/s, {n_launch} launches ({mode}), "
             f"residual {parity:.2e}, P={Ps}")
     out["refine_speedup_vs_fp64"] = round(out["fp64"]["ms_per_step_graph"] / out["fp32_refine"]["ms_per_step_graph"], 3)
     return out

@@ -432,10 +432,19 @@ typedef struct {
  * in order, or a contiguous range of them per XCD).
  * Execution order: the items behave as if run one after another in the
  * given order; launches that touch disjoint memory are grouped into
- * dependency levels, and the strided solves of one level (y and z sweeps,
- * Poisson modes of different sub-grids) run as one batched launch over the
- * ragged set unless TRI_BATCH=0.  Under TRI_F32_REFINE, items whose lines
- * are contiguous (x sweeps) use the FP64 kernel.  Synchronises the context
+ * dependency levels.  TRI_BATCH selects how a level is launched.  2 (the
+ * default): in a plan of several FP64 items, every solve of a level -- x,
+ * y and z sweeps and Poisson modes alike, each at its own partition count
+ * -- runs in ONE launch of the level kernel (512-lane workgroups, each
+ * holding blocks of one solve, with that solve's elimination); the tuner
+ * then times partition counts and launch shapes as level entries and
+ * admits only shapes the level kernel has (strided: at most 8 wavefronts
+ * a block, chunks of at most 40 rows; contiguous: the register-factor
+ * body with 4 rows per lane where the line splits that way), so a time
+ * step is one launch per dependency level.  1: the strided solves of a
+ * level that use the same kernel instance run as one batched launch, the
+ * others by themselves (single-item and TRI_F32_REFINE plans always
+ * group this way).  0: every solve by itself.  Synchronises the context
  * stream. */
 tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
                            tri_plan *out);
@@ -453,6 +462,8 @@ int tri_plan_item_partitions(tri_plan plan, int i);
  * written to buf (at most len bytes, NUL-terminated); returns the length
  * the full text needs, or -1 on a bad argument. */
 int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len);
+/* Kernel launches one tri_plan_execute queues, or -1 for a null plan. */
+int tri_plan_launch_count(tri_plan plan);
 tri_status tri_plan_destroy(tri_plan plan);
 
 /* Reference copy (measurement aid; not a step of the method).  Every solve

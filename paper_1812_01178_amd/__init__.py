@@ -22,8 +22,8 @@ __all__ = [
     "TriError", "lib", "tri_create", "tri_destroy", "tri_set_stream", "tri_set_pdd_tolerance", "tri_sync_status",
     "tri_status_string", "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep",
     "poisson_wavenumber_solve", "tri_plan_create", "tri_plan_execute", "tri_plan_capture",
-    "tri_plan_graph_launch", "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy",
-    "TriLines", "TriCoef", "TriInfo", "TriItem", "EXPORTED",
+    "tri_plan_graph_launch", "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_launch_count",
+    "tri_plan_destroy", "TriLines", "TriCoef", "TriInfo", "TriItem", "EXPORTED",
     "TRI_F64", "TRI_F32_REFINE", "TRI_REAL", "TRI_COMPLEX", "TRI_PDD", "TRI_PPT",
     "TRI_DIR_X", "TRI_DIR_Y", "TRI_DIR_Z", "TRI_ITEM_ADI_X", "TRI_ITEM_ADI_Y",
     "TRI_ITEM_ADI_Z", "TRI_ITEM_POISSON", "TRI_MAX_PARTITIONS", "tri_stream_copy", "tri_reserve",
@@ -50,7 +50,8 @@ EXPORTED = [
     "tri_create", "tri_destroy", "tri_set_stream", "tri_set_pdd_tolerance", "tri_sync_status", "tri_status_string",
     "tri_last_error", "tri_pdd_solve", "tri_ppt_solve", "adi_sweep", "poisson_wavenumber_solve",
     "tri_plan_create", "tri_plan_execute", "tri_plan_capture", "tri_plan_graph_launch",
-    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_destroy", "tri_stream_copy", "tri_reserve",
+    "tri_plan_item_partitions", "tri_plan_item_describe", "tri_plan_launch_count", "tri_plan_destroy",
+    "tri_stream_copy", "tri_reserve",
     "spanwise_rfft", "spanwise_irfft", "projection_divergence_rfft", "projection_correct", "projection_step",
     "poisson_shifted_solve", "streamwise_dct", "streamwise_idct", "projection3d_divergence_rfft",
     "projection3d_correct", "projection3d_step", "tri_ppt_pivots", "adi_sweep_noalloc",
@@ -138,6 +139,7 @@ def lib():
         "tri_plan_graph_launch": (_I, [_V]),
         "tri_plan_item_partitions": (_I, [_V, _I]),
         "tri_plan_item_describe": (_I, [_V, _I, ctypes.c_char_p, _I]),
+        "tri_plan_launch_count": (_I, [_V]),
         "tri_plan_destroy": (_I, [_V]),
         "tri_stream_copy": (_I, [_V, _V, _V, _I64]),
         "tri_reserve": (_I, [_V, _I64, _I, _I64]),
@@ -443,6 +445,10 @@ def tri_plan_item_describe(plan, i: int) -> str:
     if lib().tri_plan_item_describe(plan, int(i), buf, 256) < 0:
         raise TriError(TRI_E_ARG, "tri_plan_item_describe")
     return buf.value.decode()
+
+
+def tri_plan_launch_count(plan) -> int:
+    return int(lib().tri_plan_launch_count(plan))
 
 
 def tri_plan_destroy(plan) -> None:

@@ -126,6 +126,20 @@ int env_int(const char *name, int dflt)
     return (v && *v) ? atoi(v) : dflt;
 }
 
+// Grouping of a plan level's launches (TRI_BATCH overrides): 0 = one launch
+// each, 1 = strided launches of one kernel instance batched, 2 = one level
+// launch in plans of several FP64 items (others as 1).
+constexpr int kDefaultBatchMode = 2;
+int batch_mode() { return env_int("TRI_BATCH", kDefaultBatchMode); }
+
+// Whether the plan being created runs its levels as level launches: batch
+// mode 2 and a plan of several FP64 items (a single item has nothing to share
+// a launch with and keeps the shapes of its own kernels).  Set by
+// tri_plan_create for the duration of the call; the tuner and the schedule
+// read it.
+thread_local bool t_level_plan = false;
+bool level_plan() { return t_level_plan; }
+
 // Chunks per partition for the refinement kernel, which keeps d and x in
 // FP64 and the work vector in FP32 (5 VGPRs per row): chunks of at most 16
 // rows when possible, at most 40; more than 16 rows need P*kc <= 8.
@@ -1291,7 +1305,8 @@ std::string tune_key(const Problem &pb, int kind)
              kind, pb.method, pb.P, pb.periodic, (long long)pb.L.n, (long long)pb.L.nb0,
              (long long)pb.L.nb1, (long long)pb.L.s_j, (long long)pb.L.s_b0, (long long)pb.L.s_b1,
              (long long)pb.g_b1);
-    return buf;
+    // level launches keep their own choices (only shapes the level kernel runs)
+    return level_plan() ? std::string(buf) + " L" : std::string(buf);
 }
 
 void tune_cache_read(const char *path)
@@ -1341,26 +1356,99 @@ void tune_cache_store(const std::string &key, int v)
     fclose(fp);
 }
 
+// The level kernel's entry for an FP64 launch, if it has a body there:
+// strided launches of at most 8 wavefronts with chunks of at most 40 rows
+// (24 with two lines per lane) keep their launch shape; contiguous launches
+// of a shared matrix run the register-factor body with 4 rows per lane where
+// the line splits that way, other contiguous launches the plain body with at
+// most 8 rows per lane and as many lines per workgroup as fit.
+bool level_entry(const Launch &l, int method, LevelEntry &e)
+{
+    if (l.refine || l.args.acc || l.args.nlines == 0) return false;
+    SolveArgs a = l.args;
+    e = LevelEntry{};
+    int rLp = 0;
+    if (l.kind == 0) {
+        const int w = a.P * (a.lpl == 2 ? 1 : a.kc);
+        if (w > kLevelWaves || l.chunk_max > (a.lpl == 2 ? 24 : 40)) return false;
+        e.body = a.lpl == 2 ? kLevelStrided2 : kLevelStrided;
+        e.cmax = l.chunk_max;
+        e.chunked = a.lpl == 2 ? 0 : (a.kc > 1);
+        e.wpb = w;
+        e.sub = kLevelWaves / w;
+        e.nblocks = a.ngroups0 * a.nb1;
+        e.lds_sub = a.lpl == 2 ? 2 * a.P * 128 : (int)(strided_lds_bytes(a) / sizeof(double));
+    } else if ((l.kind == 2 || l.kind == 3) && reg_split(a.m, a.P, 4, rLp)) {
+        // shared matrix, contiguous 16-byte-aligned lines: the register-factor
+        // body with 4 rows per lane, each block a run of consecutive lines
+        // (about 512 workgroups for the entry, at most 16 lines a block)
+        a.C = 4;
+        a.Lp = rLp;
+        a.LL = a.P * rLp;
+        a.LPB = 1;
+        a.stage_stride = 2 * a.LL + 16;
+        e.body = kLevelContigReg;
+        e.cmax = 4;
+        e.wpb = a.LL / 64;
+        e.sub = kLevelWaves / e.wpb;
+        e.lines = (int)std::max<int64_t>(1, std::min<int64_t>(16, a.nlines / (512 * (int64_t)e.sub)));
+        e.nblocks = (a.nlines + e.lines - 1) / e.lines;
+        e.lds_sub = (int)(contig_reg_lds_bytes(a) / sizeof(double));
+    } else {
+        int Lp = 1;
+        while (Lp < 64 && (a.m + Lp - 1) / Lp > 8) Lp <<= 1;
+        const int C = (a.m + Lp - 1) / Lp;
+        const int LL = a.P * Lp;
+        if (C > 8 || LL > kLevelThreads) return false;
+        a.C = C;
+        a.Lp = Lp;
+        a.LL = LL;
+        a.LPB = kLevelThreads / LL;
+        e.body = kLevelContig;
+        e.cmax = C <= 4 ? 4 : 8;
+        e.wpb = kLevelWaves;
+        e.sub = 1;
+        e.nblocks = (a.nlines + a.LPB - 1) / a.LPB;
+        e.lds_sub = 2 * a.P * a.LPB;
+    }
+    e.a = a;
+    e.method = method;
+    return true;
+}
+
+// Whether every launch of `ls` has a level body (FP64 launches only).
+bool level_ok(const std::vector<Launch> &ls, int method)
+{
+    LevelEntry e;
+    for (const Launch &l : ls)
+        if (l.args.nlines > 0 && !level_entry(l, method, e)) return false;
+    return true;
+}
+
 // Candidate tuning values for a problem whose default launch is `base`.
 std::vector<int> tune_candidates(const Problem &pb, const Launch &base)
 {
     std::vector<int> c;
     const int m = (int)(pb.L.n / pb.P);
+    const bool level = level_plan();
     if (base.kind == 0) {
         // chunks per partition, each with line groups in order and with
-        // per-XCD contiguous ranges (+200)
+        // per-XCD contiguous ranges (+200); level launches take chunks of at
+        // most 40 rows on at most 8 wavefronts
         int nk = 0;
         for (int kc = 1; kc <= 16 && nk < 4; ++kc)
-            if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8) {
+            if (pick_kc(m, pb.P, kc) == kc && m / kc >= 8 &&
+                (!level || (m / kc <= 40 && pb.P * kc <= kLevelWaves))) {
                 c.push_back(kc);
                 c.push_back(kc + 200);
                 ++nk;
             }
-        if (strided2_ok(pb, m)) {   // two lines per lane, one wavefront per partition
+        if (strided2_ok(pb, m) && (!level || pb.P <= kLevelWaves)) {   // two lines per lane, one wavefront per partition
             c.push_back(1001);
             c.push_back(1201);
         }
-    } else if (base.kind == 2 || base.kind == 3) {
+    } else if ((base.kind == 2 || base.kind == 3) && !level) {
+        // (a level launch runs every contiguous solve with the plain body)
         int Lp, C;
         for (int want : {4, 8, 16})
             if (staged_split(m, Lp, C, want) && pb.P * Lp <= 1024) c.push_back(want);
@@ -1384,7 +1472,29 @@ static float time_on_scratch(tri_ctx ctx, const Problem &pb, std::vector<Launch>
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess &&
               hipMemsetAsync(scratch, 0, sizeof(double) * (size_t)span, ctx->stream) == hipSuccess;
+    // with level launches (TRI_BATCH=2) the launches are timed as the entries
+    // of one level launch, the way a plan runs them
+    LevelEntry *ltab = nullptr;
+    int lcount = 0;
+    int64_t lblocks = 0;
+    size_t llds = 0;
+    if (ok && level_plan() && level_ok(ls, pb.method)) {
+        std::vector<LevelEntry> host;
+        for (const Launch &l : ls) {
+            LevelEntry e;
+            if (l.args.nlines == 0 || !level_entry(l, pb.method, e)) continue;
+            e.begin = lblocks;
+            lblocks += (e.nblocks + e.sub - 1) / e.sub;
+            llds = std::max(llds, sizeof(double) * (size_t)e.lds_sub * (size_t)((kLevelWaves + e.wpb - 1) / e.wpb));
+            host.push_back(e);
+        }
+        lcount = (int)host.size();
+        ok = lcount == 0 || (hipMalloc((void **)&ltab, sizeof(LevelEntry) * host.size()) == hipSuccess &&
+                             hipMemcpy(ltab, host.data(), sizeof(LevelEntry) * host.size(),
+                                       hipMemcpyHostToDevice) == hipSuccess);
+    }
     auto run_all = [&]() {
+        if (ltab) return launch_level(ltab, lcount, lblocks, llds, ctx->stream) == hipSuccess;
         for (const Launch &l : ls)
             if (run_launch(l, pb.method, ctx->stream) != hipSuccess) return false;
         return true;
@@ -1401,6 +1511,7 @@ static float time_on_scratch(tri_ctx ctx, const Problem &pb, std::vector<Launch>
     (void)hipStreamSynchronize(ctx->stream);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    if (ltab) (void)hipFree(ltab);
     (void)hipFree(scratch);
     return ok ? best : -1.f;
 }
@@ -1453,11 +1564,14 @@ struct tri_plan_s {
     std::vector<Item> items;
     // Execution order: launches grouped into dependency levels (a launch
     // comes after every earlier launch whose memory it overlaps); inside a
-    // level, strided FP64 launches with the same workgroup shape form one
-    // batched launch.
+    // level, the FP64 launches run as one level launch (strided and
+    // contiguous bodies side by side), or strided launches with the same
+    // workgroup shape form one batched launch (see build_schedule).
     struct Step {
         int item = -1, launch = -1;                 // a single launch ...
         std::vector<std::pair<int, int>> members;   // ... or a batch of (item, launch)
+        bool level = false;                         // batch run by the level kernel (table in ldev)
+        LevelEntry *ldev = nullptr;
         bool refine = false;                        // batch of refinement solves
         bool exact = false;                         // ... whose chunks all have cmax rows
         bool chunked = false;
@@ -1520,7 +1634,8 @@ std::string partition_key(const tri_item &it, tri_prec prec)
     char buf[160];
     snprintf(buf, sizeof buf, "partitions k%d m%d per%d prec%d Nx%lld Ny%lld Nz%lld", it.kind, it.method,
              it.periodic, (int)prec, (long long)it.Nx, (long long)it.Ny, (long long)it.Nz);
-    return buf;
+    // level launches keep their own choices (timed as level entries)
+    return level_plan() ? std::string(buf) + " L" : std::string(buf);
 }
 
 // The PDD admission rule for one partition count: the dropped reduced-system
@@ -1549,34 +1664,51 @@ tri_status choose_partitions(tri_ctx ctx, const tri_item &it, tri_prec prec, int
         auto f = g_tune_cache.find(pkey);
         if (f != g_tune_cache.end()) listed = f->second;
     }
+    // with level launches, a partition count whose launches have no level
+    // body, or run contiguous lines with the plain body, is taken only when
+    // no other is admissible
+    const bool level = level_plan() && prec == TRI_F64;
+    auto level_body = [&](const Problem &pb) {
+        if (!level) return true;
+        std::vector<Launch> ls;
+        Tables T0{};
+        if (item_launches(ctx, pb, T0, prec, ls) != TRI_OK) return false;
+        for (const Launch &l : ls) {
+            LevelEntry e;
+            if (l.args.nlines > 0 && (!level_entry(l, pb.method, e) || e.body == kLevelContig)) return false;
+        }
+        return true;
+    };
     if (listed > 0) {
         Problem pb;
-        if (item_problem(ctx, it, listed, pb) == TRI_OK && partitions_admissible(ctx, pb)) {
+        if (item_problem(ctx, it, listed, pb) == TRI_OK && partitions_admissible(ctx, pb) && level_body(pb)) {
             P_out = listed;
             return TRI_OK;
         }
     }
     int best = 0;
     float best_ms = 1e30f;
-    for (int P : {1, 2, 4, 8, 16}) {
-        Problem pb;
-        if (item_problem(ctx, it, P, pb) != TRI_OK) continue;
-        void *mem = nullptr;
-        if (hipMalloc(&mem, tables_bytes(pb.G, pb.L.n, pb.P)) != hipSuccess) continue;
-        Tables T = carve_tables(mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
-        std::vector<Launch> ls;
-        float ms = -1.f;
-        if (item_launches(ctx, pb, T, prec, ls) == TRI_OK &&
-            launch_factor(pb.src, T, ctx->status_dev, ctx->stream) == hipSuccess &&
-            hipStreamSynchronize(ctx->stream) == hipSuccess &&
-            (pb.method != TRI_PDD || P == 1 || max_drop(T) <= kPddSafeDrop))
-            ms = time_on_scratch(ctx, pb, ls);
-        (void)hipFree(mem);
-        if (ms >= 0.f && ms < best_ms) {
-            best_ms = ms;
-            best = P;
+    for (int pass = 0; pass < 2 && best == 0; ++pass)
+        for (int P : {1, 2, 4, 8, 16}) {
+            Problem pb;
+            if (item_problem(ctx, it, P, pb) != TRI_OK) continue;
+            if (pass == 0 && !level_body(pb)) continue;
+            void *mem = nullptr;
+            if (hipMalloc(&mem, tables_bytes(pb.G, pb.L.n, pb.P)) != hipSuccess) continue;
+            Tables T = carve_tables(mem, pb.G, pb.L.n, pb.P, pb.periodic, pb.method);
+            std::vector<Launch> ls;
+            float ms = -1.f;
+            if (item_launches(ctx, pb, T, prec, ls) == TRI_OK &&
+                launch_factor(pb.src, T, ctx->status_dev, ctx->stream) == hipSuccess &&
+                hipStreamSynchronize(ctx->stream) == hipSuccess &&
+                (pb.method != TRI_PDD || P == 1 || max_drop(T) <= kPddSafeDrop))
+                ms = time_on_scratch(ctx, pb, ls);
+            (void)hipFree(mem);
+            if (ms >= 0.f && ms < best_ms) {
+                best_ms = ms;
+                best = P;
+            }
         }
-    }
     if (best == 0) return fail(ctx, TRI_E_UNSUPPORTED, "no admissible partition count for item kind %d", it.kind);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1604,6 +1736,7 @@ bool batchable(const Launch &l) { return l.kind == 0 && l.args.nlines > 0 && l.a
 
 bool refine_exact(const Launch &l) { return l.refine && l.args.Cs == l.chunk_max; }
 
+
 int64_t batch_key(const Launch &l, int method)
 {
     return ((((int64_t)(l.refine ? 1 : 0) * 2 + (refine_exact(l) ? 1 : 0)) * 128 + l.chunk_max) * 2 + method) *
@@ -1615,8 +1748,10 @@ int64_t batch_key(const Launch &l, int method)
 tri_status build_schedule(tri_plan plan)
 {
     tri_ctx ctx = plan->ctx;
-    for (auto &st : plan->steps)
+    for (auto &st : plan->steps) {
         if (st.dev) (void)hipFree(st.dev);
+        if (st.ldev) (void)hipFree(st.ldev);
+    }
     plan->steps.clear();
     struct Ref {
         int item, launch, level;
@@ -1633,8 +1768,50 @@ tri_status build_schedule(tri_plan plan)
             refs.push_back({i, j, level, sp});
             nlevels = std::max(nlevels, level + 1);
         }
-    const bool batching = env_int("TRI_BATCH", 1) != 0;
+    const int mode = level_plan() ? 2 : std::min(batch_mode(), 1);
+    const bool batching = mode != 0;
     for (int lev = 0; lev < nlevels; ++lev) {
+        if (mode == 2) {
+            // one level launch for every launch of the level that has a body there
+            std::vector<LevelEntry> host;
+            tri_plan_s::Step st;
+            st.level = true;
+            int64_t blocks = 0;
+            size_t lds = 0;
+            for (const Ref &r : refs) {
+                if (r.level != lev) continue;
+                const auto &item = plan->items[(size_t)r.item];
+                LevelEntry e;
+                if (!level_entry(item.launches[(size_t)r.launch], item.pb.method, e)) continue;
+                e.begin = blocks;
+                blocks += (e.nblocks + e.sub - 1) / e.sub;
+                lds = std::max(lds, sizeof(double) * (size_t)e.lds_sub * (size_t)((kLevelWaves + e.wpb - 1) / e.wpb));
+                host.push_back(e);
+                st.members.push_back({r.item, r.launch});
+            }
+            if (host.size() >= 2) {
+                st.count = (int)host.size();
+                st.blocks = blocks;
+                st.lds = lds;
+                const size_t bytes = sizeof(LevelEntry) * host.size();
+                if (hipMalloc((void **)&st.ldev, bytes) != hipSuccess) return fail(ctx, TRI_E_NOMEM, "level table");
+                plan->steps.push_back(st);
+                HIP_TRY(ctx, hipMemcpy(st.ldev, host.data(), bytes, hipMemcpyHostToDevice));
+            }
+            const bool merged = host.size() >= 2;
+            for (const Ref &r : refs) {
+                if (r.level != lev) continue;
+                bool in = false;
+                if (merged)
+                    for (const auto &mb : st.members) in = in || (mb.first == r.item && mb.second == r.launch);
+                if (in) continue;
+                tri_plan_s::Step one;
+                one.item = r.item;
+                one.launch = r.launch;
+                plan->steps.push_back(one);
+            }
+            continue;
+        }
         std::vector<Ref> cand;
         for (const Ref &r : refs) {
             if (r.level != lev) continue;
@@ -1698,6 +1875,7 @@ hipError_t run_step(const tri_plan_s &plan, const tri_plan_s::Step &st, hipStrea
         const auto &item = plan.items[(size_t)st.item];
         return run_launch(item.launches[(size_t)st.launch], item.pb.method, s);
     }
+    if (st.level) return launch_level(st.ldev, st.count, st.blocks, st.lds, s);
     if (st.refine)
         return launch_strided_refine_batch(st.dev, st.count, st.blocks, st.wavefronts, st.cmax, st.method, st.exact,
                                            st.lds, s);
@@ -1719,8 +1897,10 @@ tri_status tri_plan_destroy(tri_plan plan)
     if (plan->cap_stream) (void)hipStreamDestroy(plan->cap_stream);
     for (auto &it : plan->items)
         if (it.mem) (void)hipFree(it.mem);
-    for (auto &st : plan->steps)
+    for (auto &st : plan->steps) {
         if (st.dev) (void)hipFree(st.dev);
+        if (st.ldev) (void)hipFree(st.ldev);
+    }
     delete plan;
     return TRI_OK;
 }
@@ -1737,6 +1917,10 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
     plan->ctx = ctx;
     plan->prec = prec;
     plan->items.resize((size_t)n_items);
+    struct LevelScope {
+        explicit LevelScope(bool on) { t_level_plan = on; }
+        ~LevelScope() { t_level_plan = false; }
+    } level_scope(batch_mode() == 2 && n_items >= 2 && prec == TRI_F64);
     for (int i = 0; i < n_items; ++i) {
         const tri_item &it = items[i];
         tri_plan_s::Item &pi = plan->items[(size_t)i];
@@ -1857,10 +2041,29 @@ int tri_plan_item_describe(tri_plan plan, int i, char *buf, int len)
     out += " tuned=" + std::to_string(it.tuned);
     for (size_t b = 0; b < plan->steps.size(); ++b)
         for (const auto &m : plan->steps[b].members)
-            if (m.first == i)
-                out += " batch=" + std::to_string(b) + "/" + std::to_string(plan->steps[b].count) + "x" +
-                       std::to_string(plan->steps[b].wavefronts) + "w";
+            if (m.first == i) {
+                if (plan->steps[b].level)
+                    out += " level=" + std::to_string(b) + "/" + std::to_string(plan->steps[b].count);
+                else
+                    out += " batch=" + std::to_string(b) + "/" + std::to_string(plan->steps[b].count) + "x" +
+                           std::to_string(plan->steps[b].wavefronts) + "w";
+            }
     return snprintf(buf, (size_t)len, "%s", out.c_str());
+}
+
+int tri_plan_launch_count(tri_plan plan)
+{
+    if (!plan) return -1;
+    int n = 0;
+    for (const auto &st : plan->steps) {
+        if (!st.members.empty()) {
+            ++n;
+            continue;
+        }
+        const auto &item = plan->items[(size_t)st.item];
+        n += item.launches[(size_t)st.launch].args.nlines > 0 ? 1 : 0;
+    }
+    return n;
 }
 
 }  // extern "C"

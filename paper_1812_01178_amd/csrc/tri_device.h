@@ -16,6 +16,13 @@ typedef double v2d __attribute__((ext_vector_type(2)));   // 16-byte vector acce
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) int gint;
+typedef __attribute__((address_space(1))) v2d gv2d;
+// Constant-address-space views of the factor tables, which no kernel writes
+// while it reads them: wavefront-uniform loads through these are scalar loads
+// whatever else the kernel stores (the level kernel, with many bodies in one
+// function, is too large for the compiler to prove that by itself).
+typedef __attribute__((address_space(4))) double cdouble;
+typedef __attribute__((address_space(4))) int cint;
 
 // ===========================================================================
 // Reduced-system evaluation shared by the solve kernels: the left and right

@@ -134,6 +134,25 @@ struct BatchEntry {
     int method;
 };
 
+// One entry of a dependency level run by a single launch of kLevelThreads-lane
+// workgroups (k_level): the entry's blocks -- the workgroups its own launch
+// would use, of 64 * wpb lanes each -- are packed `sub` to a workgroup, and
+// workgroups [begin, begin + ceil(nblocks / sub)) of the launch run them with
+// the kernel body `body` (instance rows cmax, method, chunked or not).
+enum { kLevelStrided = 0, kLevelStrided2 = 1, kLevelContig = 2, kLevelContigReg = 3 };
+constexpr int kLevelThreads = 512;
+constexpr int kLevelWaves = kLevelThreads / 64;
+struct LevelEntry {
+    SolveArgs a;
+    int64_t begin;
+    int64_t nblocks;
+    int body, cmax, method, chunked;
+    int wpb;          // wavefronts per block
+    int sub;          // blocks per workgroup
+    int lds_sub;      // doubles of LDS per block
+    int lines;        // register-factor body: consecutive lines per block
+};
+
 // Per-line (general) coefficients.
 struct GeneralArgs {
     double *d;
@@ -171,6 +190,9 @@ hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStr
 hipError_t launch_strided_batch(const BatchEntry *entries, int count, int64_t blocks, int wavefronts, int cmax,
                                 int method, bool chunked, size_t lds, hipStream_t s);
 hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s);
+// One dependency level in one launch (device table of `count` entries sorted
+// by begin, `blocks` workgroups, `lds` bytes of LDS per workgroup).
+hipError_t launch_level(const LevelEntry *entries, int count, int64_t blocks, size_t lds, hipStream_t s);
 // Persistent LDS-staged variant for shared matrices (m % C == 0, C even).
 hipError_t launch_contig_staged(const SolveArgs &a, int method, int grid, hipStream_t s);
 size_t contig_staged_lds_bytes(const SolveArgs &a);

@@ -16,6 +16,7 @@
 
 #include <algorithm>
 
+#include "tri_contig_reg.h"
 #include "tri_device.h"
 
 namespace tri {
@@ -291,11 +292,15 @@ __device__ __forceinline__ void strided_block(const SolveArgs &A, int64_t blk, i
     }
 }
 
+// tid: the thread's index in the block (64 * P * kc threads).  A ghost block
+// (a level launch's padding) runs the same barriers and LDS traffic with every
+// lane inactive: it reads and writes no field memory.
 template <int CMAX, int METHOD, bool CHUNKED, bool ACC = false>
-__device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, double *lds)
+__device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, double *lds, int tid,
+                                              bool ghost = false)
 {
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int kc = A.kc, Cs = A.Cs;
     const int r = w / kc, s = w - r * kc;
     const int P = A.P, m = A.m;
@@ -309,16 +314,16 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     int64_t grp, b1;
     strided_block(A, blk, grp, b1);
     const int64_t b0 = grp * 64 + lane;
-    const bool active = b0 < A.nb0;
+    const bool active = !ghost && b0 < A.nb0;
     const int64_t n = A.n;
     const int64_t g = b1 * A.g_b1 + A.g_off;
     const int64_t row0 = (int64_t)r * m + (int64_t)s * Cs;
-    const gdouble *__restrict__ F = (const gdouble *)(A.F + g * (kNumFactors * n) + row0);
-    const gdouble *__restrict__ Fb = F;
-    const gdouble *__restrict__ Fa = F + n;
-    const gdouble *__restrict__ Fc = F + 2 * n;
-    const gdouble *__restrict__ Fv = F + 3 * n;
-    const gdouble *__restrict__ Fw = F + 4 * n;
+    const cdouble *__restrict__ F = (const cdouble *)(A.F + g * (kNumFactors * n) + row0);
+    const cdouble *__restrict__ Fb = F;
+    const cdouble *__restrict__ Fa = F + n;
+    const cdouble *__restrict__ Fc = F + 2 * n;
+    const cdouble *__restrict__ Fv = F + 3 * n;
+    const cdouble *__restrict__ Fw = F + 4 * n;
     const int64_t sj = A.s_j;
     gdouble *__restrict__ p = (gdouble *)(A.d + (active ? b0 : 0) * A.s_b0 + b1 * A.s_b1 + row0 * sj);
 
@@ -330,7 +335,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) x[t] = __builtin_nontemporal_load(p + t * sj);
     }
-    if (r == 0 && s == 0 && (((const gint *)A.flags)[g] & 1)) x[0] = 0.0;   // gauge-pinned row
+    if (r == 0 && s == 0 && (((const cint *)A.flags)[g] & 1)) x[0] = 0.0;   // gauge-pinned row
 
     // Eq. (5): A~_r x~ = d with the precomputed pivots
     double tip_last;
@@ -365,8 +370,8 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         double gin = 0.0;
         for (int s2 = 0; s2 < s; ++s2) gin = fend[(r * kc + s2) * 64 + lane] + pif[r * kc + s2] * gin;
         gp = gin;
-        const gdouble *__restrict__ Fb2 = Fb + A.zero;   // reissue, do not keep pass-1 loads live
-        const gdouble *__restrict__ Fa2 = Fa + A.zero;
+        const cdouble *__restrict__ Fb2 = Fb + A.zero;   // reissue, do not keep pass-1 loads live
+        const cdouble *__restrict__ Fa2 = Fa + A.zero;
 #pragma unroll
         for (int t = 0; t < CMAX; ++t)
             if (t < Cs) {
@@ -388,7 +393,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
         double xin = 0.0;
         for (int s2 = kc - 1; s2 > s; --s2) xin = bbeg[(r * kc + s2) * 64 + lane] + pib[r * kc + s2] * xin;
         xn = xin;
-        const gdouble *__restrict__ Fc2 = Fc + A.zero;
+        const cdouble *__restrict__ Fc2 = Fc + A.zero;
 #pragma unroll
         for (int t = CMAX - 1; t >= 0; --t)
             if (t < Cs) {
@@ -402,7 +407,7 @@ __device__ __forceinline__ void strided_solve(const SolveArgs &A, int64_t blk, d
     if (s == kc - 1) tips[(2 * r + 1) * 64 + lane] = tip_last;
     __syncthreads();
 
-    const gdouble *__restrict__ it = (const gdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
+    const cdouble *__restrict__ it = (const cdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
     double yl, yr;
     interface_unknowns<METHOD>(it, r, P, A.periodic,
                                [&](int q) { return tips[q * 64 + lane]; }, yl, yr);
@@ -435,7 +440,7 @@ template <int CMAX, int METHOD, bool CHUNKED, bool ACC = false>
 __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveArgs A)
 {
     extern __shared__ double lds[];
-    strided_solve<CMAX, METHOD, CHUNKED, ACC>(A, blockIdx.x, lds);
+    strided_solve<CMAX, METHOD, CHUNKED, ACC>(A, blockIdx.x, lds, (int)threadIdx.x);
 }
 
 // ===========================================================================
@@ -447,26 +452,26 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
 // One wavefront per partition (kc = 1), rows kept in VGPRs load -> store.
 // ===========================================================================
 template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
+__device__ __forceinline__ void strided2_solve(const SolveArgs &A, int64_t blk, double *lds, int tid,
+                                               bool ghost = false)
 {
-    extern __shared__ double lds[];
-    const int lane = threadIdx.x & 63;
-    const int r = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = tid & 63;
+    const int r = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int P = A.P, m = A.m;
     double *tips = lds;                                     // [2P][128]
     int64_t grp, b1;
-    strided_block(A, blockIdx.x, grp, b1);
+    strided_block(A, blk, grp, b1);
     const int64_t b0 = grp * 128 + 2 * lane;
-    const bool act0 = b0 < A.nb0, act1 = b0 + 1 < A.nb0;
+    const bool act0 = !ghost && b0 < A.nb0, act1 = !ghost && b0 + 1 < A.nb0;
     const int64_t n = A.n;
     const int64_t g = b1 * A.g_b1 + A.g_off;
     const int64_t row0 = (int64_t)r * m;
-    const gdouble *__restrict__ F = (const gdouble *)(A.F + g * (kNumFactors * n) + row0);
-    const gdouble *__restrict__ Fb = F;
-    const gdouble *__restrict__ Fa = F + n;
-    const gdouble *__restrict__ Fc = F + 2 * n;
-    const gdouble *__restrict__ Fv = F + 3 * n;
-    const gdouble *__restrict__ Fw = F + 4 * n;
+    const cdouble *__restrict__ F = (const cdouble *)(A.F + g * (kNumFactors * n) + row0);
+    const cdouble *__restrict__ Fb = F;
+    const cdouble *__restrict__ Fa = F + n;
+    const cdouble *__restrict__ Fc = F + 2 * n;
+    const cdouble *__restrict__ Fv = F + 3 * n;
+    const cdouble *__restrict__ Fw = F + 4 * n;
     const int64_t sj = A.s_j;
     gdouble *__restrict__ p = (gdouble *)(A.d + (act0 ? b0 : 0) + b1 * A.s_b1 + row0 * sj);
 
@@ -485,7 +490,7 @@ __global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
             }
         }
     }
-    if (r == 0 && (((const gint *)A.flags)[g] & 1)) {
+    if (r == 0 && (((const cint *)A.flags)[g] & 1)) {
         x0[0] = 0.0;
         x1[0] = 0.0;
     }
@@ -514,7 +519,7 @@ __global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
     tips[(2 * r + 1) * 128 + 2 * lane] = l0;
     tips[(2 * r + 1) * 128 + 2 * lane + 1] = l1;
     __syncthreads();
-    const gdouble *__restrict__ it = (const gdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
+    const cdouble *__restrict__ it = (const cdouble *)(A.IT + ((g * P + r) * 2) * (2 * P));
     double yl0, yr0, yl1, yr1;
     interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 128 + 2 * lane]; }, yl0, yr0);
     interface_unknowns<METHOD>(it, r, P, A.periodic, [&](int q) { return tips[q * 128 + 2 * lane + 1]; }, yl1, yr1);
@@ -537,6 +542,13 @@ __global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
                 __builtin_nontemporal_store(x0[t], p + t * sj);
             }
         }
+}
+
+template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
+{
+    extern __shared__ double lds[];
+    strided2_solve<CMAX, METHOD>(A, blockIdx.x, lds, (int)threadIdx.x);
 }
 
 hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStream_t s)
@@ -580,7 +592,7 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided_batch(const 
     const int64_t b = blockIdx.x;
     int i = 0;
     while (i + 1 < count && E[i + 1].begin <= b) ++i;
-    strided_solve<CMAX, METHOD, CHUNKED>(E[i].a, b - E[i].begin, lds);
+    strided_solve<CMAX, METHOD, CHUNKED>(E[i].a, b - E[i].begin, lds, (int)threadIdx.x);
 }
 
 template <int CMAX, int METHOD>
@@ -703,17 +715,16 @@ hipError_t launch_strided(const SolveArgs &a, int method, int chunk_max, hipStre
 // Thomas solution; the tips go through LDS to the other partitions.
 // ===========================================================================
 template <int CMAX, int METHOD>
-__global__ void __launch_bounds__(CMAX > 8 ? 256 : 1024) k_contig(const SolveArgs A)
+__device__ __forceinline__ void contig_solve(const SolveArgs &A, int64_t blk, double *lds, int tid)
 {
-    extern __shared__ double lds[];             // [LPB][2P] tips
-    const int tid = threadIdx.x;
+    // lds: [LPB][2P] tips
     const int LL = A.LL, Lp = A.Lp, C = A.C, m = A.m, P = A.P;
     const int li = tid / LL;
     const int lt = tid - li * LL;
     const int r = lt / Lp;
     const int k = lt - r * Lp;
     const bool inblk = li < A.LPB;
-    const int64_t L = (int64_t)blockIdx.x * A.LPB + li;
+    const int64_t L = blk * A.LPB + li;
     const bool active = inblk && L < A.nlines;
     const int64_t b0 = active ? L % A.nb0 : 0;
     const int64_t b1 = active ? L / A.nb0 : 0;
@@ -812,6 +823,13 @@ __global__ void __launch_bounds__(CMAX > 8 ? 256 : 1024) k_contig(const SolveArg
 }
 
 template <int CMAX, int METHOD>
+__global__ void __launch_bounds__(CMAX > 8 ? 256 : 1024) k_contig(const SolveArgs A)
+{
+    extern __shared__ double lds[];
+    contig_solve<CMAX, METHOD>(A, blockIdx.x, lds, (int)threadIdx.x);
+}
+
+template <int CMAX, int METHOD>
 static hipError_t launch_contig_t(const SolveArgs &a, hipStream_t s)
 {
     const int64_t blocks = (a.nlines + a.LPB - 1) / a.LPB;
@@ -831,6 +849,85 @@ hipError_t launch_contig(const SolveArgs &a, int method, hipStream_t s)
     if (a.C <= 16)
         return method == TRI_PDD ? launch_contig_t<16, TRI_PDD>(a, s) : launch_contig_t<16, TRI_PPT>(a, s);
     return hipErrorInvalidValue;
+}
+
+// ===========================================================================
+// A dependency level in one launch: the strided solves (one or two lines per
+// lane, any partition count and chunking of at most 8 wavefronts, chunks of
+// at most 40 rows) and the contiguous solves (the register-factor body with
+// 4 rows per lane, a run of consecutive lines per block; else the plain body
+// with at most 8 rows per lane) of a ragged batch run side by side in
+// 512-lane workgroups, at most 128 VGPRs (two workgroups a CU).  Each workgroup holds blocks of one entry only --
+// 8 / wpb of them, each with its own LDS region -- so every wavefront of the
+// workgroup takes the same branch and meets the same barriers; blocks past
+// the entry's end (and the waves left over when wpb does not divide 8) run
+// as ghosts.  The arithmetic of every line is that of the entry's own kernel.
+// ===========================================================================
+template <int METHOD>
+__device__ __forceinline__ void level_strided(const LevelEntry &e, int64_t blk, double *l, int tid, bool ghost)
+{
+    if (e.chunked) {
+        switch (e.cmax) {
+        case 8: strided_solve<8, METHOD, true>(e.a, blk, l, tid, ghost); break;
+        case 16: strided_solve<16, METHOD, true>(e.a, blk, l, tid, ghost); break;
+        case 24: strided_solve<24, METHOD, true>(e.a, blk, l, tid, ghost); break;
+        case 32: strided_solve<32, METHOD, true>(e.a, blk, l, tid, ghost); break;
+        default: strided_solve<40, METHOD, true>(e.a, blk, l, tid, ghost); break;
+        }
+    } else {
+        switch (e.cmax) {
+        case 8: strided_solve<8, METHOD, false>(e.a, blk, l, tid, ghost); break;
+        case 16: strided_solve<16, METHOD, false>(e.a, blk, l, tid, ghost); break;
+        case 24: strided_solve<24, METHOD, false>(e.a, blk, l, tid, ghost); break;
+        case 32: strided_solve<32, METHOD, false>(e.a, blk, l, tid, ghost); break;
+        default: strided_solve<40, METHOD, false>(e.a, blk, l, tid, ghost); break;
+        }
+    }
+}
+
+template <int METHOD>
+__device__ __forceinline__ void level_body(const LevelEntry &e, int64_t blk, double *l, int tid, bool ghost)
+{
+    if (e.body == kLevelStrided) {
+        level_strided<METHOD>(e, blk, l, tid, ghost);
+    } else if (e.body == kLevelStrided2) {
+        switch (e.cmax) {
+        case 8: strided2_solve<8, METHOD>(e.a, blk, l, tid, ghost); break;
+        case 16: strided2_solve<16, METHOD>(e.a, blk, l, tid, ghost); break;
+        default: strided2_solve<24, METHOD>(e.a, blk, l, tid, ghost); break;
+        }
+    } else if (e.body == kLevelContigReg) {
+        contig_reg_solve<4, METHOD, true>(e.a, ghost ? e.a.nlines : blk * e.lines, 1, e.lines, tid, l);
+    } else {
+        if (e.cmax <= 4) contig_solve<4, METHOD>(e.a, blk, l, tid);
+        else contig_solve<8, METHOD>(e.a, blk, l, tid);
+    }
+}
+
+__global__ void __launch_bounds__(kLevelThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_level(const LevelEntry *__restrict__ E, int count)
+{
+    extern __shared__ double lds[];
+    const int64_t wg = blockIdx.x;
+    int i = 0;
+    while (i + 1 < count && E[i + 1].begin <= wg) ++i;
+    const LevelEntry &e = E[i];
+    const int nt = 64 * e.wpb;
+    const int sb = __builtin_amdgcn_readfirstlane((int)threadIdx.x / nt);   // block within the workgroup
+    const int tid = (int)threadIdx.x - sb * nt;
+    int64_t blk = (wg - e.begin) * e.sub + sb;
+    const bool ghost = sb >= e.sub || blk >= e.nblocks;
+    if (ghost) blk = 0;
+    double *l = lds + (int64_t)sb * e.lds_sub;
+    if (e.method == TRI_PDD) level_body<TRI_PDD>(e, blk, l, tid, ghost);
+    else level_body<TRI_PPT>(e, blk, l, tid, ghost);
+}
+
+hipError_t launch_level(const LevelEntry *entries, int count, int64_t blocks, size_t lds, hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_level, dim3((unsigned)blocks), dim3(kLevelThreads), lds, s, entries, count);
+    return hipGetLastError();
 }
 
 // ===========================================================================

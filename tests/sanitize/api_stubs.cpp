@@ -83,6 +83,7 @@ hipError_t launch_strided_batch(const BatchEntry *, int, int64_t, int, int, int,
     return counted();
 }
 hipError_t launch_contig(const SolveArgs &, int, hipStream_t) { return counted(); }
+hipError_t launch_level(const LevelEntry *, int, int64_t, size_t, hipStream_t) { return counted(); }
 hipError_t launch_contig_staged(const SolveArgs &, int, int, hipStream_t) { return counted(); }
 size_t contig_staged_lds_bytes(const SolveArgs &) { return 4096; }
 int contig_staged_grid(const SolveArgs &, int) { return 256; }

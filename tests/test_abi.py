@@ -55,6 +55,7 @@ def test_null_context_and_status_strings(T):
     assert T.tri_status_string(T.TRI_E_SHAPE).startswith("invalid shape")
     assert T.tri_status_string(99) == "unknown status"
     assert L.tri_plan_item_partitions(None, 0) == -1
+    assert L.tri_plan_launch_count(None) == -1
     assert L.tri_stream_copy(None, None, None, 0) == T.TRI_E_ARG
     assert L.tri_set_pdd_tolerance(None, 1e-12) == T.TRI_E_ARG
     assert L.tri_reserve(None, 64, 4, 1) == T.TRI_E_ARG

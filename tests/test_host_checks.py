@@ -179,12 +179,13 @@ def test_bench_cpu_baseline_leaves_its_inputs_untouched(orc):
 
 def test_tune_table_lists_the_ragged_partition_choices():
     """The shipped tuning table fixes the partition count of every item of the
-    ragged eight-sub-grid batch (x, y, z sweeps and Poisson, FP64 and FP32+refine),
-    so every run of the benchmark measures the same configuration."""
+    ragged eight-sub-grid batch (x, y, z sweeps and Poisson, FP64 and FP32+refine,
+    and FP64 with the levels as level launches), so every run of the benchmark
+    measures the same configuration."""
     table = open(os.path.join(ROOT, "paper_1812_01178_amd", "tune_gfx950.txt")).read().splitlines()
     keys = {ln.rsplit("|", 1)[0]: int(ln.rsplit("|", 1)[1]) for ln in table if "|" in ln and not ln.startswith("#")}
-    for prec in (0, 1):
+    for prec, suffix in ((0, ""), (1, ""), (0, " L")):     # " L": the FP64 plan's level launches
         for nx, ny, nz in W.RAGGED_SUBGRIDS:
             for kind, per, method, n3 in ((0, 0, 0, nz), (1, 0, 0, nz), (2, 1, 0, nz), (3, 0, 1, nz // 2 + 1)):
-                key = f"partitions k{kind} m{method} per{per} prec{prec} Nx{nx} Ny{ny} Nz{n3}"
+                key = f"partitions k{kind} m{method} per{per} prec{prec} Nx{nx} Ny{ny} Nz{n3}{suffix}"
                 assert keys.get(key, 0) in (1, 2, 4, 8, 16), key
