@@ -1554,6 +1554,7 @@ static int autotune(tri_ctx ctx, const Problem &pb, const Tables &T, const Launc
 struct tri_plan_s {
     tri_ctx ctx = nullptr;
     tri_prec prec = TRI_F64;
+    int batch = 1;            // grouping of a level's launches (see kDefaultBatchMode)
     struct Item {
         Problem pb;
         Tables T;
@@ -1768,7 +1769,7 @@ tri_status build_schedule(tri_plan plan)
             refs.push_back({i, j, level, sp});
             nlevels = std::max(nlevels, level + 1);
         }
-    const int mode = level_plan() ? 2 : std::min(batch_mode(), 1);
+    const int mode = plan->batch;
     const bool batching = mode != 0;
     for (int lev = 0; lev < nlevels; ++lev) {
         if (mode == 2) {
@@ -1905,8 +1906,12 @@ tri_status tri_plan_destroy(tri_plan plan)
     return TRI_OK;
 }
 
-tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
-                           tri_plan *out)
+}  // extern "C"
+
+namespace {
+
+// Plan creation with the grouping `mode` of its levels (see kDefaultBatchMode).
+tri_status plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec, int mode, tri_plan *out)
 {
     if (!ctx || !out || (n_items > 0 && !items) || n_items < 0) return TRI_E_ARG;
     *out = nullptr;
@@ -1920,7 +1925,8 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
     struct LevelScope {
         explicit LevelScope(bool on) { t_level_plan = on; }
         ~LevelScope() { t_level_plan = false; }
-    } level_scope(batch_mode() == 2 && n_items >= 2 && prec == TRI_F64);
+    } level_scope(mode == 2 && n_items >= 2 && prec == TRI_F64);
+    plan->batch = level_plan() ? 2 : std::min(mode, 1);
     for (int i = 0; i < n_items; ++i) {
         const tri_item &it = items[i];
         tri_plan_s::Item &pi = plan->items[(size_t)i];
@@ -1967,6 +1973,16 @@ tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_
     }
     *out = plan;
     return TRI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tri_status tri_plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec prec,
+                           tri_plan *out)
+{
+    return plan_create(ctx, items, n_items, prec, batch_mode(), out);
 }
 
 tri_status tri_plan_execute(tri_plan plan)
@@ -2340,8 +2356,12 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
             if (dir == 2) z[c] = it;
             else xy[2 * c + dir] = it;
         }
-        st = tri_plan_create(ctx, xy, 6, TRI_F64, &ns->plans[s]);
-        if (!st) st = tri_plan_create(ctx, z, 3, TRI_F64, &ns->zplans[s]);
+        // (per-kernel-instance batches: the three x sweeps keep the register-factor
+        // kernel with 8 rows per lane, which a level launch cannot hold, and the
+        // three y sweeps share one batched launch anyway)
+        const int mode = std::min(batch_mode(), 1);
+        st = plan_create(ctx, xy, 6, TRI_F64, mode, &ns->plans[s]);
+        if (!st) st = plan_create(ctx, z, 3, TRI_F64, mode, &ns->zplans[s]);
         if (st) {
             const std::string why = ctx->last_error;
             ns_release(ns);
