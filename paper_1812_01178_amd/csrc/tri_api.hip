@@ -1356,6 +1356,8 @@ void tune_cache_store(const std::string &key, int v)
     fclose(fp);
 }
 
+constexpr size_t kLevelMaxLds = 64 * 1024;   // bytes of LDS a level workgroup may take
+
 // The level kernel's entry for an FP64 launch, if it has a body there:
 // strided launches of at most 8 wavefronts with chunks of at most 40 rows
 // (24 with two lines per lane) keep their launch shape; contiguous launches
@@ -1411,6 +1413,8 @@ bool level_entry(const Launch &l, int method, LevelEntry &e)
         e.nblocks = (a.nlines + a.LPB - 1) / a.LPB;
         e.lds_sub = 2 * a.P * a.LPB;
     }
+    // a workgroup's LDS (one region per block it can hold) within 64 KB
+    if (sizeof(double) * (size_t)e.lds_sub * (size_t)((kLevelWaves + e.wpb - 1) / e.wpb) > kLevelMaxLds) return false;
     e.a = a;
     e.method = method;
     return true;

@@ -409,3 +409,34 @@ def test_level_launch_register_factor_body(T, ctx, orc, monkeypatch):
         ref = fields[s].copy()
         orc.adi_sweep(orc.PDD, 0, ref, a, b, c, P, False)
         assert line_relerr(level[s], ref, axis=2) <= TOL, shapes[s]
+
+
+def test_level_launch_keeps_solves_whose_lds_does_not_fit_apart(T, ctx, orc, monkeypatch):
+    """A contiguous solve whose register-factor blocks would take more than the
+    level workgroup's 64 KB of LDS (256 rows at P = 16: eight 64-lane blocks
+    with the 16 x 16 reduced-system rows each) keeps a launch of its own; the
+    other two share the level launch.  All three match the oracle."""
+    monkeypatch.setenv("TRI_AUTOTUNE", "0")
+    monkeypatch.delenv("TRI_BATCH", raising=False)
+    shapes = [(256, 40, 3, 16), (512, 40, 3, 4), (1024, 24, 5, 8)]
+    rng = np.random.default_rng(210)
+    fields = [rng.standard_normal((nz, ny, nx)) for nx, ny, nz, _ in shapes]
+    coefs = [W.momentum_uniform(nx) for nx, _, _, _ in shapes]
+    us = [dev(f) for f in fields]
+    cf = [tuple(dev(v) for v in c) for c in coefs]
+    items = [dict(kind=T.TRI_ITEM_ADI_X, field=u, Nx=nx, Ny=ny, Nz=nz, a=c[0], b=c[1], c=c[2], P=P, periodic=0,
+                  method=T.TRI_PDD) for u, c, (nx, ny, nz, P) in zip(us, cf, shapes)]
+    plan = T.tri_plan_create(ctx, items)
+    try:
+        descr = [T.tri_plan_item_describe(plan, i) for i in range(3)]
+        assert "level=" not in descr[0] and all("level=" in d for d in descr[1:]), descr
+        assert T.tri_plan_launch_count(plan) == 2
+        T.tri_plan_execute(plan)
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_plan_destroy(plan)
+    for s, (nx, ny, nz, P) in enumerate(shapes):
+        a, b, c = coefs[s]
+        ref = fields[s].copy()
+        orc.adi_sweep(orc.PDD, 0, ref, a, b, c, P, False)
+        assert line_relerr(host(us[s]), ref, axis=2) <= TOL, shapes[s]
