@@ -5,6 +5,7 @@
 // solves, workspace refusal and tri_reserve, plans with ragged items, capture
 // and destruction.  Exit status 0 when every check holds.
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <vector>
@@ -193,6 +194,21 @@ int main()
             {TRI_ITEM_ADI_Z, u2.data(), 128, 16, 12, a12.data(), b12.data(), c12.data(), nullptr, 2, 1, TRI_PDD},
             {TRI_ITEM_POISSON, ph2.data(), 128, 16, 7, my.data(), nullptr, mc.data(), lam2.data(), 4, 0, TRI_PPT},
         };
+        // every grouping of a level's launches (one launch per solve, per kernel
+        // instance, per level): execute queues exactly the launches it reports
+        for (const char *batch : {"0", "1", "2"}) {
+            setenv("TRI_BATCH", batch, 1);
+            tri_plan plan = nullptr;
+            CHECK(tri_plan_create(ctx, items, 7, TRI_F64, &plan) == TRI_OK && plan);
+            if (!plan) continue;
+            const int n = tri_plan_launch_count(plan), l0 = g_launches;
+            CHECK(n >= 1 && n <= 7);
+            CHECK(tri_plan_execute(plan) == TRI_OK);
+            CHECK(g_launches - l0 == n);
+            CHECK(tri_plan_destroy(plan) == TRI_OK);
+        }
+        unsetenv("TRI_BATCH");
+        CHECK(tri_plan_launch_count(nullptr) == -1);
         for (tri_prec prec : {TRI_F64, TRI_F32_REFINE}) {
             tri_plan plan = nullptr;
             CHECK(tri_plan_create(ctx, items, 7, prec, &plan) == TRI_OK && plan);
