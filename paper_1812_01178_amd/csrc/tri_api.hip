@@ -1198,8 +1198,15 @@ tri_status projection3d_divergence_rfft(tri_ctx ctx, const double *u, const doub
     return TRI_OK;
 }
 
-tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, double *u, double *v, double *w,
-                                double dx, const double *dy, double dz, int64_t Nx, int64_t Ny, int64_t Nz)
+}  // extern "C"
+
+namespace {
+
+// projection3d_correct; with press also press += phi * pscale (the
+// fractional step's pressure update, from the same read of phi).
+tri_status projection3d_correct_p(tri_ctx ctx, const double *phihat, double *phi, double *u, double *v, double *w,
+                                  double dx, const double *dy, double dz, int64_t Nx, int64_t Ny, int64_t Nz,
+                                  double *press, double pscale)
 {
     if (!ctx) return TRI_E_ARG;
     if (!(dx > 0.0)) return fail(ctx, TRI_E_ARG, "projection3d_correct: dx must be > 0");
@@ -1219,13 +1226,16 @@ tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, 
     A.w_io = w;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, launch_fft(A, kFftInverseCorrect, ctx->stream));
-    HIP_TRY(ctx, launch_grad_xy(u, v, phi, dy, dx, Nx, Ny, Nz, ctx->stream));
+    if (press) HIP_TRY(ctx, launch_grad_xy_pressure(u, v, phi, dy, dx, Nx, Ny, Nz, press, pscale, ctx->stream));
+    else HIP_TRY(ctx, launch_grad_xy(u, v, phi, dy, dx, Nx, Ny, Nz, ctx->stream));
     return TRI_OK;
 }
 
-tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, double dx, const double *dy, double dz,
-                             const double *ay, const double *cy, const double *lamz, const double *lamx,
-                             double *phihat, double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P)
+// projection3d_step; with press the last kernel also adds phi * pscale to it.
+tri_status projection3d_step_p(tri_ctx ctx, double *u, double *v, double *w, double dx, const double *dy, double dz,
+                               const double *ay, const double *cy, const double *lamz, const double *lamx,
+                               double *phihat, double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P, double *press,
+                               double pscale)
 {
     if (!ctx) return TRI_E_ARG;
     FftShape S, Sx;
@@ -1257,7 +1267,25 @@ tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, doubl
     if (st) return st;
     st = streamwise_idct(ctx, phihat, Nx, nk * Ny);
     if (st) return st;
-    return projection3d_correct(ctx, phihat, phi, u, v, w, dx, dy, dz, Nx, Ny, Nz);
+    return projection3d_correct_p(ctx, phihat, phi, u, v, w, dx, dy, dz, Nx, Ny, Nz, press, pscale);
+}
+
+}  // namespace
+
+extern "C" {
+
+tri_status projection3d_correct(tri_ctx ctx, const double *phihat, double *phi, double *u, double *v, double *w,
+                                double dx, const double *dy, double dz, int64_t Nx, int64_t Ny, int64_t Nz)
+{
+    return projection3d_correct_p(ctx, phihat, phi, u, v, w, dx, dy, dz, Nx, Ny, Nz, nullptr, 0.0);
+}
+
+tri_status projection3d_step(tri_ctx ctx, double *u, double *v, double *w, double dx, const double *dy, double dz,
+                             const double *ay, const double *cy, const double *lamz, const double *lamx,
+                             double *phihat, double *phi, int64_t Nx, int64_t Ny, int64_t Nz, int P)
+{
+    return projection3d_step_p(ctx, u, v, w, dx, dy, dz, ay, cy, lamz, lamx, phihat, phi, Nx, Ny, Nz, P, nullptr,
+                               0.0);
 }
 
 tri_status projection_step(tri_ctx ctx, double *v, double *w, const double *dy, double dz, const double *ay,
@@ -2446,10 +2474,11 @@ tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
             if (st) return st;
             HIP_TRY(ctx, launch_ns_update(u, v, w, ns->D[0], ns->D[1], ns->D[2], Nx, Ny, Nz, ctx->stream));
         }
-        st = projection3d_step(ctx, u, v, w, ns->dx, ns->dy, ns->dz, ns->ay, ns->cy, ns->lamz, ns->lamx, ns->phihat,
-                               ns->phi, Nx, Ny, Nz, ns->P_poisson);
+        // the projection, whose last kernel also makes the pressure update
+        // p += phi / (alpha dt)
+        st = projection3d_step_p(ctx, u, v, w, ns->dx, ns->dy, ns->dz, ns->ay, ns->cy, ns->lamz, ns->lamx,
+                                 ns->phihat, ns->phi, Nx, Ny, Nz, ns->P_poisson, p, 1.0 / (A.alpha * ns->dt));
         if (st) return st;
-        HIP_TRY(ctx, launch_ns_pressure(p, ns->phi, 1.0 / (A.alpha * ns->dt), cells, ctx->stream));
     }
     return TRI_OK;
 }

@@ -29,6 +29,7 @@
 #include <cstdlib>
 
 #include "tri_internal.h"
+#include "tri_ns.h"
 
 namespace tri {
 namespace {
@@ -536,8 +537,9 @@ __global__ void __launch_bounds__(256) k_grad_y(double *v, const double *phi, co
 // cell (k, j, i), v[k][j][i] -= (phi_j - phi_{j-1})/h_j for j >= 1 and
 // u[k][j][i] -= (phi_i - phi_{i-1})/dx for i >= 1 (the neighbours' phi are
 // read again from cache); the wall faces j = 0, Ny and i = 0, Nx are left.
+// With pp (the time step's pressure, cells like phi) also pp += phi ps.
 __global__ void __launch_bounds__(256) k_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx,
-                                                  int Nx, int Ny, int nbx)
+                                                  int Nx, int Ny, int nbx, double *pp, double ps)
 {
     const int64_t row = blockIdx.x / nbx;                       // k Ny + j
     const int i = (int)(blockIdx.x - row * nbx) * 256 + (int)threadIdx.x;
@@ -554,6 +556,10 @@ __global__ void __launch_bounds__(256) k_grad_xy(double *u, double *v, const dou
     if (i >= 1) {
         double *up = u + row * (Nx + 1) + i;
         __builtin_nontemporal_store(__builtin_nontemporal_load(up) - (pc - p[-1]) / dx, up);
+    }
+    if (pp) {
+        double *q = pp + row * Nx + i;
+        __builtin_nontemporal_store(__builtin_nontemporal_load(q) + pc * ps, q);
     }
 }
 
@@ -770,16 +776,22 @@ hipError_t launch_dct(const DctArgs &A, bool inverse, hipStream_t s)
     return launch_dct_t<1, kDctMaxN>(A, inverse, s);
 }
 
-hipError_t launch_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
-                          int64_t Ny, int64_t Nz, hipStream_t s)
+hipError_t launch_grad_xy_pressure(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
+                                   int64_t Ny, int64_t Nz, double *p, double ps, hipStream_t s)
 {
     if (Nx < 1 || Ny < 1 || Nz < 1) return hipSuccess;
     const int64_t nbx = (Nx + 255) / 256;
     const int64_t blocks = nbx * Ny * Nz;
     if (blocks > 0x7fffffffLL || Nx > 0x7fffffffLL || Ny > 0x7fffffffLL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_grad_xy, dim3((unsigned)blocks), dim3(256), 0, s, u, v, phi, dy, dx, (int)Nx, (int)Ny,
-                       (int)nbx);
+                       (int)nbx, p, ps);
     return hipGetLastError();
+}
+
+hipError_t launch_grad_xy(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
+                          int64_t Ny, int64_t Nz, hipStream_t s)
+{
+    return launch_grad_xy_pressure(u, v, phi, dy, dx, Nx, Ny, Nz, nullptr, 0.0, s);
 }
 
 hipError_t launch_grad_y(double *v, const double *phi, const double *dy, int64_t Nx, int64_t Ny, int64_t Nz,

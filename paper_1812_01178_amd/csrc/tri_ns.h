@@ -38,5 +38,10 @@ hipError_t launch_ns_rhs(const NsRhsArgs &A, hipStream_t s);
 hipError_t launch_ns_update(double *u, double *v, double *w, const double *du, const double *dv, const double *dw,
                             int64_t Nx, int64_t Ny, int64_t Nz, hipStream_t s);
 hipError_t launch_ns_pressure(double *p, const double *phi, double scale, int64_t n, hipStream_t s);
+// The 3-D step's wall-parallel corrections (launch_grad_xy) that also add
+// phi * ps to the pressure p (cells like phi): the pressure update of a
+// sub-step from the same read of phi (tri_fft.hip).
+hipError_t launch_grad_xy_pressure(double *u, double *v, const double *phi, const double *dy, double dx, int64_t Nx,
+                                   int64_t Ny, int64_t Nz, double *p, double ps, hipStream_t s);
 
 }  // namespace tri

@@ -122,6 +122,11 @@ hipError_t launch_ns_update(double *, double *, double *, const double *, const 
     return counted();
 }
 hipError_t launch_ns_pressure(double *, const double *, double, int64_t, hipStream_t) { return counted(); }
+hipError_t launch_grad_xy_pressure(double *, double *, const double *, const double *, double, int64_t, int64_t,
+                                   int64_t, double *, double, hipStream_t)
+{
+    return counted();
+}
 
 // Transform shapes: the documented contract (the real ones live with the
 // transform kernels): N = 2^a 3^b 5^c within the limit.
