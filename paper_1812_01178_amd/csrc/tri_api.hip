@@ -2237,19 +2237,31 @@ namespace {
 // The accumulating form of a z sweep's launch: the strided kernel with one
 // line per lane (the two-lines-per-lane kernel has no accumulating
 // instance), the same partitions and factor tables.
-bool ns_acc_launch(const Launch &base, Launch &out)
+// A strided launch as its accumulating form with one line per lane.
+bool acc_one_line(Launch &l)
 {
-    if (base.kind != 0 || base.refine) return false;
-    out = base;
-    SolveArgs &a = out.args;
+    SolveArgs &a = l.args;
     if (a.lpl == 2) {
         a.lpl = 1;
         a.kc = 1;
         a.Cs = a.m;
         a.ngroups0 = (a.nb0 + 63) / 64;
-        out.chunk_max = pick_chunk(a.m);
+        l.chunk_max = pick_chunk(a.m);
     }
-    return strided_acc_supported(TRI_PDD, out.chunk_max);
+    return strided_acc_supported(TRI_PDD, l.chunk_max);
+}
+
+// The accumulating form of a z sweep's launch: two lines per lane where the
+// plan chose that shape and the target's layout keeps line pairs 16-byte
+// aligned (`pairs`), else one line per lane (which also serves at a step
+// whose target array is not 16-byte aligned).
+bool ns_acc_launch(const Launch &base, bool pairs, Launch &out)
+{
+    if (base.kind != 0 || base.refine) return false;
+    Launch one = base;
+    if (!acc_one_line(one)) return false;
+    out = (pairs && base.args.lpl == 2 && strided2_acc_supported(TRI_PDD, base.chunk_max)) ? base : one;
+    return true;
 }
 
 bool ns_overlap(const void *a, size_t na, const void *b, size_t nb)
@@ -2401,7 +2413,10 @@ tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out)
         }
         for (int c = 0; c < 3; ++c) {
             const auto &item = ns->zplans[s]->items[(size_t)c];
-            if (item.launches.size() != 1 || !ns_acc_launch(item.launches[0], ns->zacc[s][c])) ns->fused = false;
+            // line pairs of v (a_j = (Ny+1) Nx, a_b1 = Nx) and w stay aligned (Nx is
+            // even); those of u (a_b1 = Nx + 1) do not
+            if (item.launches.size() != 1 || !ns_acc_launch(item.launches[0], c > 0, ns->zacc[s][c]))
+                ns->fused = false;
         }
     }
     const char *e = getenv("TRI_NS_FUSE");
@@ -2463,6 +2478,7 @@ tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
             const int64_t aj[3] = {Ny * (Nx + 1), (Ny + 1) * Nx, Ny * Nx}, ab1[3] = {Nx + 1, Nx, Nx};
             for (int c = 0; c < 3; ++c) {
                 Launch l = ns->zacc[s][c];
+                if (l.args.lpl == 2 && (uintptr_t)tgt[c] % 16 != 0) (void)acc_one_line(l);
                 l.args.acc = tgt[c];
                 l.args.a_j = aj[c];
                 l.args.a_b0 = 1;

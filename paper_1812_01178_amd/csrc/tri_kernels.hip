@@ -451,7 +451,10 @@ __global__ void __launch_bounds__(CMAX > 40 ? 512 : 1024) k_strided(const SolveA
 // lines' recurrences side by side on the same wavefront-uniform factors.
 // One wavefront per partition (kc = 1), rows kept in VGPRs load -> store.
 // ===========================================================================
-template <int CMAX, int METHOD>
+// ACC: the solutions are added to A.acc in its own layout (a_b0 = 1, pairs
+// 16-byte aligned) instead of being stored over d, a few rows at a time so
+// that the added rows need few registers.
+template <int CMAX, int METHOD, bool ACC = false>
 __device__ __forceinline__ void strided2_solve(const SolveArgs &A, int64_t blk, double *lds, int tid,
                                                bool ghost = false)
 {
@@ -530,6 +533,39 @@ __device__ __forceinline__ void strided2_solve(const SolveArgs &A, int64_t blk, 
             x0[t] = x0[t] - yl0 * Fv[t] - yr0 * Fw[t];
             x1[t] = x1[t] - yl1 * Fv[t] - yr1 * Fw[t];
         }
+    if (ACC) {
+        constexpr int B = 6;
+        const int64_t aj = A.a_j;
+        gdouble *__restrict__ q = (gdouble *)(A.acc + (act0 ? b0 : 0) + b1 * A.a_b1 + row0 * aj);
+#pragma unroll
+        for (int t0 = 0; t0 < CMAX; t0 += B) {
+            v2d z[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int t = t0 + u;
+                z[u] = v2d{0.0, 0.0};
+                if (t < CMAX && t < m) {
+                    if (act1) z[u] = __builtin_nontemporal_load((const gv2d *)(q + t * aj));
+                    else if (act0) z[u].x = __builtin_nontemporal_load(q + t * aj);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int t = t0 + u;
+                if (t < CMAX && t < m) {
+                    if (act1) {
+                        v2d v;
+                        v.x = z[u].x + x0[t];
+                        v.y = z[u].y + x1[t];
+                        __builtin_nontemporal_store(v, (gv2d *)(q + t * aj));
+                    } else if (act0) {
+                        __builtin_nontemporal_store(z[u].x + x0[t], q + t * aj);
+                    }
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < CMAX; ++t)
         if (t < m) {
@@ -544,12 +580,14 @@ __device__ __forceinline__ void strided2_solve(const SolveArgs &A, int64_t blk, 
         }
 }
 
-template <int CMAX, int METHOD>
+template <int CMAX, int METHOD, bool ACC = false>
 __global__ void __launch_bounds__(1024) k_strided2(const SolveArgs A)
 {
     extern __shared__ double lds[];
-    strided2_solve<CMAX, METHOD>(A, blockIdx.x, lds, (int)threadIdx.x);
+    strided2_solve<CMAX, METHOD, ACC>(A, blockIdx.x, lds, (int)threadIdx.x);
 }
+
+bool strided2_acc_supported(int method, int chunk_max) { return method == TRI_PDD && chunk_max == 24; }
 
 hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStream_t s)
 {
@@ -557,7 +595,12 @@ hipError_t launch_strided2(const SolveArgs &a, int method, int chunk_max, hipStr
     const size_t lds = sizeof(double) * 2 * (size_t)a.P * 128;
     const dim3 grid((unsigned)blocks), block(64 * a.P);
     const bool pdd = method == TRI_PDD;
-    if (a.acc) return hipErrorInvalidValue;   // no accumulating instance (it would spill)
+    if (a.acc) {
+        // accumulating instances: PDD, 24 rows (the spanwise lines at P = 16)
+        if (!strided2_acc_supported(method, chunk_max)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_strided2<24, TRI_PDD, true>), grid, block, lds, s, a);
+        return hipGetLastError();
+    }
     switch (chunk_max) {
     case 8:
         if (pdd) hipLaunchKernelGGL((k_strided2<8, TRI_PDD>), grid, block, lds, s, a);

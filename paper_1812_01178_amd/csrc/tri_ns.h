@@ -38,6 +38,10 @@ hipError_t launch_ns_rhs(const NsRhsArgs &A, hipStream_t s);
 hipError_t launch_ns_update(double *u, double *v, double *w, const double *du, const double *dv, const double *dw,
                             int64_t Nx, int64_t Ny, int64_t Nz, hipStream_t s);
 hipError_t launch_ns_pressure(double *p, const double *phi, double scale, int64_t n, hipStream_t s);
+// Whether launch_strided2 (two lines per lane) has an accumulating instance
+// (a.acc set: a_b0 = 1, the target's line pairs 16-byte aligned) for this
+// method and chunk instance (tri_kernels.hip).
+bool strided2_acc_supported(int method, int chunk_max);
 // The 3-D step's wall-parallel corrections (launch_grad_xy) that also add
 // phi * ps to the pressure p (cells like phi): the pressure update of a
 // sub-step from the same read of phi (tri_fft.hip).

@@ -76,6 +76,7 @@ static hipError_t counted() { ++g_launches; return hipSuccess; }
 hipError_t launch_factor(const MatSrc &, const Tables &, int *, hipStream_t) { return counted(); }
 hipError_t launch_strided(const SolveArgs &, int, int, hipStream_t) { return counted(); }
 bool strided_acc_supported(int method, int chunk_max) { return method == 0 && chunk_max <= 24; }
+bool strided2_acc_supported(int method, int chunk_max) { return method == 0 && chunk_max == 24; }
 size_t strided_lds_bytes(const SolveArgs &) { return 4096; }
 hipError_t launch_strided2(const SolveArgs &, int, int, hipStream_t) { return counted(); }
 hipError_t launch_strided_batch(const BatchEntry *, int, int64_t, int, int, int, bool, size_t, hipStream_t)

@@ -138,8 +138,11 @@ def test_benchmark_grid_step_is_divergence_free(T, ctx):
                                                    (2048, 256, 288, (8, 4, 16), 8)])
 def test_fused_update_matches_the_separate_update(T, ctx, monkeypatch, Nx, Ny, Nz, P_adi, P_poi):
     """The z sweeps adding their solutions into u, v, w (TRI_NS_FUSE=1: required,
-    so ns_create fails if the fused form is not taken) give the same bits as
-    the z sweeps followed by the separate update kernel (TRI_NS_FUSE=0)."""
+    so ns_create fails if the fused form is not taken; two lines per lane into
+    v and w where the plan takes that shape, one line per lane into u) give the
+    same bits as the z sweeps followed by the separate update kernel
+    (TRI_NS_FUSE=0), also with v and w 8 bytes off 16-byte alignment (the
+    one-line-per-lane form then adds into them)."""
     dx, dz = 1.0 / Nx, 1.0 / Nz
     dy = np.diff(W.tanh_faces(Ny))
     g = torch.Generator(device="cuda").manual_seed(5)
@@ -151,21 +154,33 @@ def test_fused_update_matches_the_separate_update(T, ctx, monkeypatch, Nx, Ny, N
     v0[:, Ny, :] = 0.0
     w0 = 0.1 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
     p0 = 0.01 * torch.randn((Nz, Ny, Nx), dtype=torch.float64, device="cuda", generator=g)
+    def offset_copy(t):
+        """t's values in a view that starts 8 bytes past a 16-byte boundary"""
+        buf = torch.empty(t.numel() + 1, dtype=t.dtype, device=t.device)
+        view = buf[1:].view(t.shape)
+        view.copy_(t)
+        return view
+
     out = {}
-    for fuse in ("0", "1"):
+    for case in ("0", "1", "1-offset"):
+        fuse = case.split("-")[0]
         monkeypatch.setenv("TRI_NS_FUSE", fuse)
-        print(f"ns_step grid {Nx}x{Ny}x{Nz} TRI_NS_FUSE={fuse}", flush=True)
+        print(f"ns_step grid {Nx}x{Ny}x{Nz} TRI_NS_FUSE={fuse} ({case})", flush=True)
         ns = T.ns_create(ctx, Nx, Ny, Nz, dx, dz, dy, 1e-3, 1e-3, P_adi, P_poi)
         try:
             f = [t.clone() for t in (u0, v0, w0, p0)]
+            if case.endswith("offset"):
+                f[1], f[2] = offset_copy(v0), offset_copy(w0)
+                assert f[1].data_ptr() % 16 == 8 and f[2].data_ptr() % 16 == 8
             for _ in range(2):
                 T.ns_step(ns, *f, ctx)
             T.tri_sync_status(ctx)
         finally:
             T.ns_destroy(ns)
-        out[fuse] = f
-    for name, a, b in zip("uvwp", out["0"], out["1"]):
-        assert torch.equal(a, b), name
+        out[case] = f
+    for case in ("1", "1-offset"):
+        for name, a, b in zip("uvwp", out["0"], out[case]):
+            assert torch.equal(a, b), (case, name)
 
 
 def test_time_step_replays_from_a_hip_graph(T, ctx):
