@@ -2478,7 +2478,9 @@ tri_status ns_step(tri_ns ns, double *u, double *v, double *w, double *p)
             const int64_t aj[3] = {Ny * (Nx + 1), (Ny + 1) * Nx, Ny * Nx}, ab1[3] = {Nx + 1, Nx, Nx};
             for (int c = 0; c < 3; ++c) {
                 Launch l = ns->zacc[s][c];
-                if (l.args.lpl == 2 && (uintptr_t)tgt[c] % 16 != 0) (void)acc_one_line(l);
+                // two lines per lane add 16-byte pairs: the target and its strides must keep them aligned
+                if (l.args.lpl == 2 && ((uintptr_t)tgt[c] % 16 != 0 || aj[c] % 2 != 0 || ab1[c] % 2 != 0))
+                    (void)acc_one_line(l);
                 l.args.acc = tgt[c];
                 l.args.a_j = aj[c];
                 l.args.a_b0 = 1;
