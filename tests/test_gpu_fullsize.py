@@ -12,6 +12,7 @@ relative error.  Each solve runs on the pristine input.
   extended-precision exact solution (Poisson modes k <= 2 stay FP64: the oracle's PPT)
 * shifted wall-normal solves of the 3-D pressure step, 145 x 256 x 2048 complex (PPT, P=8),
   one matrix per (k, i), the (0, 0) line pinned
+* the ragged eight-sub-grid step in one launch per dependency level (x -> y -> z composed, Poisson)
 """
 import numpy as np
 import pytest
@@ -136,3 +137,47 @@ def test_fullsize_independent_lines(T, ctx, orc):
     T.tri_sync_status(ctx)
     torch.cuda.synchronize()
     assert line_relerr(dd.cpu().numpy(), ref.reshape(n, nlines), axis=0) <= TOL
+
+
+def test_fullsize_ragged_step_level_launches(T, ctx, orc, monkeypatch):
+    """The ragged eight-sub-grid step at its full shapes in bench.py's
+    configuration: one plan (partition counts from the shipped tuning table),
+    every solve of a dependency level in one launch (three launches), each
+    sub-grid's composed x -> y -> z sweep and Poisson solves against the
+    oracle at the chosen partition counts, every line."""
+    monkeypatch.delenv("TRI_BATCH", raising=False)
+    grids, items, keep = [], [], []
+    for s, (nx, ny, nz) in enumerate(W.RAGGED_SUBGRIDS):
+        g = dict(shape=(nx, ny, nz), u0=W.cfg_field(nx, ny, nz, seed=200 + s),
+                 phi0=W.cfg_poisson_rhs(nx, ny, nz, seed=300 + s),
+                 coef=(W.momentum_uniform(nx), W.momentum_stretched(ny), W.momentum_periodic(nz)),
+                 metric=W.poisson_metric(ny), lam=W.modified_wavenumbers(nz))
+        g["u"], g["phi"] = dev(g["u0"]), torch.as_tensor(g["phi0"]).cuda()
+        cf = [tuple(dev(v) for v in c) for c in g["coef"]]
+        ay, cy = (dev(v) for v in g["metric"])
+        lam = dev(g["lam"])
+        keep += [cf, ay, cy, lam]
+        for d in range(3):
+            items.append(dict(kind=d, field=g["u"], Nx=nx, Ny=ny, Nz=nz, a=cf[d][0], b=cf[d][1], c=cf[d][2], P=0,
+                              periodic=int(d == 2), method=T.TRI_PDD))
+        items.append(dict(kind=T.TRI_ITEM_POISSON, field=g["phi"], Nx=nx, Ny=ny, Nz=nz // 2 + 1, a=ay, c=cy,
+                          lam=lam, P=0, method=T.TRI_PPT))
+        grids.append(g)
+    plan = T.tri_plan_create(ctx, items)
+    try:
+        assert T.tri_plan_launch_count(plan) == 3
+        Ps = [T.tri_plan_item_partitions(plan, i) for i in range(len(items))]
+        print(f"ragged level plan P = {Ps}", flush=True)
+        T.tri_plan_execute(plan)
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_plan_destroy(plan)
+    for s, g in enumerate(grids):
+        ref = g["u0"].copy()
+        for d in range(3):
+            orc.adi_sweep(orc.PDD, d, ref, *g["coef"][d], Ps[4 * s + d], d == 2)
+        _every_line(g["u"].cpu().numpy(), ref, 0, f"ragged {g['shape']} x->y->z")
+        pref = g["phi0"].copy()
+        orc.poisson(pref, *g["metric"], g["lam"], P=Ps[4 * s + 3])
+        _every_line(g["phi"].cpu().numpy(), pref, 1, f"ragged {g['shape']} poisson")
+        del g["u"], g["phi"]
