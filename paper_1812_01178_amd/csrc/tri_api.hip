@@ -343,6 +343,36 @@ hipError_t run_launch(const Launch &l, int method, hipStream_t s)
     return l.kind == 1 ? launch_contig(l.args, method, s) : launch_strided(l.args, method, l.chunk_max, s);
 }
 
+// The infinity-norm condition bound of a problem's shared matrices for the
+// one-refinement acceptance: max_j (|a_j| + |b_j| + |c_j|) / min_j (|b_j| -
+// |a_j| - |c_j|) over every matrix (||A^-1|| <= 1 / min margin for strictly
+// diagonally dominant rows), or 0 where a row is not strictly dominant or the
+// matrices are formed on the fly (Poisson modes) or too many to read.  Reads
+// the coefficients to the host: plan creation only.
+double dominance_kappa(const Problem &pb)
+{
+    if (pb.general || pb.src.lam || !pb.src.b || pb.G < 1 || pb.G > 64) return 0.0;
+    const int64_t n = pb.L.n;
+    const int64_t span = (n - 1) * pb.src.cs_j + (pb.G - 1) * pb.src.cs_g + 1;
+    std::vector<double> a((size_t)span), b((size_t)span), c((size_t)span);
+    if (hipMemcpy(a.data(), pb.src.a, sizeof(double) * (size_t)span, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(b.data(), pb.src.b, sizeof(double) * (size_t)span, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(c.data(), pb.src.c, sizeof(double) * (size_t)span, hipMemcpyDeviceToHost) != hipSuccess)
+        return 0.0;
+    double rowmax = 0.0, margin = 1e300;
+    for (int64_t g = 0; g < pb.G; ++g)
+        for (int64_t j = 0; j < n; ++j) {
+            const int64_t J = j * pb.src.cs_j + g * pb.src.cs_g;
+            const double aa = (j == 0 && !pb.periodic) ? 0.0 : std::fabs(a[(size_t)J]);
+            const double cc = (j == n - 1 && !pb.periodic) ? 0.0 : std::fabs(c[(size_t)J]);
+            const double bb = std::fabs(b[(size_t)J]);
+            if (!std::isfinite(aa + bb + cc)) return 0.0;
+            rowmax = std::max(rowmax, aa + bb + cc);
+            margin = std::min(margin, bb - aa - cc);
+        }
+    return margin > 0.0 ? rowmax / margin : 0.0;
+}
+
 // Launch of the refinement kernel over a (sub-)problem.
 tri_status plan_refine_launch(tri_ctx ctx, const Problem &pb, const Tables &T, Launch &out, int want = 0)
 {
@@ -1992,6 +2022,14 @@ tri_status plan_create(tri_ctx ctx, const tri_item *items, int n_items, tri_prec
             if (v > 0 && item_launches(ctx, pb, pi.T, prec, pi.launches, v) != TRI_OK)
                 (void)item_launches(ctx, pb, pi.T, prec, pi.launches);
             pi.tuned = v;
+        }
+        if (prec == TRI_F32_REFINE) {
+            // the condition bound that lets a line of a well-conditioned matrix
+            // be accepted after one refinement (read from the coefficients here,
+            // never in a solve)
+            const double kap = dominance_kappa(pb);
+            for (Launch &l : pi.launches)
+                if (l.refine) l.R.kappa = kap;
         }
         if (e != hipSuccess) {
             tri_plan_destroy(plan);

@@ -254,7 +254,9 @@ __global__ void __launch_bounds__(512) k_contig_refine(const SolveArgs A, const 
             const double Xs = xmax > 0.0 ? xmax : 1.0;
             const double rate = (dprev > 0.0) ? fmin(1.0, dmax / dprev) : (dmax > 0.0 ? 1.0 : 0.0);
             est = (sweep == 0) ? 1.0 : (dmax / Xs) * rate;
-            const bool ok = (sweep >= 1 && dmax <= R.tol * Xs) || (sweep >= 2 && est <= R.tol);
+            const double rel = dmax / Xs;
+            const bool ok = (sweep >= 1 && dmax <= R.tol * Xs) || (sweep >= 2 && est <= R.tol) ||
+                            (sweep == 1 && R.kappa > 0.0 && R.kappa * rel * rel <= R.tol);
             dprev = dmax;
             E = scale_exponent(dmax);
             if (ok) {

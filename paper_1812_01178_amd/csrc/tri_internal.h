@@ -122,6 +122,11 @@ struct RefineArgs {
     int *status;
     int *sweeps_used;      // atomicMax of the refinement sweeps done, for tri_info
     unsigned long long *resid_bits;   // atomicMax of the last relative update (double bits)
+    // > 0: a bound of the infinity-norm condition number of every matrix of the
+    // launch (strictly diagonally dominant rows: max row sum / min dominance
+    // margin); a line is then also accepted after one refinement when
+    // kappa (|delta_1| / |x|)^2 <= tol
+    double kappa = 0.0;
 };
 
 // One entry of a ragged batch of strided solves run by a single launch:

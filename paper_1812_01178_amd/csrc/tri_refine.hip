@@ -256,8 +256,12 @@ __device__ __forceinline__ void strided_refine_solve(const SolveArgs &A, const R
             est = (sweep == 0) ? 1.0 : (D / Xs) * rate;
             // the contraction rate is measured between two refinement updates, so
             // a line is accepted after two refinements (or when an update alone
-            // is already below the tolerance)
-            const bool ok = !active || (sweep >= 1 && D <= R.tol * Xs) || (sweep >= 2 && est <= R.tol);
+            // is already below the tolerance); on well-conditioned matrices the
+            // first update's relative size, times the condition bound, bounds the
+            // rate, and one refinement may do
+            const double rel = D / Xs;
+            const bool ok = !active || (sweep >= 1 && D <= R.tol * Xs) || (sweep >= 2 && est <= R.tol) ||
+                            (sweep == 1 && R.kappa > 0.0 && R.kappa * rel * rel <= R.tol);
             dprev = D;
             escale[lane] = line_exponent(D);
             const bool all = __all(ok);
