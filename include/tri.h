@@ -378,13 +378,17 @@ typedef struct {
  * Nz/2 = 2^a 3^b 5^c <= 512, P_poisson splitting Ny into <= 32 rows, P_adi as
  * the sweeps require), allocate the metric, sweep coefficients and work fields
  * (7 fields of Nx Ny Nz doubles and one spectrum) and create two sweep plans
- * per sub-step (x and y sweeps; z sweeps; factors computed here).  Where the
- * z sweeps run the strided kernel with at most 24 rows a partition chunk,
- * they are launched one line per lane and add their solutions into u, v, w
- * directly (the velocity update fused into their stores; the same
- * arithmetic, one add per unknown); otherwise a separate update kernel does.  Environment: TRI_NS_FUSE=0 forces the separate update,
- * TRI_NS_FUSE=1 makes ns_create return TRI_E_UNSUPPORTED where the fused form
- * is not available.  Synchronises the context stream. */
+ * per sub-step (x and y sweeps; z sweeps; factors computed here; their
+ * strided solves of one kernel instance batched).  Where the z sweeps run
+ * the strided kernel with at most 24 rows a partition chunk, they add their
+ * solutions into u, v, w directly (the velocity update fused into their
+ * stores; the same arithmetic, one add per unknown): two lines per lane into
+ * v and w where the plan chose that shape and the step's v, w are 16-byte
+ * aligned, one line per lane otherwise; else a separate update kernel does.
+ * The pressure update is made by the projection's last kernel.  Environment:
+ * TRI_NS_FUSE=0 forces the separate update, TRI_NS_FUSE=1 makes ns_create
+ * return TRI_E_UNSUPPORTED where the fused form is not available.
+ * Synchronises the context stream. */
 tri_status ns_create(tri_ctx ctx, const tri_ns_config *cfg, tri_ns *out);
 /* One time step, in place on the caller's device fields u, v, w, p (disjoint,
  * 8-byte aligned); asynchronous on the context stream, allocates nothing.
