@@ -369,12 +369,15 @@ def test_ragged_step_level_launches_and_graph(T, ctx, orc, monkeypatch):
         T.tri_plan_destroy(plan)
 
 
-def test_level_launch_register_factor_body(T, ctx, orc, monkeypatch):
+@pytest.mark.parametrize("method,periodic", [("PDD", 0), ("PPT", 0), ("PDD", 1), ("PPT", 1)])
+def test_level_launch_register_factor_body(T, ctx, orc, monkeypatch, method, periodic):
     """Contiguous x sweeps in the level kernel's register-factor body (4 rows
-    per lane, a run of consecutive lines per block): line counts that leave
-    a short last run and ghost blocks in the last workgroup.  Equal bit for
-    bit to the register-factor kernel's own launch with 4 rows per lane, and
-    to the oracle."""
+    per lane, a run of consecutive lines per block), PDD and PPT reduced
+    systems, plain and periodic lines: line counts that leave a short last run
+    and ghost blocks in the last workgroup.  Equal bit for bit to the
+    register-factor kernel's own launch with 4 rows per lane, and to the
+    oracle."""
+    meth = getattr(T, "TRI_" + method)
     monkeypatch.setenv("TRI_AUTOTUNE", "0")
     shapes = [(1024, 4999, 1, 4), (512, 16411, 1, 4)]    # (Nx, Ny, Nz, P): 256 / 128 lanes a line
     rng = np.random.default_rng(190)
@@ -389,8 +392,8 @@ def test_level_launch_register_factor_body(T, ctx, orc, monkeypatch):
             monkeypatch.delenv("TRI_FORCE_C", raising=False)
         us = [dev(f) for f in fields]
         cf = [tuple(dev(v) for v in c) for c in coefs]
-        items = [dict(kind=T.TRI_ITEM_ADI_X, field=u, Nx=nx, Ny=ny, Nz=nz, a=c[0], b=c[1], c=c[2], P=P, periodic=0,
-                      method=T.TRI_PDD) for u, c, (nx, ny, nz, P) in zip(us, cf, shapes)]
+        items = [dict(kind=T.TRI_ITEM_ADI_X, field=u, Nx=nx, Ny=ny, Nz=nz, a=c[0], b=c[1], c=c[2], P=P,
+                      periodic=periodic, method=meth) for u, c, (nx, ny, nz, P) in zip(us, cf, shapes)]
         plan = T.tri_plan_create(ctx, items)
         try:
             n = T.tri_plan_launch_count(plan)
@@ -407,7 +410,7 @@ def test_level_launch_register_factor_body(T, ctx, orc, monkeypatch):
         assert np.array_equal(level[s], single[s]), shapes[s]
         a, b, c = coefs[s]
         ref = fields[s].copy()
-        orc.adi_sweep(orc.PDD, 0, ref, a, b, c, P, False)
+        orc.adi_sweep(getattr(orc, method), 0, ref, a, b, c, P, bool(periodic))
         assert line_relerr(level[s], ref, axis=2) <= TOL, shapes[s]
 
 
