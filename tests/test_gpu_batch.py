@@ -297,9 +297,12 @@ def test_level_launch_runs_a_ragged_batch_in_one_launch(T, ctx, orc, monkeypatch
         assert line_relerr(level[s][1], pref, axis=1) <= TOL, g["shape"]
 
 
-def test_level_launch_two_lines_per_lane(T, ctx, orc, monkeypatch):
+@pytest.mark.parametrize("method", ["PDD", "PPT"])
+def test_level_launch_two_lines_per_lane(T, ctx, orc, monkeypatch, method):
     """The level kernel's two-lines-per-lane body (periodic z sweeps with
-    16-byte lane accesses) equals that kernel's own launch bit for bit."""
+    16-byte lane accesses, PDD and PPT reduced systems) equals that kernel's
+    own launch bit for bit."""
+    meth = getattr(T, "TRI_" + method)
     monkeypatch.setenv("TRI_AUTOTUNE", "0")
     monkeypatch.setenv("TRI_LPL", "2")
     grids = _inputs(SMALL[:4], seed=150)
@@ -314,7 +317,7 @@ def test_level_launch_two_lines_per_lane(T, ctx, orc, monkeypatch):
             a, b, c = (dev(v) for v in g["coef"][2])
             keep += [a, b, c]
             items.append(dict(kind=T.TRI_ITEM_ADI_Z, field=g["u"], Nx=nx, Ny=ny, Nz=nz, a=a, b=b, c=c, P=Pz[s],
-                              periodic=1, method=T.TRI_PDD))
+                              periodic=1, method=meth))
         plan = T.tri_plan_create(ctx, items)
         try:
             n = T.tri_plan_launch_count(plan)
@@ -331,7 +334,7 @@ def test_level_launch_two_lines_per_lane(T, ctx, orc, monkeypatch):
         assert np.array_equal(level[s], single[s]), g["shape"]
         a, b, c = g["coef"][2]
         ref = g["u0"].copy()
-        orc.adi_sweep(orc.PDD, 2, ref, a, b, c, Pz[s], True)
+        orc.adi_sweep(getattr(orc, method), 2, ref, a, b, c, Pz[s], True)
         assert line_relerr(level[s], ref, axis=0) <= TOL, g["shape"]
 
 
@@ -442,4 +445,36 @@ def test_level_launch_keeps_solves_whose_lds_does_not_fit_apart(T, ctx, orc, mon
         a, b, c = coefs[s]
         ref = fields[s].copy()
         orc.adi_sweep(orc.PDD, 0, ref, a, b, c, P, False)
+        assert line_relerr(host(us[s]), ref, axis=2) <= TOL, shapes[s]
+
+
+@pytest.mark.parametrize("method,periodic", [("PDD", 1), ("PPT", 0), ("PPT", 1)])
+def test_level_launch_plain_contiguous_body(T, ctx, orc, monkeypatch, method, periodic):
+    """Contiguous lines whose partitions do not split into 4-row lanes of whole
+    wavefronts (128 rows at P = 8 and 4: 32-lane lines) run the level kernel's
+    plain contiguous body, many lines a workgroup; PDD and PPT, plain and
+    periodic lines, against the oracle."""
+    meth = getattr(T, "TRI_" + method)
+    monkeypatch.setenv("TRI_AUTOTUNE", "0")
+    monkeypatch.delenv("TRI_BATCH", raising=False)
+    shapes = [(128, 37, 5, 8), (128, 29, 3, 4)]
+    rng = np.random.default_rng(230)
+    fields = [rng.standard_normal((nz, ny, nx)) for nx, ny, nz, _ in shapes]
+    coefs = [W.momentum_uniform(nx) for nx, _, _, _ in shapes]
+    us = [dev(f) for f in fields]
+    cf = [tuple(dev(v) for v in c) for c in coefs]
+    items = [dict(kind=T.TRI_ITEM_ADI_X, field=u, Nx=nx, Ny=ny, Nz=nz, a=c[0], b=c[1], c=c[2], P=P,
+                  periodic=periodic, method=meth) for u, c, (nx, ny, nz, P) in zip(us, cf, shapes)]
+    plan = T.tri_plan_create(ctx, items)
+    try:
+        assert all("level=" in T.tri_plan_item_describe(plan, i) for i in range(2))
+        assert T.tri_plan_launch_count(plan) == 1
+        T.tri_plan_execute(plan)
+        T.tri_sync_status(ctx)
+    finally:
+        T.tri_plan_destroy(plan)
+    for s, (nx, ny, nz, P) in enumerate(shapes):
+        a, b, c = coefs[s]
+        ref = fields[s].copy()
+        orc.adi_sweep(getattr(orc, method), 0, ref, a, b, c, P, bool(periodic))
         assert line_relerr(host(us[s]), ref, axis=2) <= TOL, shapes[s]
