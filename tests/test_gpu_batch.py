@@ -253,7 +253,7 @@ def test_level_launch_runs_a_ragged_batch_in_one_launch(T, ctx, orc, monkeypatch
     monkeypatch.setenv("TRI_AUTOTUNE", "0")
     Px = [8, 4, 4, 2, 8, 4, 16, 8]
     Py = [2, 4, 1, 8, 2, 4, 8, 2]
-    Pz = [4, 8, 3, 6, 2, 3, 8, 6]
+    Pz = [4, 8, 3, 6, 2, 3, 4, 6]         # 144 / 4: one 36-row chunk a partition (the 40-row instance)
     Pp = [2, 4, 8, 8, 1, 2, 4, 8]
     grids = _inputs(SMALL, seed=130)
     monkeypatch.setenv("TRI_BATCH", "2")
